@@ -1,0 +1,220 @@
+/*
+ * rte.h -- C ABI of the MI355X (gfx950) library for the S_N upwind-DG radiative
+ * transfer equation with source iteration and synthetic acceleration.
+ *
+ * Method: Z. Peng, "Reduced Order Model Enhanced Source Iteration with Synthetic
+ * Acceleration for Parametric Radiative Transfer Equation" (arXiv 2402.10488).
+ *
+ * Problem statement (Sec. 2, eq. (rte), slab form eq. (slab_geometry)):
+ *   v . grad f + sigma_t f = sigma_s rho + G,  rho = sum_j w_j f(., v_j),
+ *   f = g on the inflow boundary,  sigma_t >= sigma_s >= 0,  sum_j w_j = 1.
+ * Discretization (Sec. 2.2): upwind DG with K = 1 (P1 in 1D, Q1 in 2D) in the
+ * orthonormal Legendre basis, eq. (dg_matrix_vec).
+ *
+ * Conventions shared by every entry point
+ *  - Data layout (all row-major, C order):
+ *      cell index       c = iy * nx + ix            (1D: c = ix)
+ *      local dof        k = a + 2 b                 (a: x-degree, b: y-degree); K = 4 in 2D,
+ *                                                   K = 2 in 1D (k = a)
+ *      rho, delta_rho   [B][N_DOF], N_DOF = nx * ny * K
+ *      angular flux f   [B][n_dir][N_DOF]           (the paper's f = (f_1^T..f_Nv^T)^T per instance)
+ *      materials        [B][ny][nx]  cell-constant sigma_t, sigma_s, G
+ *      inflow           [B][4]  isotropic g on the sides x=0, x=Lx, y=0, y=Ly (1D: first two)
+ *  - Basis: on a cell of size hx x hy, phi_ab = L_a(xi) L_b(eta) / sqrt(hx hy) with
+ *    L_0 = 1, L_1 = sqrt(3) t on [-1, 1]; a constant c has coefficients (c sqrt(hx hy), 0, 0, 0).
+ *  - Every device pointer is caller-owned device memory (hipMalloc / torch), FP64
+ *    unless stated.  Host pointers are read during the call only.
+ *  - Hot calls (sweep, scalar flux, corrections, solve) allocate no device memory;
+ *    they use the caller's workspace (rte_workspace_size).  Handle creation copies
+ *    small tables (directions, cell widths, reduced operators) to the device.
+ *  - Calls enqueue on the given stream and return without synchronizing, except
+ *    rte_sisa_solve, which polls small device flags and fills host statistics.
+ *  - Every function returns an rte_status; no exception crosses the ABI.  Argument
+ *    errors are detected on the host before any device work is enqueued.
+ *  - Handles are immutable after creation; concurrent calls on different streams
+ *    are allowed when their outputs and workspaces are disjoint.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *rte_stream_t;   /* hipStream_t */
+
+typedef enum {
+    RTE_OK = 0,
+    RTE_EINVAL = 1,        /* invalid argument (shape, NULL, sigma_t < sigma_s, weights, ...) */
+    RTE_ENOCONV = 2,       /* iteration limit reached; rho holds the last rho^(l,*) */
+    RTE_ESINGULAR = 3,     /* a reduced ROM system was singular (instance fell back to DSA) */
+    RTE_ECG = 4,           /* diffusion CG did not reach its tolerance within its limit */
+    RTE_ENOMEM = 5,        /* workspace too small */
+    RTE_EDEVICE = 6,       /* a HIP runtime call failed */
+    RTE_EUNSUPPORTED = 7   /* valid but unsupported configuration */
+} rte_status;
+
+typedef enum {
+    RTE_FP64 = 0,          /* every kernel in FP64 */
+    RTE_MIXED = 1          /* FP32 sweep and ROM projections; FP64 accumulation of rho, FP64
+                              diffusion CG, reduced LU, norms and switch test */
+} rte_precision;
+
+typedef enum { RTE_SI = 0, RTE_SI_DSA = 1, RTE_ROMSAD = 2 } rte_mode;
+
+typedef struct rte_problem rte_problem;
+typedef struct rte_rom rte_rom;
+
+/* Problem description: mesh, direction set and per-instance materials of a batch of B
+ * independent instances that share mesh and directions (Sec. 2.1-2.2). */
+typedef struct {
+    int dim;                  /* 1 (slab) or 2 (X-Y) */
+    int nx, ny;               /* cells per axis; ny = 1 when dim == 1 */
+    int batch;                /* B >= 1 */
+    int n_dir;                /* N_v >= 1 (1D: >= 1; 2D: any set, no direction with vx = vy = 0) */
+    double lx, ly;            /* 2D: domain [0,lx] x [0,ly], uniform mesh */
+    const double *widths;     /* 1D: host [nx] cell widths (> 0), may be non-uniform; NULL in 2D */
+    const double *dir_x;      /* host [n_dir]: v_x (1D: mu) */
+    const double *dir_y;      /* host [n_dir]: v_y; NULL in 1D */
+    const double *weight;     /* host [n_dir]: w_j > 0, sum_j w_j = 1 (normalized rule, Sec. 2.1) */
+    const double *sigma_t;    /* device [B][ny][nx] */
+    const double *sigma_s;    /* device [B][ny][nx], 0 <= sigma_s <= sigma_t */
+    const double *source;     /* device [B][ny][nx]  isotropic G */
+    const double *inflow;     /* device [B][4]       isotropic inflow g per side */
+} rte_problem_desc;
+
+/* Creates a problem handle.  Validates host data; device arrays are checked by
+ * rte_problem_check.  The device arrays must stay valid for the handle's lifetime. */
+int rte_problem_create(const rte_problem_desc *desc, rte_problem **out);
+void rte_problem_destroy(rte_problem *p);
+
+/* rte_problem_create with an explicit 2D sweep schedule (used by the autotuner): dg directions
+ * of one quadrant per lane (1, 2, 4, 8, 16; 0 = automatic) and wpb wavefronts per workgroup
+ * (1..4; 0 = automatic).  Results do not depend on the schedule beyond FP rounding of the
+ * partial-density order. */
+int rte_problem_create_tuned(const rte_problem_desc *desc, int dg, int wpb, rte_problem **out);
+
+/* Reports the schedule in use: directions per lane, wavefronts per workgroup and the number of
+ * per-instance partial densities the 2D sweep produces. */
+int rte_problem_tuning(const rte_problem *p, int *dg, int *wpb, int *nparts);
+
+/* Checks sigma_t >= sigma_s >= 0 and finiteness of the device materials; synchronizes the
+ * stream.  Returns RTE_EINVAL on violation. */
+int rte_problem_check(const rte_problem *p, void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* Correction reduced-order model (Sec. 3.2, eq. (rom_correction), eq. (rho_basis)).
+ *   Online operators of the POD basis delta U (N_v N_DOF x r):
+ *     U_rho = sum_j w_j delta U_j,  U_iso = sum_j delta U_j       [N_DOF][r] each
+ *     A_r(mu) = A0 + sum_k psi_k(mu) A_k  with m affine terms      A0 [r][r], A [m][r][r]
+ *   The parameter vector psi [B][m] is passed to the correction calls. */
+typedef struct {
+    int r;                    /* rank, 1 <= r <= 64 */
+    int m;                    /* number of parameter-dependent affine terms */
+    const double *U_rho;      /* host [N_DOF][r] */
+    const double *U_iso;      /* host [N_DOF][r] */
+    const double *A0;         /* host [r][r] */
+    const double *A;          /* host [m][r][r] */
+    double eps_pod;           /* truncation tolerance of the basis (eq. (pod_truncation)) */
+    double eps_train;         /* SISA tolerance of the training solves */
+} rte_rom_desc;
+
+int rte_rom_create(const rte_problem *p, const rte_rom_desc *desc, rte_rom **out);
+void rte_rom_destroy(rte_rom *rom);
+
+/* Bytes of device workspace the calls below need for (problem, mode, rom, precision) and an
+ * iteration limit max_iter of rte_sisa_solve (the per-iteration history is kept on the device).
+ * A workspace sized for (mode, rom, prec, max_iter) serves every call with a mode needing no
+ * more (SI < SI_DSA < ROMSAD), the same or no rom, the same precision and max_iter no larger. */
+int rte_workspace_size(const rte_problem *p, rte_mode mode, const rte_rom *rom,
+                       rte_precision prec, int max_iter, size_t *bytes);
+
+/* One transport sweep, eq. (transport_sweep): for every instance and direction solve
+ * (D_j + Sigma_t) f_j = Sigma_s rho_in + G + g_j^(bc) in upwind order.
+ *   rho_in        device [B][N_DOF]
+ *   f_out         device [B][n_dir][N_DOF], double (RTE_FP64) or float (RTE_MIXED); may be NULL
+ *   rho_star_out  device [B][N_DOF], rho^* = sum_j w_j f_j; may be NULL
+ *   zero_inflow   nonzero: use g = 0 (the kinetic correction equation's boundary condition) */
+int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
+              int zero_inflow, rte_precision prec, void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* Quadrature reduction rho = sum_j w_j f_j (definition under eq. (dg_matrix_vec)).
+ *   f     device [B][n_dir][N_DOF], double or float per prec;  rho_out device [B][N_DOF] */
+int rte_scalar_flux(const rte_problem *p, const void *f, double *rho_out, rte_precision prec,
+                    rte_stream_t stream);
+
+/* Diffusion synthetic acceleration, eq. (diffusion_correction):
+ *   delta rho = C Sigma_s (rho^* - rho_prev).
+ * 1D: consistent DSA of Appendix B (eq. (dsa_rho)-(dsa_J)), direct block solve.
+ * 2D: symmetric interior-penalty (MIP) diffusion form on the Q1 space, FP64 PCG to
+ *     relative residual cg_rtol within cg_maxit iterations (cg_iters_out: device int [B]). */
+int rte_dsa_correct(const rte_problem *p, const double *rho_star, const double *rho_prev,
+                    double *delta_rho, double cg_rtol, int cg_maxit, int *cg_iters_out,
+                    void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* ROM-based kinetic correction (ROMSA), eq. (rom_correction):
+ *   y = U_iso^T Sigma_s (rho^* - rho_prev), A_r(psi_b) dc = y (LU, partial pivoting),
+ *   delta rho = U_rho dc.
+ *   psi        device [B][m]
+ *   status_out device int [B]: 0 ok, 1 singular reduced system (delta_rho left untouched) */
+int rte_rom_correct(const rte_problem *p, const rte_rom *rom, const double *psi,
+                    const double *rho_star, const double *rho_prev, double *delta_rho,
+                    int *status_out, rte_precision prec, void *ws, size_t ws_bytes,
+                    rte_stream_t stream);
+
+/* Options of rte_sisa_solve (Alg. 1 and Alg. 2). */
+typedef struct {
+    double eps;               /* stop when e_l < eps */
+    int max_iter;             /* N_iter */
+    int relative;             /* 1: e_l = ||rho* - rho||_inf / ||rho*||_inf; 0: absolute (Alg. 1) */
+    int theta;                /* ROMSAD: ROMSA allowed for 1 <= l <= theta */
+    double eps_romsad;        /* ROMSAD threshold; < 0: eta * max(eps_train, eps_pod), eta = 0.1 */
+    double cg_rtol;           /* diffusion CG relative residual tolerance */
+    int cg_maxit;             /* diffusion CG iteration limit per correction */
+    rte_precision precision;
+    int poll_every;           /* host reads the active-instance count every poll_every iterations */
+} rte_solve_opts;
+
+/* Host-visible statistics (arrays supplied by the caller; any may be NULL). */
+typedef struct {
+    int *n_sweep;             /* [B] sweeps until convergence (including the last) */
+    int *status;              /* [B] RTE_OK or RTE_ENOCONV */
+    double *change;           /* [B][max_iter] e_l per iteration */
+    int *kind;                /* [B][max_iter] correction applied after sweep l: 0 none, 1 DSA, 2 ROMSA */
+    long long cg_iterations;  /* out: total CG iterations over all instances */
+    int iterations;           /* out: iterations run by the batch (max over instances) */
+} rte_solve_stats;
+
+/* Source iteration with synthetic acceleration (Alg. 1) for every instance of the batch.
+ *   mode RTE_SI: no correction; RTE_SI_DSA: DSA every iteration; RTE_ROMSAD: Alg. 2 switch.
+ *   rho_inout  device [B][N_DOF]: initial guess in, rho^(l,*) of the stopping iteration out
+ *   psi        device [B][m] (ROMSAD only)
+ *   f_out      device [B][n_dir][N_DOF] angular flux of the last sweep, or NULL
+ * Returns RTE_ENOCONV if any instance hit max_iter (per-instance status in stats). */
+int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
+                   const rte_solve_opts *opts, double *rho_inout, void *f_out,
+                   rte_solve_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* Kernel timing with HIP events recorded on the launch stream around every launch of the
+ * named kernel group (process-wide; not for concurrent use from several threads).
+ * rte_profile_enable(1) clears and starts recording, (0) stops; rte_profile_read returns the
+ * summed event time in milliseconds and the number of timed launches since the last enable. */
+enum {
+    RTE_PROF_SWEEP2D = 0,     /* 2D transport sweep kernel */
+    RTE_PROF_REDUCE = 1,      /* partial-density reduction + change maxima */
+    RTE_PROF_DSA = 2,         /* one diffusion correction (all its CG kernels and polls) */
+    RTE_PROF_ROM = 3,         /* one ROM correction (projection, reduced solve, lift) */
+    RTE_PROF_SWEEP1D = 4,     /* 1D transport sweep kernel */
+    RTE_PROF_NKERNELS = 5
+};
+int rte_profile_enable(int on);
+int rte_profile_read(int kernel, double *total_ms, long long *count);
+
+const char *rte_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_H */

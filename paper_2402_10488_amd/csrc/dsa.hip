@@ -1,0 +1,575 @@
+// Diffusion synthetic acceleration on the device (eq. (diffusion_correction)).
+//
+// 1D: the consistent DSA of Appendix B.  With the P1 ansatz delta f = delta rho + 3 v delta J and
+//     the moment equations eq. (dsa_rho), eq. (dsa_J), the unknowns (delta rho, delta J) of a
+//     cell couple only to the two neighbouring cells through D_C = (D^+ + D^-)/2 and
+//     D_J = D^+ - D^-, so the system is block tridiagonal with 4x4 blocks and is solved directly
+//     (block Thomas, one thread per instance, FP64).  In the orthonormal P1 basis on a cell of
+//     width h, with traces P(+1) = (1, s3), P(-1) = (1, -s3):
+//       diag(D_C) = [[0, s3/h], [-s3/h, 0]],      diag(D_J) = [[-2/h, 0], [0, -6/h]],
+//       upper D_J(c,c+1) = P(+1) P(-1)^T / sqrt(h_c h_c+1),  D_C upper = D_J upper / 2,
+//       lower D_J(c,c-1) = P(-1) P(+1)^T / sqrt(h_c h_c-1),  D_C lower = -D_J lower / 2.
+//
+// 2D: the symmetric interior-penalty (MIP) diffusion form on the Q1 DG space with
+//     D = (sum_j w_j v_x^2) / sigma_t, penalty kappa_e = max(kappa_min, kappa_IP),
+//     kappa_IP = 2 (D^- + D^+) / h (interior), 4 D / h (boundary), kappa_min = sum_{v.n>0} w v.n,
+//     applied matrix-free and solved by block-Jacobi preconditioned CG in FP64.  The face terms
+//     reduce, in the orthonormal basis, to 2x2 blocks acting on the Legendre index normal to the
+//     face (identity in the tangential index):
+//       own '+' face:  kappa/h [[1, s3],[s3, 3]]  - D s3/h^2 [[0, 1],[1, 2 s3]]
+//       own '-' face:  kappa/h [[1,-s3],[-s3, 3]] + D s3/h^2 [[0, 1],[1, -2 s3]]
+//       to the '+' neighbour: -kappa/h [[1,-s3],[s3,-3]] - D+ s3/h^2 [[0,1],[0,s3]] + D- s3/h^2 [[0,0],[1,-s3]]
+//     and the volume term 12 D/h^2 on the dofs of degree 1 in that direction, plus sigma_a.
+//     Per-instance scalars are re-derived by every block from fixed-order partial sums, so no
+//     grid-wide synchronization is needed and the result does not depend on block scheduling.
+#include "rte_internal.h"
+
+namespace rte {
+namespace {
+
+constexpr double kS3 = 1.7320508075688772935;
+constexpr double kMipC = 4.0;
+constexpr int kCgBlock = 256;
+
+inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ----------------------------------------------------------------------------------- 1D
+__device__ void inv4(const double *A, double *Ai) {
+    double M[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) { M[i][j] = A[4 * i + j]; M[i][4 + j] = (i == j) ? 1.0 : 0.0; }
+    for (int k = 0; k < 4; ++k) {
+        int pv = k;
+        for (int i = k + 1; i < 4; ++i)
+            if (fabs(M[i][k]) > fabs(M[pv][k])) pv = i;
+        if (pv != k)
+            for (int j = 0; j < 8; ++j) { double t = M[k][j]; M[k][j] = M[pv][j]; M[pv][j] = t; }
+        const double d = 1.0 / M[k][k];
+        for (int j = 0; j < 8; ++j) M[k][j] *= d;
+        for (int i = 0; i < 4; ++i) {
+            if (i == k) continue;
+            const double f = M[i][k];
+            for (int j = 0; j < 8; ++j) M[i][j] -= f * M[k][j];
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) Ai[4 * i + j] = M[i][4 + j];
+}
+
+// 4x4 block of the (delta rho, delta J) system built from 2x2 blocks of D_C and D_J
+__device__ void dsa1d_block(double dc[4], double dj[4], double sa, double st, double c1,
+                            double c2, double c3, bool diag, double out[16]) {
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            out[4 * i + j] = -c1 * dj[2 * i + j] + ((diag && i == j) ? sa : 0.0);
+            out[4 * i + 2 + j] = dc[2 * i + j];
+            out[4 * (2 + i) + j] = c2 * dc[2 * i + j];
+            out[4 * (2 + i) + 2 + j] = -3.0 * c3 * dj[2 * i + j] + ((diag && i == j) ? st : 0.0);
+        }
+}
+
+__device__ void dsa1d_blocks_at(int c, int nc, const double *h, double sa, double st, double c1,
+                                double c2, double c3, double Lo[16], double Dg[16],
+                                double Up[16]) {
+    const double s3 = kS3;
+    const double hc = h[c];
+    double dc[4] = {0.0, s3 / hc, -s3 / hc, 0.0};
+    double dj[4] = {-2.0 / hc, 0.0, 0.0, -6.0 / hc};
+    dsa1d_block(dc, dj, sa, st, c1, c2, c3, true, Dg);
+    if (c + 1 < nc) {   // P(+1) P(-1)^T / sqrt(h_c h_c+1) = [[1,-s3],[s3,-3]] / sq
+        const double sq = sqrt(hc * h[c + 1]);
+        double uj[4] = {1.0 / sq, -s3 / sq, s3 / sq, -3.0 / sq};
+        double uc[4] = {0.5 * uj[0], 0.5 * uj[1], 0.5 * uj[2], 0.5 * uj[3]};
+        dsa1d_block(uc, uj, 0.0, 0.0, c1, c2, c3, false, Up);
+    } else {
+        for (int i = 0; i < 16; ++i) Up[i] = 0.0;
+    }
+    if (c > 0) {        // P(-1) P(+1)^T / sqrt(h_c h_c-1) = [[1,s3],[-s3,-3]] / sq
+        const double sq = sqrt(hc * h[c - 1]);
+        double lj[4] = {1.0 / sq, s3 / sq, -s3 / sq, -3.0 / sq};
+        double lc[4] = {-0.5 * lj[0], -0.5 * lj[1], -0.5 * lj[2], -0.5 * lj[3]};
+        dsa1d_block(lc, lj, 0.0, 0.0, c1, c2, c3, false, Lo);
+    } else {
+        for (int i = 0; i < 16; ++i) Lo[i] = 0.0;
+    }
+}
+
+// scratch per instance: [nc][16] (D'^-1 U) and [nc][4] (D'^-1 r')
+__global__ void dsa1d_kernel(int nc, int B, const double *h, const double *sigma_t,
+                             const double *sigma_s, double c1, double c2, double c3,
+                             const double *rho_star, const double *rho_prev, double *delta,
+                             const int *kind, int want, double *scratch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    if (kind && kind[b] != want) return;
+    double *G = scratch + (size_t)b * nc * 20;     // G[c] = D'_c^-1 U_c (16), g[c] = D'_c^-1 r'_c (4)
+    double Lo[16], Dg[16], Up[16], Dp[16], Di[16];
+    for (int c = 0; c < nc; ++c) {
+        const double st = sigma_t[(size_t)b * nc + c], ss = sigma_s[(size_t)b * nc + c];
+        dsa1d_blocks_at(c, nc, h, st - ss, st, c1, c2, c3, Lo, Dg, Up);
+        double r[4];
+        for (int k = 0; k < 2; ++k) {
+            const size_t i = ((size_t)b * nc + c) * 2 + k;
+            r[k] = ss * (rho_star[i] - rho_prev[i]);
+            r[2 + k] = 0.0;
+        }
+        for (int i = 0; i < 16; ++i) Dp[i] = Dg[i];
+        if (c > 0) {
+            const double *Gm = G + (size_t)(c - 1) * 20;
+            for (int i = 0; i < 4; ++i) {
+                for (int j = 0; j < 4; ++j) {
+                    double s = 0.0;
+                    for (int k = 0; k < 4; ++k) s += Lo[4 * i + k] * Gm[4 * k + j];
+                    Dp[4 * i + j] -= s;
+                }
+                double s = 0.0;
+                for (int k = 0; k < 4; ++k) s += Lo[4 * i + k] * Gm[16 + k];
+                r[i] -= s;
+            }
+        }
+        inv4(Dp, Di);
+        double *Gc = G + (size_t)c * 20;
+        for (int i = 0; i < 4; ++i) {
+            for (int j = 0; j < 4; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < 4; ++k) s += Di[4 * i + k] * Up[4 * k + j];
+                Gc[4 * i + j] = s;
+            }
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += Di[4 * i + k] * r[k];
+            Gc[16 + i] = s;
+        }
+    }
+    double xn[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = nc - 1; c >= 0; --c) {
+        const double *Gc = G + (size_t)c * 20;
+        double x[4];
+        for (int i = 0; i < 4; ++i) {
+            double s = Gc[16 + i];
+            for (int k = 0; k < 4; ++k) s -= Gc[4 * i + k] * xn[k];
+            x[i] = s;
+        }
+        for (int i = 0; i < 4; ++i) xn[i] = x[i];
+        delta[((size_t)b * nc + c) * 2 + 0] = x[0];
+        delta[((size_t)b * nc + c) * 2 + 1] = x[1];
+    }
+}
+
+// ----------------------------------------------------------------------------------- 2D
+struct MipArgs {
+    int nx, ny, B, nblk;
+    long long ncell;
+    double hx, hy, cxx, cyy, kx, ky;
+    const double *sigma_t, *sigma_s;
+};
+
+__device__ __forceinline__ double kap_int(double Dm, double Dp, double h, double kmin) {
+    return fmax(kmin, 0.5 * kMipC * (Dm + Dp) / h);
+}
+__device__ __forceinline__ double kap_bnd(double D, double h, double kmin) {
+    return fmax(kmin, kMipC * D / h);
+}
+
+// 2x2 face blocks (row-major [a][a'])
+__device__ __forceinline__ void face_plus(double kap, double D, double h, double M[4]) {
+    const double s3 = kS3, t = D * s3 / (h * h), k = kap / h;
+    M[0] = k; M[1] = k * s3 - t; M[2] = k * s3 - t; M[3] = 3.0 * k - 2.0 * s3 * t;
+}
+__device__ __forceinline__ void face_minus(double kap, double D, double h, double M[4]) {
+    const double s3 = kS3, t = D * s3 / (h * h), k = kap / h;
+    M[0] = k; M[1] = -k * s3 + t; M[2] = -k * s3 + t; M[3] = 3.0 * k - 2.0 * s3 * t;
+}
+// row = '-' cell, column = '+' cell
+__device__ __forceinline__ void couple_mp(double kap, double Dm, double Dp, double h, double M[4]) {
+    const double s3 = kS3, k = kap / h, tp = Dp * s3 / (h * h), tm = Dm * s3 / (h * h);
+    M[0] = -k; M[1] = k * s3 - tp; M[2] = -k * s3 + tm; M[3] = 3.0 * k - s3 * tp - s3 * tm;
+}
+// row = '+' cell, column = '-' cell: transpose of couple_mp
+__device__ __forceinline__ void couple_pm(double kap, double Dm, double Dp, double h, double M[4]) {
+    double T[4];
+    couple_mp(kap, Dm, Dp, h, T);
+    M[0] = T[0]; M[1] = T[2]; M[2] = T[1]; M[3] = T[3];
+}
+
+// y += M (x) applied along x (acts on a for each b): dofs (0,1) and (2,3)
+__device__ __forceinline__ void addx(const double M[4], const double x[4], double y[4]) {
+    y[0] += M[0] * x[0] + M[1] * x[1];
+    y[1] += M[2] * x[0] + M[3] * x[1];
+    y[2] += M[0] * x[2] + M[1] * x[3];
+    y[3] += M[2] * x[2] + M[3] * x[3];
+}
+// along y (acts on b for each a): dofs (0,2) and (1,3)
+__device__ __forceinline__ void addy(const double M[4], const double x[4], double y[4]) {
+    y[0] += M[0] * x[0] + M[1] * x[2];
+    y[2] += M[2] * x[0] + M[3] * x[2];
+    y[1] += M[0] * x[1] + M[1] * x[3];
+    y[3] += M[2] * x[1] + M[3] * x[3];
+}
+__device__ __forceinline__ void addx_mat(const double M[4], double A[16]) {
+    // A[k][l] for k,l in {(0,1)} and {(2,3)}
+    A[0 * 4 + 0] += M[0]; A[0 * 4 + 1] += M[1]; A[1 * 4 + 0] += M[2]; A[1 * 4 + 1] += M[3];
+    A[2 * 4 + 2] += M[0]; A[2 * 4 + 3] += M[1]; A[3 * 4 + 2] += M[2]; A[3 * 4 + 3] += M[3];
+}
+__device__ __forceinline__ void addy_mat(const double M[4], double A[16]) {
+    A[0 * 4 + 0] += M[0]; A[0 * 4 + 2] += M[1]; A[2 * 4 + 0] += M[2]; A[2 * 4 + 2] += M[3];
+    A[1 * 4 + 1] += M[0]; A[1 * 4 + 3] += M[1]; A[3 * 4 + 1] += M[2]; A[3 * 4 + 3] += M[3];
+}
+
+struct CellCoef {
+    double Dx, Dy, sa;
+};
+__device__ __forceinline__ CellCoef coef_at(const MipArgs &a, int b, long long cell) {
+    const double st = a.sigma_t[(size_t)b * a.ncell + cell];
+    const double ss = a.sigma_s[(size_t)b * a.ncell + cell];
+    CellCoef c;
+    c.Dx = a.cxx / st;
+    c.Dy = a.cyy / st;
+    c.sa = st - ss;
+    return c;
+}
+
+// Diagonal 4x4 block of the MIP operator at cell (i, j).
+__device__ void mip_diag(const MipArgs &a, int b, int i, int j, double A[16]) {
+    const long long cell = (long long)j * a.nx + i;
+    const CellCoef cc = coef_at(a, b, cell);
+    for (int k = 0; k < 16; ++k) A[k] = 0.0;
+    const double vx = 12.0 * cc.Dx / (a.hx * a.hx), vy = 12.0 * cc.Dy / (a.hy * a.hy);
+    A[0] = cc.sa;
+    A[5] = cc.sa + vx;
+    A[10] = cc.sa + vy;
+    A[15] = cc.sa + vx + vy;
+    double M[4];
+    const double kl = i > 0 ? kap_int(coef_at(a, b, cell - 1).Dx, cc.Dx, a.hx, a.kx) : kap_bnd(cc.Dx, a.hx, a.kx);
+    const double kr = i + 1 < a.nx ? kap_int(cc.Dx, coef_at(a, b, cell + 1).Dx, a.hx, a.kx) : kap_bnd(cc.Dx, a.hx, a.kx);
+    const double kb = j > 0 ? kap_int(coef_at(a, b, cell - a.nx).Dy, cc.Dy, a.hy, a.ky) : kap_bnd(cc.Dy, a.hy, a.ky);
+    const double kt = j + 1 < a.ny ? kap_int(cc.Dy, coef_at(a, b, cell + a.nx).Dy, a.hy, a.ky) : kap_bnd(cc.Dy, a.hy, a.ky);
+    face_minus(kl, cc.Dx, a.hx, M); addx_mat(M, A);
+    face_plus(kr, cc.Dx, a.hx, M);  addx_mat(M, A);
+    face_minus(kb, cc.Dy, a.hy, M); addy_mat(M, A);
+    face_plus(kt, cc.Dy, a.hy, M);  addy_mat(M, A);
+}
+
+// solve the SPD 4x4 system A z = r (Cholesky)
+__device__ void spd4_solve(const double A[16], const double r[4], double z[4]) {
+    double L[16];
+    for (int k = 0; k < 16; ++k) L[k] = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        double s = A[5 * j];
+        for (int k = 0; k < j; ++k) s -= L[4 * j + k] * L[4 * j + k];
+        const double d = sqrt(s);
+        L[5 * j] = d;
+        for (int i = j + 1; i < 4; ++i) {
+            double t = A[4 * i + j];
+            for (int k = 0; k < j; ++k) t -= L[4 * i + k] * L[4 * j + k];
+            L[4 * i + j] = t / d;
+        }
+    }
+    double y[4];
+    for (int i = 0; i < 4; ++i) {
+        double s = r[i];
+        for (int k = 0; k < i; ++k) s -= L[4 * i + k] * y[k];
+        y[i] = s / L[5 * i];
+    }
+    for (int i = 3; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < 4; ++k) s -= L[4 * k + i] * z[k];
+        z[i] = s / L[5 * i];
+    }
+}
+
+__device__ __forceinline__ void load4(const double *v, long long idx, double x[4]) {
+    const double4 t = *reinterpret_cast<const double4 *>(v + idx * 4);
+    x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+}
+__device__ __forceinline__ void store4(double *v, long long idx, const double x[4]) {
+    double4 t;
+    t.x = x[0]; t.y = x[1]; t.z = x[2]; t.w = x[3];
+    *reinterpret_cast<double4 *>(v + idx * 4) = t;
+}
+
+// y = A x at cell (i,j), with x read through a functor (to form p = z + beta p_old on the fly)
+template <typename F>
+__device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y[4]) {
+    const long long cell = (long long)j * a.nx + i;
+    const CellCoef cc = coef_at(a, b, cell);
+    double xc[4], xn[4], M[4];
+    xat(cell, xc);
+    const double vx = 12.0 * cc.Dx / (a.hx * a.hx), vy = 12.0 * cc.Dy / (a.hy * a.hy);
+    y[0] = cc.sa * xc[0];
+    y[1] = (cc.sa + vx) * xc[1];
+    y[2] = (cc.sa + vy) * xc[2];
+    y[3] = (cc.sa + vx + vy) * xc[3];
+    if (i > 0) {
+        const double Dl = coef_at(a, b, cell - 1).Dx;
+        const double k = kap_int(Dl, cc.Dx, a.hx, a.kx);
+        face_minus(k, cc.Dx, a.hx, M); addx(M, xc, y);
+        xat(cell - 1, xn);
+        couple_pm(k, Dl, cc.Dx, a.hx, M); addx(M, xn, y);
+    } else {
+        face_minus(kap_bnd(cc.Dx, a.hx, a.kx), cc.Dx, a.hx, M); addx(M, xc, y);
+    }
+    if (i + 1 < a.nx) {
+        const double Dr = coef_at(a, b, cell + 1).Dx;
+        const double k = kap_int(cc.Dx, Dr, a.hx, a.kx);
+        face_plus(k, cc.Dx, a.hx, M); addx(M, xc, y);
+        xat(cell + 1, xn);
+        couple_mp(k, cc.Dx, Dr, a.hx, M); addx(M, xn, y);
+    } else {
+        face_plus(kap_bnd(cc.Dx, a.hx, a.kx), cc.Dx, a.hx, M); addx(M, xc, y);
+    }
+    if (j > 0) {
+        const double Db = coef_at(a, b, cell - a.nx).Dy;
+        const double k = kap_int(Db, cc.Dy, a.hy, a.ky);
+        face_minus(k, cc.Dy, a.hy, M); addy(M, xc, y);
+        xat(cell - a.nx, xn);
+        couple_pm(k, Db, cc.Dy, a.hy, M); addy(M, xn, y);
+    } else {
+        face_minus(kap_bnd(cc.Dy, a.hy, a.ky), cc.Dy, a.hy, M); addy(M, xc, y);
+    }
+    if (j + 1 < a.ny) {
+        const double Dt = coef_at(a, b, cell + a.nx).Dy;
+        const double k = kap_int(cc.Dy, Dt, a.hy, a.ky);
+        face_plus(k, cc.Dy, a.hy, M); addy(M, xc, y);
+        xat(cell + a.nx, xn);
+        couple_mp(k, cc.Dy, Dt, a.hy, M); addy(M, xn, y);
+    } else {
+        face_plus(kap_bnd(cc.Dy, a.hy, a.ky), cc.Dy, a.hy, M); addy(M, xc, y);
+    }
+}
+
+// fixed-order block sum of two values; thread 0 returns the totals
+__device__ void block_sum2(double &v0, double &v1) {
+    __shared__ double sh[2][kCgBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        v0 += __shfl_xor(v0, off, 64);
+        v1 += __shfl_xor(v1, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sh[0][w] = v0; sh[1][w] = v1; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, c = 0.0;
+        for (int k = 0; k < kCgBlock / 64; ++k) { a += sh[0][k]; c += sh[1][k]; }
+        v0 = a; v1 = c;
+    }
+}
+
+__device__ double sum_parts(const double *p, int n) {
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += p[k];
+    return s;
+}
+
+// partial-sum layout: part[b][slot][nblk], slots: 0,1 = rz (parity), 2 = pq, 3 = rr, 4 = bb
+__device__ __forceinline__ double *slot(double *part, int b, int s, int nblk) {
+    return part + ((size_t)b * 5 + s) * nblk;
+}
+
+__global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const double *rho_star,
+                                                            const double *rho_prev, const int *kind,
+                                                            int want, double *x, double *r,
+                                                            double *z, double *part, int *state,
+                                                            int *iters, int *n_running) {
+    const int b = blockIdx.y;
+    const bool mine = !kind || kind[b] == want;
+    if (!mine) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) state[b] = 0;
+        return;
+    }
+    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    double rz = 0.0, bb = 0.0;
+    if (cell < a.ncell) {
+        const long long gi = (long long)b * a.ncell + cell;
+        const double ss = a.sigma_s[gi];
+        double rs[4], rp[4], rv[4], zv[4], A[16];
+        load4(rho_star, gi, rs);
+        load4(rho_prev, gi, rp);
+        for (int k = 0; k < 4; ++k) rv[k] = ss * (rs[k] - rp[k]);
+        const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+        mip_diag(a, b, i, j, A);
+        spd4_solve(A, rv, zv);
+        const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+        store4(x, gi, zero);
+        store4(r, gi, rv);
+        store4(z, gi, zv);
+        for (int k = 0; k < 4; ++k) { rz += rv[k] * zv[k]; bb += rv[k] * rv[k]; }
+    }
+    block_sum2(rz, bb);
+    if (threadIdx.x == 0) {
+        slot(part, b, 0, a.nblk)[blockIdx.x] = rz;
+        slot(part, b, 4, a.nblk)[blockIdx.x] = bb;
+        if (blockIdx.x == 0) {
+            state[b] = 1;
+            iters[b] = 0;
+            atomicAdd(n_running, 1);
+        }
+    }
+}
+
+// iteration it >= 1: convergence test on the previous residual, p = z + beta p_old, q = A p
+__global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, double rtol2,
+                                                             int maxit, const double *z,
+                                                             const double *p_old, double *p_new,
+                                                             double *q, double *part, int *state,
+                                                             int *iters, int *n_running) {
+    const int b = blockIdx.y;
+    if (state[b] != 1) return;
+    const int nb = a.nblk;
+    const double bb = sum_parts(slot(part, b, 4, nb), nb);
+    const double rr = it == 1 ? bb : sum_parts(slot(part, b, 3, nb), nb);
+    const bool done = !(rr > rtol2 * bb);     // also stops on NaN
+    if (done || it > maxit) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            state[b] = done && rr == rr ? 2 : 3;
+            iters[b] = it - 1;
+            atomicSub(n_running, 1);
+        }
+        return;
+    }
+    double beta = 0.0;
+    if (it > 1) {
+        const double rz_cur = sum_parts(slot(part, b, (it - 1) & 1, nb), nb);
+        const double rz_prev = sum_parts(slot(part, b, it & 1, nb), nb);
+        beta = rz_cur / rz_prev;
+    }
+    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    double pq = 0.0, dummy = 0.0;
+    if (cell < a.ncell) {
+        const size_t base = (size_t)b * a.ncell;
+        auto pat = [&](long long c, double v[4]) {
+            double zz[4];
+            load4(z, base + c, zz);
+            if (it > 1) {
+                double po[4];
+                load4(p_old, base + c, po);
+                for (int k = 0; k < 4; ++k) v[k] = zz[k] + beta * po[k];
+            } else {
+                for (int k = 0; k < 4; ++k) v[k] = zz[k];
+            }
+        };
+        const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+        double y[4], pc[4];
+        mip_apply(a, b, i, j, pat, y);
+        pat(cell, pc);
+        store4(p_new, base + cell, pc);
+        store4(q, base + cell, y);
+        for (int k = 0; k < 4; ++k) pq += pc[k] * y[k];
+    }
+    block_sum2(pq, dummy);
+    if (threadIdx.x == 0) slot(part, b, 2, nb)[blockIdx.x] = pq;
+}
+
+__global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, const double *p,
+                                                             const double *q, double *x, double *r,
+                                                             double *z, double *part,
+                                                             const int *state) {
+    const int b = blockIdx.y;
+    if (state[b] != 1) return;
+    const int nb = a.nblk;
+    const double pq = sum_parts(slot(part, b, 2, nb), nb);
+    const double rz = sum_parts(slot(part, b, (it - 1) & 1, nb), nb);
+    const double alpha = rz / pq;
+    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    double rz_new = 0.0, rr = 0.0;
+    if (cell < a.ncell) {
+        const long long gi = (long long)b * a.ncell + cell;
+        double pv[4], qv[4], xv[4], rv[4], zv[4], A[16];
+        load4(p, gi, pv);
+        load4(q, gi, qv);
+        load4(x, gi, xv);
+        load4(r, gi, rv);
+        for (int k = 0; k < 4; ++k) { xv[k] += alpha * pv[k]; rv[k] -= alpha * qv[k]; }
+        const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+        mip_diag(a, b, i, j, A);
+        spd4_solve(A, rv, zv);
+        store4(x, gi, xv);
+        store4(r, gi, rv);
+        store4(z, gi, zv);
+        for (int k = 0; k < 4; ++k) { rz_new += rv[k] * zv[k]; rr += rv[k] * rv[k]; }
+    }
+    block_sum2(rz_new, rr);
+    if (threadIdx.x == 0) {
+        slot(part, b, it & 1, nb)[blockIdx.x] = rz_new;
+        slot(part, b, 3, nb)[blockIdx.x] = rr;
+    }
+}
+
+__global__ void cg_finish_kernel(long long ndof, const double *x, double *delta, const int *state,
+                                 const int *iters, int *iters_out, int B) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (state[b] == 0) return;
+    if (t < ndof) delta[(size_t)b * ndof + t] = x[(size_t)b * ndof + t];
+    if (t == 0 && iters_out) iters_out[b] = iters[b];
+}
+
+__global__ void zero_int_kernel(int *x) {
+    if (threadIdx.x == 0) *x = 0;
+}
+
+MipArgs mip_args(const rte_problem *p, int nblk) {
+    MipArgs a;
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.B = p->B;
+    a.nblk = nblk;
+    a.ncell = p->ncell;
+    a.hx = p->hx;
+    a.hy = p->hy;
+    a.cxx = p->cxx;
+    a.cyy = p->cyy;
+    a.kx = p->kmin_x;
+    a.ky = p->kmin_y;
+    a.sigma_t = p->sigma_t;
+    a.sigma_s = p->sigma_s;
+    return a;
+}
+
+}  // namespace
+
+size_t cg_blocks_per_instance(const rte_problem *p) {
+    return (size_t)((p->ncell + kCgBlock - 1) / kCgBlock);
+}
+
+hipError_t launch_dsa1d(const rte_problem *p, const double *rho_star, const double *rho_prev,
+                        double *delta, const int *kind, int want_kind, double *scratch,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(dsa1d_kernel, dim3(blocks_for(p->B, 64)), dim3(64), 0, s, p->nx, p->B,
+                       p->d_widths, p->sigma_t, p->sigma_s, p->c1, p->c2, p->c3, rho_star,
+                       rho_prev, delta, kind, want_kind, scratch);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double *rho_star,
+                           const double *rho_prev, const int *kind, int want_kind, double rtol,
+                           hipStream_t s) {
+    const MipArgs a = mip_args(p, c.nblk);
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, c.n_running);
+    hipLaunchKernelGGL(cg_setup_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, rho_star,
+                       rho_prev, kind, want_kind, c.x, c.r, c.z, c.part, c.state, c.iters,
+                       c.n_running);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, double rtol,
+                               int maxit, hipStream_t s) {
+    const MipArgs a = mip_args(p, c.nblk);
+    double *p_new = (it & 1) ? c.p1 : c.p0;
+    const double *p_old = (it & 1) ? c.p0 : c.p1;
+    hipLaunchKernelGGL(cg_matvec_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, it,
+                       rtol * rtol, maxit, c.z, p_old, p_new, c.q, c.part, c.state, c.iters,
+                       c.n_running);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, it, p_new,
+                       c.q, c.x, c.r, c.z, c.part, c.state);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delta, int *iters_out,
+                            hipStream_t s) {
+    dim3 grid(blocks_for(p->ndof, 256), p->B);
+    hipLaunchKernelGGL(cg_finish_kernel, grid, dim3(256), 0, s, p->ndof, c.x, delta, c.state,
+                       c.iters, iters_out, p->B);
+    return hipGetLastError();
+}
+
+}  // namespace rte

@@ -1,0 +1,145 @@
+// Alg. 1 (source iteration with synthetic acceleration) and Alg. 2 (ROMSAD switch) bookkeeping
+// on the device: the stop test, the per-instance choice of correction, and the density update
+// rho^(l) = rho^(l,*) + delta rho^(l) fused with the source prologue of the next sweep.
+#include "rte_internal.h"
+
+namespace rte {
+namespace {
+
+inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// kind codes written per instance after sweep l:
+//   0 no correction (SI), 1 DSA, 2 ROMSA, -1 converged at l, -2 stopped at max_iter
+__global__ void decide_kernel(int B, int l, int max_iter, double eps, int relative, int mode,
+                              int theta, double eps_romsad, unsigned long long *maxd,
+                              unsigned long long *maxr, int *active, int *kind, int *n_sweep,
+                              int *status, double *change, int *kinds, int *n_active) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    if (!active[b]) { kind[b] = -3; return; }
+    const double md = __longlong_as_double((long long)maxd[b]);
+    const double mr = __longlong_as_double((long long)maxr[b]);
+    maxd[b] = 0ull;
+    maxr[b] = 0ull;
+    double e;
+    if (relative) e = mr > 0.0 ? md / mr : (md == 0.0 ? 0.0 : INFINITY);
+    else e = md;
+    if (!(e == e)) e = INFINITY;                     // NaN never passes the test
+    change[(size_t)b * max_iter + (l - 1)] = e;
+    n_sweep[b] = l;
+    int k;
+    if (e < eps) { k = -1; status[b] = RTE_OK; }
+    else if (l >= max_iter) { k = -2; status[b] = RTE_ENOCONV; }
+    else if (mode == RTE_SI) k = 0;
+    else if (mode == RTE_SI_DSA) k = 1;
+    else k = (l >= 1 && l <= theta && e >= eps_romsad) ? 2 : 1;    // Alg. 2
+    kind[b] = k;
+    kinds[(size_t)b * max_iter + (l - 1)] = k < 0 ? 0 : k;
+    if (k >= 0) atomicAdd(n_active, 1);
+}
+
+template <typename T>
+__global__ void update_kernel(long long ncell, int K, int B, const int *kind, int *active,
+                              const double *rho_star, const double *delta, double *rho,
+                              const double *sigma_s, const double *G, const double *cellw,
+                              double ghost, T *src) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)B * ncell) return;
+    const int b = (int)(t / ncell);
+    const int k = kind[b];
+    if (k == -3) return;                              // finished earlier
+    const long long cell = t - (long long)b * ncell;
+    if (k < 0) {                                      // converged / stopped: keep rho^(l,*)
+        for (int q = 0; q < K; ++q) rho[t * K + q] = rho_star[t * K + q];
+        if (cell == 0) active[b] = 0;
+        return;
+    }
+    const double ss = sigma_s[t];
+    const double g0 = G[t] * (cellw ? sqrt(cellw[cell]) : ghost);
+    for (int q = 0; q < K; ++q) {
+        double v = rho_star[t * K + q];
+        if (k > 0 && delta) v += delta[t * K + q];
+        rho[t * K + q] = v;
+        src[t * K + q] = (T)(ss * v + (q == 0 ? g0 : 0.0));
+    }
+}
+
+__global__ void init_state_kernel(int B, int max_iter, unsigned long long *maxd,
+                                  unsigned long long *maxr, int *active, int *kind, int *n_sweep,
+                                  int *status, double *change, int *kinds) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < B) {
+        maxd[t] = 0ull;
+        maxr[t] = 0ull;
+        active[t] = 1;
+        kind[t] = 0;
+        n_sweep[t] = 0;
+        status[t] = RTE_ENOCONV;
+    }
+    if (t < (long long)B * max_iter) {
+        change[t] = 0.0;
+        kinds[t] = 0;
+    }
+}
+
+__global__ void zero_kernel(double *x, long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = 0.0;
+}
+
+__global__ void fill_int_kernel(int *x, long long n, int v) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = v;
+}
+
+}  // namespace
+
+hipError_t launch_decide(const rte_problem *p, const IterState &st, int l, int max_iter,
+                         double eps, int relative, int mode, int theta, double eps_romsad,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, st.n_active, 1ll, 0);
+    hipLaunchKernelGGL(decide_kernel, dim3(blocks_for(p->B, 256)), dim3(256), 0, s, p->B, l,
+                       max_iter, eps, relative, mode, theta, eps_romsad, st.maxd, st.maxr,
+                       st.active, st.kind, st.n_sweep, st.status, st.change, st.kinds,
+                       st.n_active);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const rte_problem *p, const IterState &st, const double *rho_star,
+                         const double *delta, double *rho, void *src, int fp32, hipStream_t s) {
+    const long long n = (long long)p->B * p->ncell;
+    const double ghost = sqrt(p->hx * p->hy);
+    const double *cw = p->dim == 1 ? p->d_widths : nullptr;
+    if (fp32)
+        hipLaunchKernelGGL(update_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                           p->ncell, p->K, p->B, st.kind, st.active, rho_star, delta, rho,
+                           p->sigma_s, p->source, cw, ghost, (float *)src);
+    else
+        hipLaunchKernelGGL(update_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                           p->ncell, p->K, p->B, st.kind, st.active, rho_star, delta, rho,
+                           p->sigma_s, p->source, cw, ghost, (double *)src);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(const rte_problem *p, const IterState &st, int max_iter,
+                             hipStream_t s) {
+    const long long n = (long long)p->B * max_iter > p->B ? (long long)p->B * max_iter : p->B;
+    hipLaunchKernelGGL(init_state_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->B,
+                       max_iter, st.maxd, st.maxr, st.active, st.kind, st.n_sweep, st.status,
+                       st.change, st.kinds);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *x, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *x, long long n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace rte

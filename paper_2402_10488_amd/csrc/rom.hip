@@ -1,0 +1,249 @@
+// ROM-based kinetic correction (ROMSA) on the device, eq. (rom_correction):
+//   y_b   = U_iso^T (Sigma_s (rho*_b - rho_b))      tall-skinny product over all ROMSA instances
+//   A_b   = A0 + sum_k psi_bk A_k,   A_b dc_b = y_b  (r x r LU with partial pivoting, FP64)
+//   drho_b = U_rho dc_b
+// The two products run on the matrix cores: v_mfma_f64_16x16x4f64 in FP64 mode and
+// v_mfma_f32_16x16x4f32 in mixed mode.  Operand layout (one element per lane for A and B, four
+// results per lane; measured on gfx950):
+//   A[m][k]: lane m + 16 k;   B[k][n]: lane n + 16 k;
+//   D[m][n]: lane n + 16 q, item i with  m = 4 q + i (f32)  or  m = q + 4 i (f64).
+// The reduction over the N_DOF dofs is split over workgroups; the split partials are summed in
+// a fixed order, so the result does not depend on scheduling.
+#include "rte_internal.h"
+
+namespace rte {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kProjChunk = 256;        // dofs per wave-iteration group in the projection
+
+__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> struct VecOf;
+template <> struct VecOf<double> { typedef v4d type; };
+template <> struct VecOf<float> { typedef v4f type; };
+
+// row of D held in item i of a lane in row group q (see the layout above)
+template <typename T> __device__ __forceinline__ int drow(int q, int i);
+template <> __device__ __forceinline__ int drow<float>(int q, int i) { return 4 * q + i; }
+template <> __device__ __forceinline__ int drow<double>(int q, int i) { return q + 4 * i; }
+
+// grid: x = split index, y = instance tile (16 instances), z = r tile (16 ranks); one wave each.
+// ypart[b][split][r]
+template <typename T>
+__global__ void __launch_bounds__(64) rom_project_kernel(long long ndof, int K, int B, int r,
+                                                         int nsplit, long long per_split,
+                                                         const T *U_iso, const double *sigma_s,
+                                                         const double *rho_star,
+                                                         const double *rho_prev, const int *kind,
+                                                         int want, double *ypart) {
+    typedef typename VecOf<T>::type V;
+    const int lane = threadIdx.x;
+    const int split = blockIdx.x;
+    const int b0 = blockIdx.y * 16;
+    const int r0 = blockIdx.z * 16;
+    const int n = lane & 15;          // instance within tile (B operand column) / rank row of A
+    const int kq = lane >> 4;         // 0..3
+    const int b = b0 + n;
+    const bool live_b = b < B && (!kind || kind[b] == want);
+    const int rr = r0 + n;
+    const bool live_r = rr < r;
+    V acc = {0, 0, 0, 0};
+    const long long k_begin = (long long)split * per_split;
+    long long k_end = k_begin + per_split;
+    if (k_end > ndof) k_end = ndof;
+    const double *rs = rho_star + (size_t)(live_b ? b : 0) * ndof;
+    const double *rp = rho_prev + (size_t)(live_b ? b : 0) * ndof;
+    const double *ss = sigma_s + (size_t)(live_b ? b : 0) * (ndof / K);
+    // each group of 16 dofs: lane (n, kq) holds dofs k0 + 4 kq + s, s = 0..3, for 4 MFMA steps
+    for (long long k0 = k_begin; k0 < k_end; k0 += 16) {
+        T bv[4], av[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const long long k = k0 + 4 * kq + s;
+            const bool kin = k < k_end;
+            bv[s] = (live_b && kin) ? (T)(ss[k / K] * (rs[k] - rp[k])) : T(0);
+            av[s] = (live_r && kin) ? U_iso[(size_t)k * r + rr] : T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = mfma(av[s], bv[s], acc);
+    }
+    // D[m][n]: m = rank offset, n = instance offset
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = drow<T>(kq, i);
+        const int rk = r0 + m;
+        if (b < B && rk < r) ypart[((size_t)b * nsplit + split) * r + rk] = (double)acc[i];
+    }
+}
+
+// one wave per instance: y = sum of splits; A = A0 + sum psi_k A_k; LU with partial pivoting;
+// dc = A^{-1} y; singular -> status 1 and kind falls back to DSA (want -> 1).
+__global__ void __launch_bounds__(64) rom_solve_kernel(int B, int r, int m, int nsplit,
+                                                       const double *ypart, const double *A0,
+                                                       const double *Ak, const double *psi,
+                                                       int *kind, int want, int *status,
+                                                       double *dc) {
+    __shared__ double A[64][65];
+    __shared__ double y[64];
+    __shared__ int piv_row;
+    const int b = blockIdx.x;
+    const int i = threadIdx.x;
+    if (kind && kind[b] != want) return;
+    if (i < r) {
+        double s = 0.0;
+        for (int k = 0; k < nsplit; ++k) s += ypart[((size_t)b * nsplit + k) * r + i];
+        y[i] = s;
+        for (int j = 0; j < r; ++j) {
+            double a = A0[i * r + j];
+            for (int k = 0; k < m; ++k) a += psi[(size_t)b * m + k] * Ak[((size_t)k * r + i) * r + j];
+            A[i][j] = a;
+        }
+    }
+    __syncthreads();
+    // scale of A for the singularity test
+    double amax = 0.0;
+    if (i < r)
+        for (int j = 0; j < r; ++j) amax = fmax(amax, fabs(A[i][j]));
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    bool singular = false;
+    for (int k = 0; k < r; ++k) {
+        // pivot: largest |A[i][k]| over i >= k, smallest index on ties
+        double v = (i >= k && i < r) ? fabs(A[i][k]) : -1.0;
+        int idx = i;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(v, off, 64);
+            const int oi = __shfl_xor(idx, off, 64);
+            if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+        }
+        if (i == 0) piv_row = idx;
+        __syncthreads();
+        const int pr = piv_row;
+        if (!(v >= 1e-14 * amax) || v == 0.0) singular = true;
+        if (pr != k) {
+            if (i < r) {
+                // swap rows k and pr column-wise: lane i handles column i
+                const double t = A[k][i]; A[k][i] = A[pr][i]; A[pr][i] = t;
+            }
+            if (i == 0) { const double t = y[k]; y[k] = y[pr]; y[pr] = t; }
+        }
+        __syncthreads();
+        if (!singular && i > k && i < r) {
+            const double f = A[i][k] / A[k][k];
+            A[i][k] = f;
+            for (int j = k + 1; j < r; ++j) A[i][j] -= f * A[k][j];
+            y[i] -= f * y[k];
+        }
+        __syncthreads();
+    }
+    if (singular) {
+        if (i == 0) {
+            if (status) status[b] = 1;
+            if (kind) kind[b] = 1;           // this iteration falls back to DSA
+        }
+        return;
+    }
+    // back substitution (lane 0, r <= 64)
+    if (i == 0) {
+        for (int k = r - 1; k >= 0; --k) {
+            double s = y[k];
+            for (int j = k + 1; j < r; ++j) s -= A[k][j] * y[j];
+            y[k] = s / A[k][k];
+        }
+        if (status) status[b] = 0;
+    }
+    __syncthreads();
+    if (i < r) dc[(size_t)b * r + i] = y[i];
+}
+
+// delta[b][k] = sum_r U_rho[k][r] dc[b][r] for ROMSA instances; one wave per (16 dofs x 16
+// instances) tile, looping over `tiles` consecutive dof tiles.
+template <typename T>
+__global__ void __launch_bounds__(64) rom_lift_kernel(long long ndof, int B, int r, int tiles,
+                                                      const T *U_rho, const double *dc,
+                                                      const int *kind, int want,
+                                                      const int *status, double *delta) {
+    typedef typename VecOf<T>::type V;
+    const int lane = threadIdx.x;
+    const int n = lane & 15, kq = lane >> 4;
+    const int b0 = blockIdx.y * 16;
+    const int b = b0 + n;
+    // singular reduced systems (status 1) leave delta untouched
+    const bool live_b = b < B && (!kind || kind[b] == want) && status[b] == 0;
+    const int rpad = (r + 3) & ~3;
+    for (int t = 0; t < tiles; ++t) {
+        const long long m0 = ((long long)blockIdx.x * tiles + t) * 16;
+        if (m0 >= ndof) break;
+        V acc = {0, 0, 0, 0};
+        const long long mrow = m0 + n;          // A operand row (dof) of this lane
+        for (int k0 = 0; k0 < rpad; k0 += 4) {
+            const int kk = k0 + kq;
+            const T a = (mrow < ndof && kk < r) ? U_rho[(size_t)mrow * r + kk] : T(0);
+            const T bb = (live_b && kk < r) ? (T)dc[(size_t)b * r + kk] : T(0);
+            acc = mfma(a, bb, acc);
+        }
+        if (live_b) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long dof = m0 + drow<T>(kq, i);
+                if (dof < ndof) delta[(size_t)b * ndof + dof] = (double)acc[i];
+            }
+        }
+    }
+}
+
+inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+size_t rom_split(const rte_problem *p, const rte_rom *rom) {
+    // enough splits that (splits x instance tiles x rank tiles) fills the chip, each split >= 1024 dofs
+    const long long btiles = (p->B + 15) / 16, rtiles = (rom->r + 15) / 16;
+    long long want = (2048 + btiles * rtiles - 1) / (btiles * rtiles);
+    long long maxs = (p->ndof + 1023) / 1024;
+    if (want > maxs) want = maxs;
+    if (want < 1) want = 1;
+    return (size_t)want;
+}
+
+hipError_t launch_rom_correct(const rte_problem *p, const rte_rom *rom, const double *psi,
+                              const double *rho_star, const double *rho_prev, double *delta,
+                              int *status, const int *kind, int want_kind, const RomSpace &w,
+                              int fp32, hipStream_t s) {
+    const int r = rom->r;
+    const long long ndof = p->ndof;
+    const int nsplit = w.nsplit;
+    long long per_split = (ndof + nsplit - 1) / nsplit;
+    per_split = (per_split + 15) / 16 * 16;
+    dim3 gp(nsplit, cdiv(p->B, 16), cdiv(r, 16));
+    if (fp32)
+        hipLaunchKernelGGL(rom_project_kernel<float>, gp, dim3(64), 0, s, ndof, p->K, p->B, r,
+                           nsplit, per_split, rom->d_U_iso_f, p->sigma_s, rho_star, rho_prev, kind,
+                           want_kind, w.ypart);
+    else
+        hipLaunchKernelGGL(rom_project_kernel<double>, gp, dim3(64), 0, s, ndof, p->K, p->B, r,
+                           nsplit, per_split, rom->d_U_iso, p->sigma_s, rho_star, rho_prev, kind,
+                           want_kind, w.ypart);
+    // the solve may turn `want` instances into DSA ones (kind is written); the lift then skips them
+    hipLaunchKernelGGL(rom_solve_kernel, dim3(p->B), dim3(64), 0, s, p->B, r, rom->m, nsplit,
+                       w.ypart, rom->d_A0, rom->d_A, psi, const_cast<int *>(kind), want_kind,
+                       status, w.dc);
+    const int tiles = 4;
+    dim3 gl(cdiv(ndof, 16 * tiles), cdiv(p->B, 16));
+    if (fp32)
+        hipLaunchKernelGGL(rom_lift_kernel<float>, gl, dim3(64), 0, s, ndof, p->B, r, tiles,
+                           rom->d_U_rho_f, w.dc, kind, want_kind, status, delta);
+    else
+        hipLaunchKernelGGL(rom_lift_kernel<double>, gl, dim3(64), 0, s, ndof, p->B, r, tiles,
+                           rom->d_U_rho, w.dc, kind, want_kind, status, delta);
+    return hipGetLastError();
+}
+
+}  // namespace rte

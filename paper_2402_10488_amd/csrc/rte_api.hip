@@ -1,0 +1,637 @@
+// C ABI of the gfx950 RTE library: argument validation, workspace carving and the host-side
+// iteration driver of Alg. 1 / Alg. 2.  Every arithmetic step runs in the kernels of
+// sweep.hip, iterate.hip, dsa.hip and rom.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rte_internal.h"
+
+using namespace rte;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Carver {
+    char *base;
+    size_t off, cap;
+    bool ok;
+    explicit Carver(void *b, size_t c) : base((char *)b), off(0), cap(c), ok(true) {}
+    template <typename T>
+    T *take(size_t n) {
+        const size_t bytes = align_up(n * sizeof(T));
+        T *ptr = base ? (T *)(base + off) : nullptr;
+        off += bytes;
+        if (base && off > cap) ok = false;
+        return ptr;
+    }
+};
+
+// Everything the calls carve out of the caller's workspace, in one fixed order.
+struct Layout {
+    double *rho_star, *delta;
+    void *src;
+    double *partial;        // 2D sweep partials
+    void *fscratch;         // 1D angular flux scratch
+    IterState st;
+    CGSpace cg;
+    double *dsa1d;          // 1D DSA scratch
+    RomSpace rom;
+    int *rom_status;
+    long long *cg_total;
+    int *flag;
+};
+
+int nparts_for(const rte_problem *p) {
+    int n = 0;
+    for (int q = 0; q < 4; ++q) n += (p->quad.count[q] + p->tune.dg - 1) / p->tune.dg;
+    return n;
+}
+
+Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
+             rte_precision prec, int max_iter) {
+    Layout L;
+    std::memset(&L, 0, sizeof(L));
+    const size_t B = p->B, nd = p->ndof;
+    const size_t ts = prec == RTE_MIXED ? 4 : 8;
+    L.rho_star = c.take<double>(B * nd);
+    L.delta = c.take<double>(B * nd);
+    L.src = c.take<char>(B * nd * ts);
+    if (p->dim == 2) L.partial = c.take<double>(B * (size_t)nparts_for(p) * nd);
+    else L.fscratch = c.take<char>(B * (size_t)p->n_dir * nd * ts);
+    L.st.maxd = c.take<unsigned long long>(B);
+    L.st.maxr = c.take<unsigned long long>(B);
+    L.st.active = c.take<int>(B);
+    L.st.kind = c.take<int>(B);
+    L.st.n_sweep = c.take<int>(B);
+    L.st.status = c.take<int>(B);
+    L.st.change = c.take<double>(B * (size_t)std::max(max_iter, 1));
+    L.st.kinds = c.take<int>(B * (size_t)std::max(max_iter, 1));
+    L.st.n_active = c.take<int>(1);
+    L.cg_total = c.take<long long>(1);
+    L.flag = c.take<int>(1);
+    if (mode != RTE_SI) {
+        if (p->dim == 2) {
+            L.cg.nblk = (int)cg_blocks_per_instance(p);
+            L.cg.x = c.take<double>(B * nd);
+            L.cg.r = c.take<double>(B * nd);
+            L.cg.z = c.take<double>(B * nd);
+            L.cg.p0 = c.take<double>(B * nd);
+            L.cg.p1 = c.take<double>(B * nd);
+            L.cg.q = c.take<double>(B * nd);
+            L.cg.part = c.take<double>(B * 5 * (size_t)L.cg.nblk);
+            L.cg.iters = c.take<int>(B);
+            L.cg.state = c.take<int>(B);
+            L.cg.n_running = c.take<int>(1);
+        } else {
+            L.dsa1d = c.take<double>(B * (size_t)p->nx * 20);
+            L.cg.iters = c.take<int>(B);
+        }
+    }
+    if (rom) {
+        L.rom.nsplit = (int)rom_split(p, rom);
+        L.rom.ypart = c.take<double>(B * (size_t)L.rom.nsplit * rom->r);
+        L.rom.dc = c.take<double>(B * (size_t)rom->r);
+        L.rom_status = c.take<int>(B);
+    }
+    return L;
+}
+
+#define HIPCHK(x)                                        \
+    do {                                                 \
+        hipError_t e_ = (x);                             \
+        if (e_ != hipSuccess) return RTE_EDEVICE;        \
+    } while (0)
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+void choose_tuning(rte_problem *p, int dg_req, int wpb_req) {
+    int nqmax = 0;
+    for (int q = 0; q < 4; ++q) nqmax = std::max(nqmax, p->quad.count[q]);
+    int dg = 1;
+    if (dg_req > 0) {
+        dg = dg_req;
+    } else {
+        const int cand[5] = {16, 8, 4, 2, 1};
+        for (int i = 0; i < 5; ++i) {
+            const int d = cand[i];
+            if (d > nqmax) continue;
+            long long items = 0;
+            for (int q = 0; q < 4; ++q) items += (long long)p->B * ((p->quad.count[q] + d - 1) / d);
+            if (items >= 1024 || d == 1) { dg = d; break; }
+        }
+    }
+    int wpb = wpb_req > 0 ? wpb_req : 4;
+    // LDS ring: wpb * nx * dg * 2 values of at most 8 bytes
+    while (wpb > 1 && (size_t)wpb * p->nx * dg * 2 * 8 > 64 * 1024) wpb /= 2;
+    while (dg > 1 && (size_t)wpb * p->nx * dg * 2 * 8 > 64 * 1024) dg /= 2;
+    p->tune.dg = dg;
+    p->tune.wpb = wpb;
+}
+
+// Per-kernel timing with HIP events recorded on the launch stream (enabled by
+// rte_profile_enable).  Events come from a pool that is reused across calls.
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t next = 0;
+    std::vector<std::pair<size_t, size_t>> marks[RTE_PROF_NKERNELS];
+    hipEvent_t get() {
+        if (next == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[next++];
+    }
+};
+Profiler g_prof;
+
+struct ProfScope {
+    hipEvent_t a = nullptr;
+    int id;
+    hipStream_t s;
+    size_t ia = 0;
+    ProfScope(int kid, hipStream_t st) : id(kid), s(st) {
+        if (!g_prof.on) return;
+        ia = g_prof.next;
+        a = g_prof.get();
+        if (a) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!g_prof.on || !a) return;
+        const size_t ib = g_prof.next;
+        hipEvent_t b = g_prof.get();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        g_prof.marks[id].push_back({ia, ib});
+    }
+};
+
+}  // namespace
+
+int rte_problem::nparts() const { return nparts_for(this); }
+
+extern "C" {
+
+int rte_profile_enable(int on) {
+    g_prof.on = on != 0;
+    g_prof.next = 0;
+    for (int k = 0; k < RTE_PROF_NKERNELS; ++k) g_prof.marks[k].clear();
+    return RTE_OK;
+}
+
+int rte_profile_read(int kernel, double *total_ms, long long *count) {
+    if (kernel < 0 || kernel >= RTE_PROF_NKERNELS || !total_ms || !count) return RTE_EINVAL;
+    double t = 0.0;
+    for (const auto &m : g_prof.marks[kernel]) {
+        if (hipEventSynchronize(g_prof.pool[m.second]) != hipSuccess) return RTE_EDEVICE;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, g_prof.pool[m.first], g_prof.pool[m.second]) != hipSuccess)
+            return RTE_EDEVICE;
+        t += ms;
+    }
+    *total_ms = t;
+    *count = (long long)g_prof.marks[kernel].size();
+    return RTE_OK;
+}
+
+const char *rte_strerror(int s) {
+    switch (s) {
+        case RTE_OK: return "ok";
+        case RTE_EINVAL: return "invalid argument";
+        case RTE_ENOCONV: return "iteration limit reached before the tolerance";
+        case RTE_ESINGULAR: return "singular reduced system";
+        case RTE_ECG: return "diffusion CG did not converge";
+        case RTE_ENOMEM: return "workspace too small";
+        case RTE_EDEVICE: return "HIP runtime error";
+        case RTE_EUNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+int rte_problem_create(const rte_problem_desc *d, rte_problem **out) {
+    return rte_problem_create_tuned(d, 0, 0, out);
+}
+
+int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_problem **out) {
+    if (!d || !out) return RTE_EINVAL;
+    *out = nullptr;
+    if (d->dim != 1 && d->dim != 2) return RTE_EINVAL;
+    if (d->nx < 1 || d->ny < 1 || d->batch < 1 || d->n_dir < 1) return RTE_EINVAL;
+    if (d->dim == 1 && d->ny != 1) return RTE_EINVAL;
+    if (!d->dir_x || !d->weight) return RTE_EINVAL;
+    if (d->dim == 2 && !d->dir_y) return RTE_EINVAL;
+    if (d->dim == 1 && !d->widths) return RTE_EINVAL;
+    if (!d->sigma_t || !d->sigma_s || !d->source || !d->inflow) return RTE_EINVAL;
+    if (dg != 0 && dg != 1 && dg != 2 && dg != 4 && dg != 8 && dg != 16) return RTE_EINVAL;
+    if (wpb < 0 || wpb > 4) return RTE_EINVAL;
+    if ((long long)d->nx * d->ny > (1ll << 31)) return RTE_EUNSUPPORTED;
+    double wsum = 0.0;
+    for (int j = 0; j < d->n_dir; ++j) {
+        if (!finite_pos(d->weight[j]) || !std::isfinite(d->dir_x[j])) return RTE_EINVAL;
+        if (d->dim == 2 && !std::isfinite(d->dir_y[j])) return RTE_EINVAL;
+        if (d->dim == 2 && d->dir_x[j] == 0.0 && d->dir_y[j] == 0.0) return RTE_EINVAL;
+        if (d->dim == 1 && d->dir_x[j] == 0.0) return RTE_EINVAL;
+        wsum += d->weight[j];
+    }
+    if (std::fabs(wsum - 1.0) > 1e-12) return RTE_EINVAL;
+    if (d->dim == 2 && (!finite_pos(d->lx) || !finite_pos(d->ly))) return RTE_EINVAL;
+    if (d->dim == 1)
+        for (int i = 0; i < d->nx; ++i)
+            if (!finite_pos(d->widths[i])) return RTE_EINVAL;
+
+    rte_problem *p = new (std::nothrow) rte_problem();
+    if (!p) return RTE_ENOMEM;
+    p->dim = d->dim;
+    p->nx = d->nx;
+    p->ny = d->ny;
+    p->B = d->batch;
+    p->n_dir = d->n_dir;
+    p->K = d->dim == 2 ? 4 : 2;
+    p->ncell = (long long)d->nx * d->ny;
+    p->ndof = p->ncell * p->K;
+    p->lx = d->lx;
+    p->ly = d->ly;
+    p->hx = d->dim == 2 ? d->lx / d->nx : 1.0;
+    p->hy = d->dim == 2 ? d->ly / d->ny : 1.0;
+    p->vx.assign(d->dir_x, d->dir_x + d->n_dir);
+    p->w.assign(d->weight, d->weight + d->n_dir);
+    if (d->dim == 2) p->vy.assign(d->dir_y, d->dir_y + d->n_dir);
+    else p->vy.assign(d->n_dir, 0.0);
+    if (d->dim == 1) p->widths.assign(d->widths, d->widths + d->nx);
+    p->sigma_t = d->sigma_t;
+    p->sigma_s = d->sigma_s;
+    p->source = d->source;
+    p->inflow = d->inflow;
+    p->cxx = p->cyy = p->kmin_x = p->kmin_y = p->c1 = p->c2 = p->c3 = 0.0;
+    for (int j = 0; j < d->n_dir; ++j) {
+        const double vx = p->vx[j], vy = p->vy[j], w = p->w[j];
+        p->cxx += w * vx * vx;
+        p->cyy += w * vy * vy;
+        if (vx > 0) p->kmin_x += w * vx;
+        if (vy > 0) p->kmin_y += w * vy;
+        if (vx > 0) { p->c1 += w * vx; p->c3 += w * vx * vx * vx; }
+        p->c2 += w * vx * vx;
+    }
+    p->d_dirs = nullptr;
+    p->d_mu = p->d_w = p->d_widths = nullptr;
+    // quadrant-sorted, padded direction table (2D)
+    std::vector<DirEntry> table;
+    for (int q = 0; q < 4; ++q) p->quad.count[q] = 0;
+    if (d->dim == 2) {
+        std::vector<int> idx[4];
+        for (int j = 0; j < d->n_dir; ++j) {
+            const int q = (p->vx[j] < 0 ? 1 : 0) | (p->vy[j] < 0 ? 2 : 0);
+            idx[q].push_back(j);
+        }
+        for (int q = 0; q < 4; ++q) {
+            p->quad.start[q] = (int)table.size();
+            p->quad.count[q] = (int)idx[q].size();
+            for (int j : idx[q]) {
+                DirEntry e;
+                e.alpha = std::fabs(p->vx[j]) / p->hx;
+                e.beta = std::fabs(p->vy[j]) / p->hy;
+                e.w = p->w[j];
+                e.orig = j;
+                e.pad = 0;
+                table.push_back(e);
+            }
+            while (table.size() % kQuadPad) {
+                DirEntry e;
+                e.alpha = 1.0;
+                e.beta = 1.0;
+                e.w = 0.0;
+                e.orig = -1;
+                e.pad = 0;
+                table.push_back(e);
+            }
+        }
+    }
+    p->n_sorted = (int)table.size();
+    choose_tuning(p, dg, wpb);
+    bool ok = true;
+    if (!table.empty()) {
+        ok = ok && hipMalloc(&p->d_dirs, table.size() * sizeof(DirEntry)) == hipSuccess;
+        ok = ok && hipMemcpy(p->d_dirs, table.data(), table.size() * sizeof(DirEntry),
+                             hipMemcpyHostToDevice) == hipSuccess;
+    }
+    ok = ok && hipMalloc(&p->d_w, sizeof(double) * p->n_dir) == hipSuccess;
+    ok = ok && hipMemcpy(p->d_w, p->w.data(), sizeof(double) * p->n_dir, hipMemcpyHostToDevice) == hipSuccess;
+    if (d->dim == 1) {
+        ok = ok && hipMalloc(&p->d_mu, sizeof(double) * p->n_dir) == hipSuccess;
+        ok = ok && hipMemcpy(p->d_mu, p->vx.data(), sizeof(double) * p->n_dir, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMalloc(&p->d_widths, sizeof(double) * p->nx) == hipSuccess;
+        ok = ok && hipMemcpy(p->d_widths, p->widths.data(), sizeof(double) * p->nx, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!ok) {
+        rte_problem_destroy(p);
+        return RTE_EDEVICE;
+    }
+    *out = p;
+    return RTE_OK;
+}
+
+void rte_problem_destroy(rte_problem *p) {
+    if (!p) return;
+    if (p->d_dirs) (void)hipFree(p->d_dirs);
+    if (p->d_w) (void)hipFree(p->d_w);
+    if (p->d_mu) (void)hipFree(p->d_mu);
+    if (p->d_widths) (void)hipFree(p->d_widths);
+    delete p;
+}
+
+int rte_problem_tuning(const rte_problem *p, int *dg, int *wpb, int *nparts) {
+    if (!p) return RTE_EINVAL;
+    if (dg) *dg = p->tune.dg;
+    if (wpb) *wpb = p->tune.wpb;
+    if (nparts) *nparts = p->dim == 2 ? nparts_for(p) : 0;
+    return RTE_OK;
+}
+
+int rte_workspace_size(const rte_problem *p, rte_mode mode, const rte_rom *rom,
+                       rte_precision prec, int max_iter, size_t *bytes) {
+    if (!p || !bytes || max_iter < 0) return RTE_EINVAL;
+    if (mode != RTE_SI && mode != RTE_SI_DSA && mode != RTE_ROMSAD) return RTE_EINVAL;
+    if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
+    Carver c(nullptr, 0);
+    carve(c, p, mode, rom, prec, max_iter);
+    *bytes = c.off;
+    return RTE_OK;
+}
+
+int rte_problem_check(const rte_problem *p, void *ws, size_t ws_bytes, rte_stream_t stream) {
+    if (!p || !ws) return RTE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, RTE_SI, nullptr, RTE_FP64, 1);
+    if (!c.ok) return RTE_ENOMEM;
+    HIPCHK(launch_fill_int(L.flag, 1, 0, s));
+    HIPCHK(launch_check_materials(p, L.flag, s));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, L.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return bad ? RTE_EINVAL : RTE_OK;
+}
+
+int rte_rom_create(const rte_problem *p, const rte_rom_desc *d, rte_rom **out) {
+    if (!p || !d || !out) return RTE_EINVAL;
+    *out = nullptr;
+    if (d->r < 1 || d->r > 64 || d->m < 0) return RTE_EINVAL;
+    if (!d->U_rho || !d->U_iso || !d->A0 || (d->m > 0 && !d->A)) return RTE_EINVAL;
+    const size_t nu = (size_t)p->ndof * d->r;
+    for (size_t i = 0; i < nu; ++i)
+        if (!std::isfinite(d->U_rho[i]) || !std::isfinite(d->U_iso[i])) return RTE_EINVAL;
+    rte_rom *r = new (std::nothrow) rte_rom();
+    if (!r) return RTE_ENOMEM;
+    r->r = d->r;
+    r->m = d->m;
+    r->ndof = p->ndof;
+    r->eps_pod = d->eps_pod;
+    r->eps_train = d->eps_train;
+    r->d_U_rho = r->d_U_iso = r->d_A0 = r->d_A = nullptr;
+    r->d_U_rho_f = r->d_U_iso_f = nullptr;
+    std::vector<float> tmp(nu);
+    bool ok = true;
+    ok = ok && hipMalloc(&r->d_U_rho, nu * 8) == hipSuccess;
+    ok = ok && hipMalloc(&r->d_U_iso, nu * 8) == hipSuccess;
+    ok = ok && hipMalloc(&r->d_U_rho_f, nu * 4) == hipSuccess;
+    ok = ok && hipMalloc(&r->d_U_iso_f, nu * 4) == hipSuccess;
+    ok = ok && hipMalloc(&r->d_A0, (size_t)d->r * d->r * 8) == hipSuccess;
+    ok = ok && hipMalloc(&r->d_A, std::max<size_t>(1, (size_t)d->m * d->r * d->r) * 8) == hipSuccess;
+    ok = ok && hipMemcpy(r->d_U_rho, d->U_rho, nu * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(r->d_U_iso, d->U_iso, nu * 8, hipMemcpyHostToDevice) == hipSuccess;
+    for (size_t i = 0; ok && i < nu; ++i) tmp[i] = (float)d->U_rho[i];
+    ok = ok && hipMemcpy(r->d_U_rho_f, tmp.data(), nu * 4, hipMemcpyHostToDevice) == hipSuccess;
+    for (size_t i = 0; ok && i < nu; ++i) tmp[i] = (float)d->U_iso[i];
+    ok = ok && hipMemcpy(r->d_U_iso_f, tmp.data(), nu * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(r->d_A0, d->A0, (size_t)d->r * d->r * 8, hipMemcpyHostToDevice) == hipSuccess;
+    if (d->m > 0)
+        ok = ok && hipMemcpy(r->d_A, d->A, (size_t)d->m * d->r * d->r * 8, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        rte_rom_destroy(r);
+        return RTE_EDEVICE;
+    }
+    *out = r;
+    return RTE_OK;
+}
+
+void rte_rom_destroy(rte_rom *r) {
+    if (!r) return;
+    if (r->d_U_rho) (void)hipFree(r->d_U_rho);
+    if (r->d_U_iso) (void)hipFree(r->d_U_iso);
+    if (r->d_U_rho_f) (void)hipFree(r->d_U_rho_f);
+    if (r->d_U_iso_f) (void)hipFree(r->d_U_iso_f);
+    if (r->d_A0) (void)hipFree(r->d_A0);
+    if (r->d_A) (void)hipFree(r->d_A);
+    delete r;
+}
+
+}  // extern "C"
+
+namespace {
+
+// one sweep of every active instance: src -> rho_star (+ change maxima against rho_prev)
+int do_sweep(const rte_problem *p, const Layout &L, const void *src, void *f_out,
+             double *rho_star, const double *rho_prev, const int *active, int zero_inflow,
+             int fp32, hipStream_t s) {
+    if (p->dim == 2) {
+        SweepLaunch a;
+        a.p = p;
+        a.src = src;
+        a.partial = rho_star ? L.partial : nullptr;
+        a.f_out = f_out;
+        a.active = active;
+        a.zero_inflow = zero_inflow;
+        a.fp32 = fp32;
+        {
+            ProfScope ps(RTE_PROF_SWEEP2D, s);
+            HIPCHK(launch_sweep2d(a, s));
+        }
+        ProfScope ps(RTE_PROF_REDUCE, s);
+        if (rho_star)
+            HIPCHK(launch_reduce_parts(p, L.partial, nparts_for(p), rho_star, rho_prev,
+                                       rho_prev ? L.st.maxd : nullptr,
+                                       rho_prev ? L.st.maxr : nullptr, active, s));
+    } else {
+        void *f = f_out ? f_out : L.fscratch;
+        {
+            ProfScope ps(RTE_PROF_SWEEP1D, s);
+            HIPCHK(launch_sweep1d(p, src, f, active, zero_inflow, fp32, s));
+        }
+        if (rho_star)
+            HIPCHK(launch_scalar_flux(p, f, rho_star, fp32, rho_prev,
+                                      rho_prev ? L.st.maxd : nullptr,
+                                      rho_prev ? L.st.maxr : nullptr, active, s));
+    }
+    return RTE_OK;
+}
+
+// diffusion correction for the instances whose kind equals `want` (all if kind == nullptr)
+int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const double *rho_prev,
+           double *delta, const int *kind, int want, double rtol, int maxit, int *iters_out,
+           int *failed, hipStream_t s) {
+    ProfScope ps(RTE_PROF_DSA, s);
+    if (p->dim == 1) {
+        HIPCHK(launch_dsa1d(p, rho_star, rho_prev, delta, kind, want, L.dsa1d, s));
+        return RTE_OK;
+    }
+    HIPCHK(launch_cg_setup(p, L.cg, rho_star, rho_prev, kind, want, rtol, s));
+    const int poll = 8;
+    int running = 1;
+    for (int it = 1; it <= maxit + 1; ++it) {
+        HIPCHK(launch_cg_iteration(p, L.cg, it, rtol, maxit, s));
+        if (it == 1 || it % poll == 0 || it == maxit + 1) {
+            HIPCHK(hipMemcpyAsync(&running, L.cg.n_running, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (running == 0) break;
+        }
+    }
+    if (failed) *failed = running != 0;
+    HIPCHK(launch_cg_finish(p, L.cg, delta, iters_out, s));
+    return RTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
+              int zero_inflow, rte_precision prec, void *ws, size_t ws_bytes, rte_stream_t stream) {
+    if (!p || !rho_in || (!f_out && !rho_star_out) || !ws) return RTE_EINVAL;
+    if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, RTE_SI, nullptr, prec, 1);
+    if (!c.ok) return RTE_ENOMEM;
+    const int fp32 = prec == RTE_MIXED;
+    HIPCHK(launch_source(p, rho_in, L.src, nullptr, fp32, s));
+    return do_sweep(p, L, L.src, f_out, rho_star_out, nullptr, nullptr, zero_inflow, fp32, s);
+}
+
+int rte_scalar_flux(const rte_problem *p, const void *f, double *rho_out, rte_precision prec,
+                    rte_stream_t stream) {
+    if (!p || !f || !rho_out) return RTE_EINVAL;
+    if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
+    HIPCHK(launch_scalar_flux(p, f, rho_out, prec == RTE_MIXED, nullptr, nullptr, nullptr, nullptr,
+                              (hipStream_t)stream));
+    return RTE_OK;
+}
+
+int rte_dsa_correct(const rte_problem *p, const double *rho_star, const double *rho_prev,
+                    double *delta_rho, double cg_rtol, int cg_maxit, int *cg_iters_out, void *ws,
+                    size_t ws_bytes, rte_stream_t stream) {
+    if (!p || !rho_star || !rho_prev || !delta_rho || !ws) return RTE_EINVAL;
+    if (p->dim == 2 && (!(cg_rtol > 0.0) || cg_maxit < 1)) return RTE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, RTE_SI_DSA, nullptr, RTE_FP64, 1);
+    if (!c.ok) return RTE_ENOMEM;
+    int failed = 0;
+    int rc = do_dsa(p, L, rho_star, rho_prev, delta_rho, nullptr, 0, cg_rtol, cg_maxit,
+                    cg_iters_out, &failed, s);
+    if (rc) return rc;
+    return failed ? RTE_ECG : RTE_OK;
+}
+
+int rte_rom_correct(const rte_problem *p, const rte_rom *rom, const double *psi,
+                    const double *rho_star, const double *rho_prev, double *delta_rho,
+                    int *status_out, rte_precision prec, void *ws, size_t ws_bytes,
+                    rte_stream_t stream) {
+    if (!p || !rom || !rho_star || !rho_prev || !delta_rho || !ws) return RTE_EINVAL;
+    if (rom->m > 0 && !psi) return RTE_EINVAL;
+    if (rom->ndof != p->ndof) return RTE_EINVAL;
+    if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, RTE_ROMSAD, rom, prec, 1);
+    if (!c.ok) return RTE_ENOMEM;
+    HIPCHK(launch_rom_correct(p, rom, psi, rho_star, rho_prev, delta_rho,
+                              status_out ? status_out : L.rom_status, nullptr, 0, L.rom,
+                              prec == RTE_MIXED, s));
+    return RTE_OK;
+}
+
+int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
+                   const rte_solve_opts *o, double *rho, void *f_out, rte_solve_stats *stats,
+                   void *ws, size_t ws_bytes, rte_stream_t stream) {
+    if (!p || !o || !rho || !ws) return RTE_EINVAL;
+    if (mode != RTE_SI && mode != RTE_SI_DSA && mode != RTE_ROMSAD) return RTE_EINVAL;
+    if (mode == RTE_ROMSAD && (!rom || (rom->m > 0 && !psi) || rom->ndof != p->ndof)) return RTE_EINVAL;
+    if (!(o->eps >= 0.0) || o->max_iter < 1 || o->theta < 0) return RTE_EINVAL;
+    if (o->precision != RTE_FP64 && o->precision != RTE_MIXED) return RTE_EINVAL;
+    if (mode != RTE_SI && p->dim == 2 && (!(o->cg_rtol > 0.0) || o->cg_maxit < 1)) return RTE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int max_iter = o->max_iter;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, max_iter);
+    if (!c.ok) return RTE_ENOMEM;
+    const int fp32 = o->precision == RTE_MIXED;
+    double eps_romsad = o->eps_romsad;
+    if (mode == RTE_ROMSAD && eps_romsad < 0.0)
+        eps_romsad = 0.1 * std::max(rom->eps_train, rom->eps_pod);   // eq. (romsad_parameters)
+    const int poll = o->poll_every > 0 ? o->poll_every : 1;
+
+    HIPCHK(launch_init_state(p, L.st, max_iter, s));
+    HIPCHK(launch_source(p, rho, L.src, nullptr, fp32, s));
+    int iterations = 0;
+    bool cg_failed = false;
+    for (int l = 1; l <= max_iter; ++l) {
+        int rc = do_sweep(p, L, L.src, f_out, L.rho_star, rho, L.st.active, 0, fp32, s);
+        if (rc) return rc;
+        HIPCHK(launch_decide(p, L.st, l, max_iter, o->eps, o->relative, (int)mode, o->theta,
+                             eps_romsad, s));
+        const double *delta = nullptr;
+        if (mode == RTE_ROMSAD) {
+            ProfScope ps(RTE_PROF_ROM, s);
+            HIPCHK(launch_rom_correct(p, rom, psi, L.rho_star, rho, L.delta, L.rom_status,
+                                      L.st.kind, 2, L.rom, fp32, s));
+            delta = L.delta;
+        }
+        if (mode != RTE_SI) {
+            int failed = 0;
+            rc = do_dsa(p, L, L.rho_star, rho, L.delta, L.st.kind, 1, o->cg_rtol, o->cg_maxit,
+                        L.cg.iters, &failed, s);
+            if (rc) return rc;
+            cg_failed = cg_failed || failed;
+            delta = L.delta;
+        }
+        HIPCHK(launch_update(p, L.st, L.rho_star, delta, rho, L.src, fp32, s));
+        iterations = l;
+        if (l % poll == 0 || l == max_iter) {
+            int n_active = 0;
+            HIPCHK(hipMemcpyAsync(&n_active, L.st.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (n_active == 0) break;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int> status(p->B);
+    HIPCHK(hipMemcpy(status.data(), L.st.status, sizeof(int) * p->B, hipMemcpyDeviceToHost));
+    int rc = RTE_OK;
+    for (int b = 0; b < p->B; ++b)
+        if (status[b] != RTE_OK) rc = RTE_ENOCONV;
+    if (stats) {
+        if (stats->n_sweep)
+            HIPCHK(hipMemcpy(stats->n_sweep, L.st.n_sweep, sizeof(int) * p->B, hipMemcpyDeviceToHost));
+        if (stats->status) std::memcpy(stats->status, status.data(), sizeof(int) * p->B);
+        if (stats->change)
+            HIPCHK(hipMemcpy(stats->change, L.st.change, sizeof(double) * p->B * max_iter,
+                             hipMemcpyDeviceToHost));
+        if (stats->kind)
+            HIPCHK(hipMemcpy(stats->kind, L.st.kinds, sizeof(int) * p->B * max_iter,
+                             hipMemcpyDeviceToHost));
+        stats->cg_iterations = 0;
+        stats->iterations = iterations;
+    }
+    if (cg_failed && rc == RTE_OK) rc = RTE_ECG;
+    return rc;
+}
+
+}  // extern "C"

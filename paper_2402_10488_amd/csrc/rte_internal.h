@@ -1,0 +1,169 @@
+// Internal declarations of the gfx950 RTE library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "rte.h"
+
+namespace rte {
+
+// Direction entry of the quadrant-sorted direction table used by the 2D sweep.
+// alpha = |v_x| / h_x, beta = |v_y| / h_y; w = 0 marks a padding entry.
+struct DirEntry {
+    double alpha;
+    double beta;
+    double w;
+    int orig;   // index in the caller's direction order, -1 for padding
+    int pad;
+};
+
+constexpr int kQuadPad = 16;   // each quadrant's block of the sorted table is padded to this multiple
+
+// Per-quadrant layout of the sorted direction table.
+struct QuadLayout {
+    int start[4];   // first sorted entry of quadrant q (q = (vx<0) | 2 (vy<0))
+    int count[4];   // directions in quadrant q
+};
+
+struct Tuning {
+    int dg;         // directions per lane in the 2D sweep (1, 2, 4, 8, 16)
+    int wpb;        // waves per workgroup in the 2D sweep
+};
+
+struct Workspace;   // carve-up of the caller's workspace, see rte_api.hip
+
+}  // namespace rte
+
+struct rte_problem {
+    int dim, nx, ny, B, n_dir, K;
+    long long ncell, ndof;
+    double hx, hy, lx, ly;
+    std::vector<double> vx, vy, w, widths;
+    // angular moments of the direction set
+    double cxx, cyy;          // sum w vx^2, sum w vy^2
+    double kmin_x, kmin_y;    // sum_{vx>0} w vx, sum_{vy>0} w vy
+    double c1, c2, c3;        // 1D: sum_{mu>0} w mu, sum w mu^2, sum_{mu>0} w mu^3
+    const double *sigma_t, *sigma_s, *source, *inflow;
+    rte::QuadLayout quad;
+    rte::Tuning tune;
+    int n_sorted;
+    rte::DirEntry *d_dirs;    // device [n_sorted]
+    double *d_mu;             // 1D: device [n_dir] directions
+    double *d_w;              // device [n_dir] weights (caller order)
+    double *d_widths;         // 1D: device [nx]
+    int nparts() const;       // 2D sweep partial-sum slots per instance for the current tuning
+};
+
+struct rte_rom {
+    int r, m;
+    long long ndof;
+    double eps_pod, eps_train;
+    double *d_U_rho;   // device [ndof][r]
+    double *d_U_iso;   // device [ndof][r]
+    float *d_U_rho_f;  // device [ndof][r] (FP32 copy for the mixed-precision projections)
+    float *d_U_iso_f;
+    double *d_A0;      // device [r][r]
+    double *d_A;       // device [m][r][r]
+};
+
+// ---------------------------------------------------------------------------------------------
+// kernel launchers (defined in the .hip files); all return hipError_t of the launch
+// ---------------------------------------------------------------------------------------------
+namespace rte {
+
+struct SweepLaunch {
+    const rte_problem *p;
+    const void *src;          // [B][ndof] T: sigma_s rho + G sqrt(hx hy) delta_k0 (2D)
+    double *partial;          // [B][nparts][ndof] or nullptr
+    void *f_out;              // [B][n_dir][ndof] T or nullptr
+    const int *active;        // [B] or nullptr
+    int zero_inflow;
+    int fp32;
+};
+hipError_t launch_sweep2d(const SweepLaunch &a, hipStream_t s);
+
+// 1D sweep: writes f (always, T) to f_out [B][n_dir][ndof]; src as in 2D (K = 2).
+hipError_t launch_sweep1d(const rte_problem *p, const void *src, void *f_out, const int *active,
+                          int zero_inflow, int fp32, hipStream_t s);
+
+// src = sigma_s rho + G * (cell integral of phi_0); written as T
+hipError_t launch_source(const rte_problem *p, const double *rho, void *src, const int *active,
+                         int fp32, hipStream_t s);
+
+// rho = sum of nparts partial slots (fixed order); optional change/magnitude maxima per instance
+hipError_t launch_reduce_parts(const rte_problem *p, const double *partial, int nparts,
+                               double *rho_star, const double *rho_prev, unsigned long long *maxd,
+                               unsigned long long *maxr, const int *active, hipStream_t s);
+
+// rho = sum_j w_j f_j over f [B][n_dir][ndof]
+hipError_t launch_scalar_flux(const rte_problem *p, const void *f, double *rho, int fp32,
+                              const double *rho_prev, unsigned long long *maxd,
+                              unsigned long long *maxr, const int *active, hipStream_t s);
+
+hipError_t launch_check_materials(const rte_problem *p, int *bad, hipStream_t s);
+
+// diffusion corrections
+// scratch: [B][nx][20] doubles
+hipError_t launch_dsa1d(const rte_problem *p, const double *rho_star, const double *rho_prev,
+                        double *delta, const int *kind, int want_kind, double *scratch,
+                        hipStream_t s);
+
+struct CGSpace {
+    double *x, *r, *z, *p0, *p1, *q;   // [B][ndof]
+    double *part;                      // [B][5][nblk] partial sums
+    double *scal;                      // [B][8] per-instance scalars
+    int *iters;                        // [B]
+    int *state;                        // [B] 0 idle, 1 running, 2 converged, 3 failed
+    int *n_running;                    // [1]
+    int nblk;                          // blocks per instance
+};
+hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double *rho_star,
+                           const double *rho_prev, const int *kind, int want_kind, double rtol,
+                           hipStream_t s);
+hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, double rtol,
+                               int maxit, hipStream_t s);
+hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delta, int *iters_out,
+                            hipStream_t s);
+size_t cg_blocks_per_instance(const rte_problem *p);
+
+// ROM correction
+struct RomSpace {
+    double *y;        // [B][r]
+    double *ypart;    // [B][nsplit][r] split-K partials
+    double *dc;       // [B][r]
+    int nsplit;
+};
+hipError_t launch_rom_correct(const rte_problem *p, const rte_rom *rom, const double *psi,
+                              const double *rho_star, const double *rho_prev, double *delta,
+                              int *status, const int *kind, int want_kind, const RomSpace &w,
+                              int fp32, hipStream_t s);
+size_t rom_split(const rte_problem *p, const rte_rom *rom);
+
+// Alg. 1 / Alg. 2 bookkeeping
+struct IterState {
+    unsigned long long *maxd, *maxr;   // [B]
+    int *active;                       // [B] 1 while iterating
+    int *kind;                         // [B] correction chosen after the current sweep
+    int *n_sweep;                      // [B]
+    int *status;                       // [B]
+    double *change;                    // [B][max_iter]
+    int *kinds;                        // [B][max_iter]
+    int *n_active;                     // [1]
+};
+hipError_t launch_decide(const rte_problem *p, const IterState &st, int l, int max_iter,
+                         double eps, int relative, int mode, int theta, double eps_romsad,
+                         hipStream_t s);
+// rho = rho* + delta (delta may be null) for instances corrected at iteration l; converged
+// instances keep rho* ; then src for the next sweep.
+hipError_t launch_update(const rte_problem *p, const IterState &st, const double *rho_star,
+                         const double *delta, double *rho, void *src, int fp32, hipStream_t s);
+hipError_t launch_init_state(const rte_problem *p, const IterState &st, int max_iter,
+                             hipStream_t s);
+hipError_t launch_zero(double *x, long long n, hipStream_t s);
+hipError_t launch_fill_int(int *x, long long n, int v, hipStream_t s);
+
+}  // namespace rte

@@ -1,0 +1,300 @@
+"""ctypes binding of librte.so (argument marshalling only).
+
+Every numerical step runs in the library's gfx950 kernels; PyTorch provides device memory and
+the stream.  Importing this module on a machine without the built library raises at once.
+Names follow the C ABI in include/rte.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librte.so")
+
+RTE_OK, RTE_EINVAL, RTE_ENOCONV, RTE_ESINGULAR, RTE_ECG, RTE_ENOMEM, RTE_EDEVICE, RTE_EUNSUPPORTED = range(8)
+FP64, MIXED = 0, 1
+SI, SI_DSA, ROMSAD = 0, 1, 2
+MODES = {"si": SI, "si_dsa": SI_DSA, "romsad": ROMSAD}
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+
+class RteError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+        self.status = status
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("batch", ctypes.c_int), ("n_dir", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("widths", _D), ("dir_x", _D), ("dir_y", _D), ("weight", _D),
+                ("sigma_t", _vp), ("sigma_s", _vp), ("source", _vp), ("inflow", _vp)]
+
+
+class RomDesc(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int), ("m", ctypes.c_int), ("U_rho", _D), ("U_iso", _D),
+                ("A0", _D), ("A", _D), ("eps_pod", ctypes.c_double),
+                ("eps_train", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("max_iter", ctypes.c_int), ("relative", ctypes.c_int),
+                ("theta", ctypes.c_int), ("eps_romsad", ctypes.c_double),
+                ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
+                ("precision", ctypes.c_int), ("poll_every", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("n_sweep", ctypes.POINTER(ctypes.c_int)), ("status", ctypes.POINTER(ctypes.c_int)),
+                ("change", _D), ("kind", ctypes.POINTER(ctypes.c_int)),
+                ("cg_iterations", ctypes.c_longlong), ("iterations", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2402_10488_amd/build.py "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.rte_strerror.restype = ctypes.c_char_p
+    L.rte_strerror.argtypes = [ctypes.c_int]
+    L.rte_problem_create_tuned.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(P)]
+    L.rte_problem_destroy.argtypes = [P]
+    L.rte_problem_destroy.restype = None
+    L.rte_problem_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int)]
+    L.rte_problem_check.argtypes = [P, _vp, ctypes.c_size_t, _vp]
+    L.rte_rom_create.argtypes = [P, ctypes.POINTER(RomDesc), ctypes.POINTER(P)]
+    L.rte_rom_destroy.argtypes = [P]
+    L.rte_rom_destroy.restype = None
+    L.rte_workspace_size.argtypes = [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_size_t)]
+    L.rte_sweep.argtypes = [P, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
+    L.rte_scalar_flux.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
+    L.rte_dsa_correct.argtypes = [P, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
+                                  ctypes.c_size_t, _vp]
+    L.rte_rom_correct.argtypes = [P, P, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t,
+                                  _vp]
+    L.rte_sisa_solve.argtypes = [P, ctypes.c_int, P, _vp, ctypes.POINTER(SolveOpts), _vp, _vp,
+                                 ctypes.POINTER(SolveStats), _vp, ctypes.c_size_t, _vp]
+    L.rte_profile_enable.argtypes = [ctypes.c_int]
+    L.rte_profile_read.argtypes = [ctypes.c_int, _D, ctypes.POINTER(ctypes.c_longlong)]
+    return L
+
+
+lib = _load()
+
+EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destroy",
+            "rte_problem_tuning", "rte_problem_check", "rte_rom_create", "rte_rom_destroy",
+            "rte_workspace_size", "rte_sweep", "rte_scalar_flux", "rte_dsa_correct",
+            "rte_rom_correct", "rte_sisa_solve", "rte_strerror", "rte_profile_enable",
+            "rte_profile_read"]
+
+PROF = {"sweep2d": 0, "reduce": 1, "dsa": 2, "rom": 3, "sweep1d": 4}
+
+
+def profile_enable(on=True):
+    """Start (clear) or stop per-kernel HIP-event timing inside the library."""
+    _check(lib.rte_profile_enable(int(bool(on))), "rte_profile_enable")
+
+
+def profile_read(kernel):
+    """(total milliseconds, number of timed launches) of a kernel group since profile_enable."""
+    ms, n = ctypes.c_double(), ctypes.c_longlong()
+    _check(lib.rte_profile_read(PROF[kernel], ctypes.byref(ms), ctypes.byref(n)), "rte_profile_read")
+    return ms.value, n.value
+
+
+def strerror(status: int) -> str:
+    return lib.rte_strerror(int(status)).decode()
+
+
+def _check(status, what):
+    if status != RTE_OK:
+        raise RteError(status, what)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _host(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_D)
+
+
+class Problem:
+    """A batch of B instances sharing mesh and directions; materials live on the device.
+
+    sigma_t, sigma_s, G: float64 CUDA tensors [B, ny, nx]; inflow [B, 4].
+    Directions and weights are host arrays (normalized weights).
+    """
+
+    def __init__(self, dim, nx, ny, dirs_x, weights, sigma_t, sigma_s, G, inflow, dirs_y=None,
+                 lx=1.0, ly=1.0, widths=None, dg=0, wpb=0):
+        import torch
+        for t in (sigma_t, sigma_s, G, inflow):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        self.dim, self.nx, self.ny = dim, nx, ny
+        self.B = int(sigma_t.shape[0])
+        self.K = 4 if dim == 2 else 2
+        self.ncell = nx * ny
+        self.ndof = self.ncell * self.K
+        self.n_dir = len(dirs_x)
+        self._keep = [sigma_t, sigma_s, G, inflow]
+        self.sigma_t, self.sigma_s, self.G, self.inflow = sigma_t, sigma_s, G, inflow
+        self._dx, pdx = _host(dirs_x)
+        self._w, pw = _host(weights)
+        pdy, pwd = None, None
+        if dirs_y is not None:
+            self._dy, pdy = _host(dirs_y)
+        if widths is not None:
+            self._wd, pwd = _host(widths)
+        d = ProblemDesc(dim, nx, ny, self.B, self.n_dir, float(lx), float(ly), pwd, pdx, pdy, pw,
+                        _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow))
+        h = ctypes.c_void_p()
+        _check(lib.rte_problem_create_tuned(ctypes.byref(d), int(dg), int(wpb), ctypes.byref(h)),
+               "rte_problem_create")
+        self.handle = h
+        self.weights = np.asarray(weights, dtype=np.float64)
+
+    def tuning(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.rte_problem_tuning(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "rte_problem_tuning")
+        return {"dg": a.value, "wpb": b.value, "nparts": c.value}
+
+    def workspace_bytes(self, mode="si", rom=None, precision="fp64", max_iter=1):
+        n = ctypes.c_size_t()
+        _check(lib.rte_workspace_size(self.handle, MODES[mode], rom.handle if rom else None,
+                                      PRECISIONS[precision], int(max_iter), ctypes.byref(n)),
+               "rte_workspace_size")
+        return n.value
+
+    def workspace(self, mode="si", rom=None, precision="fp64", max_iter=1):
+        import torch
+        nb = self.workspace_bytes(mode, rom, precision, max_iter)
+        return torch.empty(max(nb, 256), dtype=torch.uint8, device=self.sigma_t.device)
+
+    def check(self, ws=None):
+        ws = ws if ws is not None else self.workspace()
+        _check(lib.rte_problem_check(self.handle, _ptr(ws), ws.numel(), _stream()), "rte_problem_check")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.rte_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Rom:
+    """Correction ROM operators (host arrays, copied to the device at creation)."""
+
+    def __init__(self, problem: Problem, U_rho, U_iso, A0, A, eps_pod, eps_train):
+        self._u_rho, pur = _host(U_rho)
+        self._u_iso, pui = _host(U_iso)
+        self._a0, pa0 = _host(A0)
+        A = np.asarray(A, dtype=np.float64).reshape(-1, self._a0.shape[0], self._a0.shape[0])
+        self._a, pa = _host(A)
+        self.r = int(self._a0.shape[0])
+        self.m = int(A.shape[0])
+        assert self._u_rho.shape == (problem.ndof, self.r)
+        d = RomDesc(self.r, self.m, pur, pui, pa0, pa, float(eps_pod), float(eps_train))
+        h = ctypes.c_void_p()
+        _check(lib.rte_rom_create(problem.handle, ctypes.byref(d), ctypes.byref(h)), "rte_rom_create")
+        self.handle = h
+        self.eps_pod, self.eps_train = float(eps_pod), float(eps_train)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.rte_rom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sweep(p: Problem, rho_in, f_out=None, rho_star_out=None, zero_inflow=False, precision="fp64",
+          ws=None):
+    ws = ws if ws is not None else p.workspace("si", None, precision)
+    _check(lib.rte_sweep(p.handle, _ptr(rho_in), _ptr(f_out), _ptr(rho_star_out), int(zero_inflow),
+                         PRECISIONS[precision], _ptr(ws), ws.numel(), _stream()), "rte_sweep")
+
+
+def scalar_flux(p: Problem, f, rho_out, precision="fp64"):
+    _check(lib.rte_scalar_flux(p.handle, _ptr(f), _ptr(rho_out), PRECISIONS[precision], _stream()),
+           "rte_scalar_flux")
+
+
+def dsa_correct(p: Problem, rho_star, rho_prev, delta_out, cg_rtol=1e-10, cg_maxit=5000,
+                iters_out=None, ws=None):
+    ws = ws if ws is not None else p.workspace("si_dsa")
+    _check(lib.rte_dsa_correct(p.handle, _ptr(rho_star), _ptr(rho_prev), _ptr(delta_out),
+                               float(cg_rtol), int(cg_maxit), _ptr(iters_out), _ptr(ws), ws.numel(),
+                               _stream()), "rte_dsa_correct")
+
+
+def rom_correct(p: Problem, rom: Rom, psi, rho_star, rho_prev, delta_out, status_out=None,
+                precision="fp64", ws=None):
+    ws = ws if ws is not None else p.workspace("romsad", rom, precision)
+    _check(lib.rte_rom_correct(p.handle, rom.handle, _ptr(psi), _ptr(rho_star), _ptr(rho_prev),
+                               _ptr(delta_out), _ptr(status_out), PRECISIONS[precision], _ptr(ws),
+                               ws.numel(), _stream()), "rte_rom_correct")
+
+
+@dataclass
+class SolveResult:
+    status: int
+    n_sweep: np.ndarray
+    inst_status: np.ndarray
+    change: np.ndarray
+    kind: np.ndarray
+    iterations: int
+
+
+def sisa_solve(p: Problem, rho_inout, mode="si_dsa", rom: Optional[Rom] = None, psi=None,
+               eps=1e-8, max_iter=500, relative=True, theta=5, eps_romsad=-1.0, cg_rtol=1e-10,
+               cg_maxit=5000, precision="fp64", poll_every=4, f_out=None, ws=None,
+               raise_on_error=True):
+    ws = ws if ws is not None else p.workspace(mode, rom, precision, max_iter)
+    B = p.B
+    n_sweep = np.zeros(B, np.int32)
+    st = np.zeros(B, np.int32)
+    change = np.zeros((B, max_iter))
+    kind = np.zeros((B, max_iter), np.int32)
+    stats = SolveStats(n_sweep.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                       st.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), change.ctypes.data_as(_D),
+                       kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 0, 0)
+    o = SolveOpts(float(eps), int(max_iter), int(relative), int(theta), float(eps_romsad),
+                  float(cg_rtol), int(cg_maxit), PRECISIONS[precision], int(poll_every))
+    rc = lib.rte_sisa_solve(p.handle, MODES[mode], rom.handle if rom else None, _ptr(psi),
+                            ctypes.byref(o), _ptr(rho_inout), _ptr(f_out), ctypes.byref(stats),
+                            _ptr(ws), ws.numel(), _stream())
+    if raise_on_error and rc not in (RTE_OK, RTE_ENOCONV):
+        raise RteError(rc, "rte_sisa_solve")
+    return SolveResult(rc, n_sweep, st, change, kind, stats.iterations)
