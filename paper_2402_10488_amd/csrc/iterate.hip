@@ -39,10 +39,11 @@ __global__ void decide_kernel(int B, int l, int max_iter, double eps, int relati
 }
 
 template <typename T>
-__global__ void update_kernel(long long ncell, int K, int B, const int *kind, int *active,
-                              const double *rho_star, const double *delta, double *rho,
+__global__ void update_kernel(int dim, long long ncell, int K, int B, int nx, int ny,
+                              const int *kind, int *active, const double *rho_star,
+                              const double *delta, double *rho, const double *sigma_t,
                               const double *sigma_s, const double *G, const double *cellw,
-                              double ghost, T *src) {
+                              double ghost, const int *offA, const int *offB, T *src) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)B * ncell) return;
     const int b = (int)(t / ncell);
@@ -56,12 +57,14 @@ __global__ void update_kernel(long long ncell, int K, int B, const int *kind, in
     }
     const double ss = sigma_s[t];
     const double g0 = G[t] * (cellw ? sqrt(cellw[cell]) : ghost);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int q = 0; q < K; ++q) {
-        double v = rho_star[t * K + q];
-        if (k > 0 && delta) v += delta[t * K + q];
-        rho[t * K + q] = v;
-        src[t * K + q] = (T)(ss * v + (q == 0 ? g0 : 0.0));
+        double r = rho_star[t * K + q];
+        if (k > 0 && delta) r += delta[t * K + q];
+        rho[t * K + q] = r;
+        v[q] = ss * r + (q == 0 ? g0 : 0.0);
     }
+    write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, offA, offB, v, sigma_t[t], src);
 }
 
 __global__ void init_state_kernel(int B, int max_iter, unsigned long long *maxd,
@@ -112,12 +115,14 @@ hipError_t launch_update(const rte_problem *p, const IterState &st, const double
     const double *cw = p->dim == 1 ? p->d_widths : nullptr;
     if (fp32)
         hipLaunchKernelGGL(update_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                           p->ncell, p->K, p->B, st.kind, st.active, rho_star, delta, rho,
-                           p->sigma_s, p->source, cw, ghost, (float *)src);
+                           p->dim, p->ncell, p->K, p->B, p->nx, p->ny, st.kind, st.active,
+                           rho_star, delta, rho, p->sigma_t, p->sigma_s, p->source, cw, ghost,
+                           p->d_offA, p->d_offB, (float *)src);
     else
         hipLaunchKernelGGL(update_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                           p->ncell, p->K, p->B, st.kind, st.active, rho_star, delta, rho,
-                           p->sigma_s, p->source, cw, ghost, (double *)src);
+                           p->dim, p->ncell, p->K, p->B, p->nx, p->ny, st.kind, st.active,
+                           rho_star, delta, rho, p->sigma_t, p->sigma_s, p->source, cw, ghost,
+                           p->d_offA, p->d_offB, (double *)src);
     return hipGetLastError();
 }
 

@@ -48,11 +48,7 @@ struct Layout {
     int *flag;
 };
 
-int nparts_for(const rte_problem *p) {
-    int n = 0;
-    for (int q = 0; q < 4; ++q) n += (p->quad.count[q] + p->tune.dg - 1) / p->tune.dg;
-    return n;
-}
+int nparts_for(const rte_problem *p) { return sweep_nparts(p); }
 
 Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
              rte_precision prec, int max_iter) {
@@ -62,7 +58,8 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     const size_t ts = prec == RTE_MIXED ? 4 : 8;
     L.rho_star = c.take<double>(B * nd);
     L.delta = c.take<double>(B * nd);
-    L.src = c.take<char>(B * nd * ts);
+    // sweep input block: 2D two diagonal layouts of (source, sigma_t); 1D natural source
+    L.src = c.take<char>(p->dim == 2 ? B * (size_t)p->ncell * 10 * ts : B * nd * ts);
     if (p->dim == 2) L.partial = c.take<double>(B * (size_t)nparts_for(p) * nd);
     else L.fscratch = c.take<char>(B * (size_t)p->n_dir * nd * ts);
     L.st.maxd = c.take<unsigned long long>(B);
@@ -118,19 +115,25 @@ void choose_tuning(rte_problem *p, int dg_req, int wpb_req) {
     if (dg_req > 0) {
         dg = dg_req;
     } else {
-        const int cand[5] = {16, 8, 4, 2, 1};
-        for (int i = 0; i < 5; ++i) {
+        // largest group that still gives >= 4096 wavefronts (16 per CU), at most 8 directions
+        // per lane (the FP64 kernel spills beyond that)
+        const int cand[4] = {8, 4, 2, 1};
+        for (int i = 0; i < 4; ++i) {
             const int d = cand[i];
             if (d > nqmax) continue;
             long long items = 0;
             for (int q = 0; q < 4; ++q) items += (long long)p->B * ((p->quad.count[q] + d - 1) / d);
-            if (items >= 1024 || d == 1) { dg = d; break; }
+            if (items >= 4096 || d == 1) { dg = d; break; }   // items = wavefronts
         }
     }
+    // wavefronts per workgroup: as many direction groups of a quadrant as fit (<= 4)
     int wpb = wpb_req > 0 ? wpb_req : 4;
-    // LDS ring: wpb * nx * dg * 2 values of at most 8 bytes
-    while (wpb > 1 && (size_t)wpb * p->nx * dg * 2 * 8 > 64 * 1024) wpb /= 2;
-    while (dg > 1 && (size_t)wpb * p->nx * dg * 2 * 8 > 64 * 1024) dg /= 2;
+    const int groups = (nqmax + dg - 1) / dg;
+    if (wpb_req <= 0 && wpb > groups) wpb = groups < 1 ? 1 : groups;
+    // LDS: partial-sum buffers 2*wpb*64*4 doubles + rings wpb*nx*dg*2 values of <= 8 bytes
+    auto lds = [&](int w, int d) { return (size_t)2 * w * 64 * 4 * 8 + (size_t)w * p->nx * d * 2 * 8; };
+    while (wpb > 1 && lds(wpb, dg) > 64 * 1024) wpb /= 2;
+    while (dg > 1 && lds(wpb, dg) > 64 * 1024) dg /= 2;
     p->tune.dg = dg;
     p->tune.wpb = wpb;
 }
@@ -282,6 +285,7 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
     }
     p->d_dirs = nullptr;
     p->d_mu = p->d_w = p->d_widths = nullptr;
+    p->d_offA = p->d_offB = nullptr;
     // quadrant-sorted, padded direction table (2D)
     std::vector<DirEntry> table;
     for (int q = 0; q < 4; ++q) p->quad.count[q] = 0;
@@ -330,6 +334,23 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
         ok = ok && hipMalloc(&p->d_widths, sizeof(double) * p->nx) == hipSuccess;
         ok = ok && hipMemcpy(p->d_widths, p->widths.data(), sizeof(double) * p->nx, hipMemcpyHostToDevice) == hipSuccess;
     }
+    if (d->dim == 2) {
+        // diagonal offsets of the sweep layouts (cells per diagonal, prefix sums)
+        const int nd = p->nx + p->ny - 1, nx = p->nx, ny = p->ny;
+        std::vector<int> offA(nd), offB(nd);
+        int acc_a = 0, acc_b = 0;
+        for (int dd = 0; dd < nd; ++dd) {
+            offA[dd] = acc_a;
+            offB[dd] = acc_b;
+            acc_a += std::min(dd, ny - 1) - std::max(0, dd - nx + 1) + 1;
+            acc_b += std::min(ny - 1, nx + ny - 2 - dd) - std::max(0, ny - 1 - dd) + 1;
+        }
+        ok = ok && acc_a == nx * ny && acc_b == nx * ny;
+        ok = ok && hipMalloc(&p->d_offA, sizeof(int) * nd) == hipSuccess;
+        ok = ok && hipMalloc(&p->d_offB, sizeof(int) * nd) == hipSuccess;
+        ok = ok && hipMemcpy(p->d_offA, offA.data(), sizeof(int) * nd, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(p->d_offB, offB.data(), sizeof(int) * nd, hipMemcpyHostToDevice) == hipSuccess;
+    }
     if (!ok) {
         rte_problem_destroy(p);
         return RTE_EDEVICE;
@@ -344,6 +365,8 @@ void rte_problem_destroy(rte_problem *p) {
     if (p->d_w) (void)hipFree(p->d_w);
     if (p->d_mu) (void)hipFree(p->d_mu);
     if (p->d_widths) (void)hipFree(p->d_widths);
+    if (p->d_offA) (void)hipFree(p->d_offA);
+    if (p->d_offB) (void)hipFree(p->d_offB);
     delete p;
 }
 

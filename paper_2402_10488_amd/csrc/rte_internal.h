@@ -55,8 +55,58 @@ struct rte_problem {
     double *d_mu;             // 1D: device [n_dir] directions
     double *d_w;              // device [n_dir] weights (caller order)
     double *d_widths;         // 1D: device [nx]
+    int *d_offA, *d_offB;     // 2D: device [nx+ny-1] diagonal offsets of the sweep layouts
     int nparts() const;       // 2D sweep partial-sum slots per instance for the current tuning
 };
+
+namespace rte {
+// Diagonal-major cell layouts of the 2D sweep.  A wavefront of the sweep visits, at every step,
+// cells of one anti-diagonal x + y = const (quadrants (+,+), (-,-)) or of one diagonal
+// x - y = const (quadrants (-,+), (+,-)) in consecutive rows; storing the per-cell sweep inputs
+// and outputs diagonal by diagonal, row-ascending, makes those accesses contiguous.
+//   layout A: d = x + y,            row range y in [max(0, d-nx+1), min(d, ny-1)]
+//   layout B: d = x - y + ny - 1,   row range y in [max(0, ny-1-d), min(ny-1, nx+ny-2-d)]
+__device__ __forceinline__ int pos_a(const int *off, int nx, int ny, int x, int y) {
+    const int d = x + y;
+    const int ylo = d - nx + 1 > 0 ? d - nx + 1 : 0;
+    return off[d] + y - ylo;
+}
+__device__ __forceinline__ int pos_b(const int *off, int nx, int ny, int x, int y) {
+    const int d = x - y + ny - 1;
+    const int ylo = ny - 1 - d > 0 ? ny - 1 - d : 0;
+    return off[d] + y - ylo;
+}
+// quadrant q = (vx<0) | 2 (vy<0): q = 0, 3 sweep anti-diagonals (layout A), q = 1, 2 diagonals (B)
+__device__ __forceinline__ bool quad_uses_a(int q) { return q == 0 || q == 3; }
+
+template <typename T>
+struct Vec4 { T x, y, z, w; };
+
+// sweep input block from rho (2D: both diagonal layouts and sigma_t; 1D: natural order)
+template <typename T>
+__device__ __forceinline__ void write_sweep_input(int dim, long long ncell, int B, int b, int nx,
+                                                  int ny, long long cell, const int *offA,
+                                                  const int *offB, const double v[4], double st,
+                                                  T *src) {
+    if (dim == 1) {
+        T *o = src + ((size_t)b * ncell + cell) * 2;
+        o[0] = (T)v[0];
+        o[1] = (T)v[1];
+        return;
+    }
+    const int x = (int)(cell % nx), y = (int)(cell / nx);
+    const size_t nb4 = (size_t)B * ncell * 4;
+    const size_t pa = (size_t)b * ncell + pos_a(offA, nx, ny, x, y);
+    const size_t pb = (size_t)b * ncell + pos_b(offB, nx, ny, x, y);
+    Vec4<T> o;
+    o.x = (T)v[0]; o.y = (T)v[1]; o.z = (T)v[2]; o.w = (T)v[3];
+    *reinterpret_cast<Vec4<T> *>(src + pa * 4) = o;
+    *reinterpret_cast<Vec4<T> *>(src + nb4 + pb * 4) = o;
+    src[2 * nb4 + pa] = (T)st;
+    src[2 * nb4 + (size_t)B * ncell + pb] = (T)st;
+}
+
+}  // namespace rte
 
 struct rte_rom {
     int r, m;
@@ -75,9 +125,13 @@ struct rte_rom {
 // ---------------------------------------------------------------------------------------------
 namespace rte {
 
+// 2D sweep input block (one allocation, T = float or double):
+//   srcA [B][ncell][4], srcB [B][ncell][4]  sigma_s rho + G sqrt(hx hy) delta_k0 in layouts A, B
+//   sigA [B][ncell],    sigB [B][ncell]     sigma_t in layouts A, B
+// 1D: src [B][ncell][2] in natural order.
 struct SweepLaunch {
     const rte_problem *p;
-    const void *src;          // [B][ndof] T: sigma_s rho + G sqrt(hx hy) delta_k0 (2D)
+    const void *src;          // sweep input block (see above)
     double *partial;          // [B][nparts][ndof] or nullptr
     void *f_out;              // [B][n_dir][ndof] T or nullptr
     const int *active;        // [B] or nullptr
@@ -85,12 +139,15 @@ struct SweepLaunch {
     int fp32;
 };
 hipError_t launch_sweep2d(const SweepLaunch &a, hipStream_t s);
+// wavefronts per sweep workgroup (direction groups summed in LDS) and partial slots per instance
+int sweep_waves(const rte_problem *p);
+int sweep_nparts(const rte_problem *p);
 
 // 1D sweep: writes f (always, T) to f_out [B][n_dir][ndof]; src as in 2D (K = 2).
 hipError_t launch_sweep1d(const rte_problem *p, const void *src, void *f_out, const int *active,
                           int zero_inflow, int fp32, hipStream_t s);
 
-// src = sigma_s rho + G * (cell integral of phi_0); written as T
+// sweep input block from rho: src = sigma_s rho + G * (cell integral of phi_0), plus sigma_t
 hipError_t launch_source(const rte_problem *p, const double *rho, void *src, const int *active,
                          int fp32, hipStream_t s);
 

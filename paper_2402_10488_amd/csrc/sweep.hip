@@ -24,18 +24,16 @@ namespace {
 
 constexpr double kS3 = 1.7320508075688772935;
 
-template <typename T>
-struct Vec4 { T x, y, z, w; };
-
 struct Sweep2DArgs {
     int nx, ny, B, nbands, P, n_dir, nparts;
-    int gq[4];
-    int qstart[4];
+    int gq[4];       // workgroups (blocks of W direction groups) per quadrant
+    int qstart[4];   // first entry of each quadrant in the sorted direction table
+    int qpad[4];     // padded table length of each quadrant
     long long ncell;
     double ghost;            // sqrt(hx hy): coefficient of a unit constant on phi_0
     int zero_inflow;
     const DirEntry *dirs;
-    const double *sigma_t;
+    const int *offA, *offB;  // diagonal offsets of the two sweep layouts
     const void *src;
     const double *inflow;
     double *partial;
@@ -43,151 +41,286 @@ struct Sweep2DArgs {
     const int *active;
 };
 
-// Q1 cell solve in reflected coordinates; unknown order k = a + 2b: (f00, f10, f01, f11).
+__device__ __forceinline__ float recip(float x);
+__device__ __forceinline__ double recip(double x);
+
+// Per-direction constants of the Q1 cell solve in reflected coordinates (a = |vx|/hx,
+// b = |vy|/hy); with p = b + sigma and q = 3b + sigma the Schur-complement coefficients are
+//   u = a (4a + p + q) = 4a(a + b) + 2a sigma,   w = p q + 3b^2 - 6a^2 = sigma (sigma + 4b) + 6(b^2 - a^2)
+// so every cell-dependent quantity is one or two fused operations on sigma.
 template <typename T>
-__device__ __forceinline__ void q1_solve(T al, T be, T sig, T r0, T r1, T r2, T r3, T &f0, T &f1,
-                                         T &f2, T &f3) {
+struct DirConst {
+    T al, be, ca, cb;       // a, b, s3 a, s3 b
+    T k1, k2, k3, be4;      // 4a(a+b), 2a, 6(b^2-a^2), 4b
+    T txc, twoal2;          // b + 2a, 2a^2
+    T x00c, x11c;           // a + b, 3a + b
+};
+
+template <typename T>
+__device__ __forceinline__ DirConst<T> dir_const(double a, double b) {
+    DirConst<T> d;
+    d.al = (T)a;
+    d.be = (T)b;
+    d.ca = (T)(kS3 * a);
+    d.cb = (T)(kS3 * b);
+    d.k1 = (T)(4.0 * a * (a + b));
+    d.k2 = (T)(2.0 * a);
+    d.k3 = (T)(6.0 * (b * b - a * a));
+    d.be4 = (T)(4.0 * b);
+    d.txc = (T)(b + 2.0 * a);
+    d.twoal2 = (T)(2.0 * a * a);
+    d.x00c = (T)(a + b);
+    d.x11c = (T)(3.0 * a + b);
+    return d;
+}
+
+// Q1 cell solve in reflected coordinates; unknown order k = a + 2b: (f00, f10, f01, f11).
+// Block elimination with X = aA + pI, Y = aA + qI (A = [[1, s3], [-s3, 3]], A^2 = 4A - 6I):
+//   (X Y + 3b^2 I) F1 = X R1 + s3 b R0  with  X Y + 3b^2 I = uA + wI,   F0 = X^{-1}(R0 - s3 b F1)
+template <typename T>
+__device__ __forceinline__ void q1_solve(const DirConst<T> &d, T sig, T r0, T r1, T r2, T r3,
+                                         T &f0, T &f1, T &f2, T &f3) {
     const T c = T(kS3);
-    const T p = be + sig;
-    const T q = T(3) * be + sig;
-    const T u = al * (T(4) * al + p + q);
-    const T w = p * q + T(3) * be * be - T(6) * al * al;
-    const T tm = w + T(2) * u;
-    const T detM = tm * tm + T(2) * u * u;          // det(uA + wI) = (w+2u)^2 + 2u^2 > 0
-    const T tx = p + T(2) * al;
-    const T detX = tx * tx + T(2) * al * al;        // det(X) = (p+2a)^2 + 2a^2 > 0
-    const T inv = T(1) / (detM * detX);
+    const T u = d.k2 * sig + d.k1;
+    const T w = sig * (sig + d.be4) + d.k3;
+    const T tm = T(2) * u + w;
+    const T detM = tm * tm + (u + u) * u;           // det(uA + wI) = (w+2u)^2 + 2u^2 > 0
+    const T tx = sig + d.txc;
+    const T detX = tx * tx + d.twoal2;              // det(X) = (p+2a)^2 + 2a^2 > 0
+    const T inv = recip(detM * detX);
     const T iM = detX * inv;
     const T iX = detM * inv;
-    const T ca = c * al, cb = c * be, cu = c * u;
-    // right-hand side of the Schur system: X R1 + c b R0
-    const T g0 = (al + p) * r2 + ca * r3 + cb * r0;
-    const T g1 = -ca * r2 + (T(3) * al + p) * r3 + cb * r1;
+    const T x00 = sig + d.x00c;                     // a + p
+    const T x11 = sig + d.x11c;                     // 3a + p
+    const T g0 = x00 * r2 + (d.ca * r3 + d.cb * r0);
+    const T g1 = x11 * r3 + (d.cb * r1 - d.ca * r2);
+    const T cu = c * u;
     f2 = ((T(3) * u + w) * g0 - cu * g1) * iM;
     f3 = (cu * g0 + (u + w) * g1) * iM;
-    const T h0 = r0 - cb * f2;
-    const T h1 = r1 - cb * f3;
-    f0 = ((T(3) * al + p) * h0 - ca * h1) * iX;
-    f1 = (ca * h0 + (al + p) * h1) * iX;
+    const T h0 = r0 - d.cb * f2;
+    const T h1 = r1 - d.cb * f3;
+    f0 = (x11 * h0 - d.ca * h1) * iX;
+    f1 = (d.ca * h0 + x00 * h1) * iX;
 }
 
+// wave-uniform value (all lanes hold the same number) moved to a scalar register
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uni(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 template <typename T>
-__device__ __forceinline__ T shfl_up1(T v) {
-    return __shfl_up(v, 1, 64);
+__device__ __forceinline__ DirConst<T> uni(DirConst<T> d) {
+    d.al = uni(d.al); d.be = uni(d.be); d.ca = uni(d.ca); d.cb = uni(d.cb);
+    d.k1 = uni(d.k1); d.k2 = uni(d.k2); d.k3 = uni(d.k3); d.be4 = uni(d.be4);
+    d.txc = uni(d.txc); d.twoal2 = uni(d.twoal2); d.x00c = uni(d.x00c); d.x11c = uni(d.x11c);
+    return d;
 }
 
-template <typename T, int DG>
+// Cross-lane move "lane j receives lane j-1" as a DPP whole-wave shift (wave_shr:1); lane 0
+// keeps its own value (it is overwritten by the caller).
+__device__ __forceinline__ float shfl_up1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138,
+                                                      0xf, 0xf, false));
+}
+__device__ __forceinline__ double shfl_up1(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
+}
+
+// reciprocal: hardware estimate refined by one Newton step (FP32), two steps (FP64)
+__device__ __forceinline__ float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return r * (2.0f - x * r);
+}
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * (2.0 - x * r);
+    return r * (2.0 - x * r);
+}
+
+// One workgroup = W wavefronts = W consecutive direction groups of one (instance, quadrant).
+// The wavefronts walk the same pipeline in lockstep (one barrier per step), so at every step
+// lane j of every wavefront is at the same cell; their FP64 partial densities are summed in
+// LDS in a fixed order and one partial per (instance, quadrant block) is written.
+template <typename T, int DG, bool WF>
 __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ double smem_d[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    const long long item = (long long)blockIdx.x * wpb + wv;
-    if (item >= (long long)a.B * a.nparts) return;           // whole wavefront leaves
-    const int b = (int)(item / a.nparts);
-    const int gpart = (int)(item - (long long)b * a.nparts);
+    const int W = blockDim.x >> 6;
+    const int item = blockIdx.x;                              // (instance, quadrant block)
+    if (item >= a.B * a.nparts) return;                       // whole workgroup leaves
+    const int b = item / a.nparts;
+    const int gpart = item - b * a.nparts;
     if (a.active && a.active[b] == 0) return;
     int part = gpart, q = 0;
     while (q < 3 && part >= a.gq[q]) { part -= a.gq[q]; ++q; }
-    const int d0 = a.qstart[q] + part * DG;
+    const int g = part * W + wv;                              // direction group of this wave
+    const int d0 = a.qstart[q] + g * DG;
+    const int dend = a.qstart[q] + a.qpad[q];                 // end of this quadrant's table
     const bool rx = (q & 1) != 0, ry = (q & 2) != 0;
-    T *ring = reinterpret_cast<T *>(smem_raw) + (size_t)wv * a.nx * DG * 2;
+    // LDS: [2][W][64][4] doubles of partial densities (double buffered by step parity), then
+    // the W rings of y-traces handed from lane 63 to lane 0 of the next band
+    double *red = smem_d;
+    T *ring = reinterpret_cast<T *>(smem_d + 2 * W * 64 * 4) + (size_t)wv * a.nx * DG * 2;
 
-    T al[DG], be[DG];
-    double wt[DG];
+    DirConst<T> dc[DG];
+    T wt[DG];
     int orig[DG];
+    const T c = T(kS3);
 #pragma unroll
     for (int d = 0; d < DG; ++d) {
-        const DirEntry e = a.dirs[d0 + d];
-        al[d] = (T)e.alpha;
-        be[d] = (T)e.beta;
-        wt[d] = e.w;
-        orig[d] = e.orig;
+        DirEntry e;
+        if (d0 + d < dend) e = a.dirs[d0 + d];
+        else { e.alpha = 1.0; e.beta = 1.0; e.w = 0.0; e.orig = -1; e.pad = 0; }
+        dc[d] = uni(dir_const<T>(e.alpha, e.beta));
+        wt[d] = uni((T)e.w);
+        orig[d] = __builtin_amdgcn_readfirstlane(e.orig);
     }
     const T gx = a.zero_inflow ? T(0) : (T)(a.inflow[4 * b + (rx ? 1 : 0)] * a.ghost);
     const T gy = a.zero_inflow ? T(0) : (T)(a.inflow[4 * b + (ry ? 3 : 2)] * a.ghost);
     const T sx = rx ? T(-1) : T(1), sy = ry ? T(-1) : T(1);
     const double dsx = rx ? -1.0 : 1.0, dsy = ry ? -1.0 : 1.0;
-    const T c = T(kS3);
 
-    const T *src = reinterpret_cast<const T *>(a.src) + (size_t)b * a.ncell * 4;
-    const double *sig_t = a.sigma_t + (size_t)b * a.ncell;
+    // this quadrant's layout of the sweep inputs (see SweepLaunch)
+    const bool la = quad_uses_a(q);
+    const int *off = la ? a.offA : a.offB;
+    const size_t nb4 = (size_t)a.B * a.ncell * 4;
+    const T *base = reinterpret_cast<const T *>(a.src);
+    const T *src = base + (la ? 0 : nb4) + (size_t)b * a.ncell * 4;
+    const T *sig_t = base + 2 * nb4 + (la ? 0 : (size_t)a.B * a.ncell) + (size_t)b * a.ncell;
     double *part_out = a.partial ? a.partial + ((size_t)b * a.nparts + gpart) * a.ncell * 4 : nullptr;
-    T *fout = a.f_out ? reinterpret_cast<T *>(a.f_out) + (size_t)b * a.n_dir * a.ncell * 4 : nullptr;
+    T *fout = WF ? reinterpret_cast<T *>(a.f_out) + (size_t)b * a.n_dir * a.ncell * 4 : nullptr;
 
     T tx0[DG], tx1[DG], ty0[DG], ty1[DG];
 #pragma unroll
     for (int d = 0; d < DG; ++d) { tx0[d] = tx1[d] = ty0[d] = ty1[d] = T(0); }
 
-    const long long total = (long long)a.nbands * a.P + 63;
-    for (long long t = 0; t < total; ++t) {
+    // lane position in the pipeline: band k, column i (k P + i = t - lane), tracked
+    // incrementally so the loop carries no division
+    const int P = a.P, nx = a.nx, ny = a.ny, nb = a.nbands;
+    int k = 0, i = -lane;
+    // natural cell index (for f) and position in the diagonal layout (inputs, partials)
+    auto cell_of = [&](int kk, int ii, bool &ok, int &pos) -> int {
+        const int jr = kk * 64 + lane;
+        ok = ii >= 0 && kk < nb && ii < nx && jr < ny;
+        const int ip = rx ? nx - 1 - ii : ii;
+        const int jp = ry ? ny - 1 - jr : jr;
+        pos = ok ? (la ? pos_a(off, nx, ny, ip, jp) : pos_b(off, nx, ny, ip, jp)) : 0;
+        return ok ? jp * nx + ip : 0;
+    };
+    bool ok_cur;
+    int pos_cur;
+    int cell_cur = cell_of(k, i, ok_cur, pos_cur);
+    Vec4<T> sv_cur = {T(0), T(0), T(0), T(0)};
+    T sg_cur = T(0);
+    if (ok_cur) {
+        sv_cur = *reinterpret_cast<const Vec4<T> *>(src + (size_t)pos_cur * 4);
+        sg_cur = sig_t[pos_cur];
+    }
+    const int total = nb * P + 63;
+    for (int t = 0; t < total; ++t) {
         T yi0[DG], yi1[DG];
 #pragma unroll
-        for (int d = 0; d < DG; ++d) {               // all lanes take part in the shuffle
+        for (int d = 0; d < DG; ++d) {               // all lanes take part in the shift
             yi0[d] = shfl_up1(ty0[d]);
             yi1[d] = shfl_up1(ty1[d]);
         }
-        const long long u = t - lane;
-        if (u < 0) continue;
-        const int k = (int)(u / a.P);
-        const int i = (int)(u - (long long)k * a.P);
-        const int jr = k * 64 + lane;
-        if (k >= a.nbands || i >= a.nx || jr >= a.ny) continue;
-        if (lane == 0) {
-#pragma unroll
-            for (int d = 0; d < DG; ++d) {
-                if (k == 0) { yi0[d] = gy; yi1[d] = T(0); }
-                else { yi0[d] = ring[(i * DG + d) * 2]; yi1[d] = ring[(i * DG + d) * 2 + 1]; }
-            }
+        // next position and prefetch of its cell data (overlaps this step's arithmetic)
+        int kn = k, in_ = i + 1;
+        if (in_ == P) { in_ = 0; ++kn; }
+        bool ok_next;
+        int pos_next;
+        const int cell_next = cell_of(kn, in_, ok_next, pos_next);
+        Vec4<T> sv_next = {T(0), T(0), T(0), T(0)};
+        T sg_next = T(0);
+        if (ok_next) {
+            sv_next = *reinterpret_cast<const Vec4<T> *>(src + (size_t)pos_next * 4);
+            sg_next = sig_t[pos_next];
         }
-        if (i == 0) {
-#pragma unroll
-            for (int d = 0; d < DG; ++d) { tx0[d] = gx; tx1[d] = T(0); }
-        }
-        const int ip = rx ? a.nx - 1 - i : i;
-        const int jp = ry ? a.ny - 1 - jr : jr;
-        const long long cell = (long long)jp * a.nx + ip;
-        const Vec4<T> sv = *reinterpret_cast<const Vec4<T> *>(src + cell * 4);
-        const T s0 = sv.x, s1 = sx * sv.y, s2 = sy * sv.z, s3 = sx * sy * sv.w;
-        const T sig = (T)sig_t[cell];
+        // the lane's DG directions are summed in T, the groups and quadrants in FP64
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        if (ok_cur) {
+            if (lane == 0) {
 #pragma unroll
-        for (int d = 0; d < DG; ++d) {
-            const T ca = c * al[d], cb = c * be[d];
-            const T r0 = s0 + al[d] * tx0[d] + be[d] * yi0[d];
-            const T r1 = s1 - ca * tx0[d] + be[d] * yi1[d];
-            const T r2 = s2 + al[d] * tx1[d] - cb * yi0[d];
-            const T r3 = s3 - ca * tx1[d] - cb * yi1[d];
-            T f0, f1, f2, f3;
-            q1_solve<T>(al[d], be[d], sig, r0, r1, r2, r3, f0, f1, f2, f3);
-            tx0[d] = f0 + c * f1;
-            tx1[d] = f2 + c * f3;
-            ty0[d] = f0 + c * f2;
-            ty1[d] = f1 + c * f3;
-            acc0 += wt[d] * (double)f0;
-            acc1 += wt[d] * (double)f1;
-            acc2 += wt[d] * (double)f2;
-            acc3 += wt[d] * (double)f3;
-            if (fout && orig[d] >= 0) {
-                Vec4<T> o;
-                o.x = f0; o.y = sx * f1; o.z = sy * f2; o.w = sx * sy * f3;
-                *reinterpret_cast<Vec4<T> *>(fout + ((size_t)orig[d] * a.ncell + cell) * 4) = o;
+                for (int d = 0; d < DG; ++d) {
+                    if (k == 0) { yi0[d] = gy; yi1[d] = T(0); }
+                    else { yi0[d] = ring[(i * DG + d) * 2]; yi1[d] = ring[(i * DG + d) * 2 + 1]; }
+                }
             }
-        }
-        if (lane == 63) {
+            if (i == 0) {
+#pragma unroll
+                for (int d = 0; d < DG; ++d) { tx0[d] = gx; tx1[d] = T(0); }
+            }
+            const T s0 = sv_cur.x, s1 = sx * sv_cur.y, s2 = sy * sv_cur.z, s3 = sx * sy * sv_cur.w;
+            const T sig = sg_cur;
+            T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
-                ring[(i * DG + d) * 2] = ty0[d];
-                ring[(i * DG + d) * 2 + 1] = ty1[d];
+                const T r0 = s0 + dc[d].al * tx0[d] + dc[d].be * yi0[d];
+                const T r1 = s1 - dc[d].ca * tx0[d] + dc[d].be * yi1[d];
+                const T r2 = s2 + dc[d].al * tx1[d] - dc[d].cb * yi0[d];
+                const T r3 = s3 - dc[d].ca * tx1[d] - dc[d].cb * yi1[d];
+                T f0, f1, f2, f3;
+                q1_solve<T>(dc[d], sig, r0, r1, r2, r3, f0, f1, f2, f3);
+                tx0[d] = f0 + c * f1;
+                tx1[d] = f2 + c * f3;
+                ty0[d] = f0 + c * f2;
+                ty1[d] = f1 + c * f3;
+                a0 += wt[d] * f0;
+                a1 += wt[d] * f1;
+                a2 += wt[d] * f2;
+                a3 += wt[d] * f3;
+                if (WF && orig[d] >= 0) {
+                    Vec4<T> o;
+                    o.x = f0; o.y = sx * f1; o.z = sy * f2; o.w = sx * sy * f3;
+                    *reinterpret_cast<Vec4<T> *>(fout + ((size_t)orig[d] * a.ncell + cell_cur) * 4) = o;
+                }
             }
+            if (lane == 63) {
+#pragma unroll
+                for (int d = 0; d < DG; ++d) {
+                    ring[(i * DG + d) * 2] = ty0[d];
+                    ring[(i * DG + d) * 2 + 1] = ty1[d];
+                }
+            }
+            acc0 = (double)a0;
+            acc1 = (double)a1;
+            acc2 = (double)a2;
+            acc3 = (double)a3;
         }
         if (part_out) {
-            double *o = part_out + cell * 4;
-            o[0] = acc0;
-            o[1] = dsx * acc1;
-            o[2] = dsy * acc2;
-            o[3] = dsx * dsy * acc3;
+            // sum the W wavefronts' partials of this cell in LDS (fixed order), one writer
+            double *slot = red + (size_t)(t & 1) * W * 64 * 4;
+            double4 v;
+            v.x = acc0; v.y = acc1; v.z = acc2; v.w = acc3;
+            *reinterpret_cast<double4 *>(slot + ((size_t)wv * 64 + lane) * 4) = v;
+            __syncthreads();
+            if (wv == 0 && ok_cur) {
+                double4 sum = *reinterpret_cast<const double4 *>(slot + (size_t)lane * 4);
+                for (int w2 = 1; w2 < W; ++w2) {
+                    const double4 o = *reinterpret_cast<const double4 *>(slot + ((size_t)w2 * 64 + lane) * 4);
+                    sum.x += o.x; sum.y += o.y; sum.z += o.z; sum.w += o.w;
+                }
+                sum.y *= dsx; sum.z *= dsy; sum.w *= dsx * dsy;
+                *reinterpret_cast<double4 *>(part_out + (size_t)pos_cur * 4) = sum;
+            }
         }
+        k = kn;
+        i = in_;
+        ok_cur = ok_next;
+        cell_cur = cell_next;
+        pos_cur = pos_next;
+        sv_cur = sv_next;
+        sg_cur = sg_next;
     }
 }
 
@@ -230,9 +363,10 @@ __global__ void __launch_bounds__(256) sweep1d_kernel(int nc, int n_dir, int B, 
 
 // ------------------------------------------------------------------ source, reductions
 template <typename T>
-__global__ void source_kernel(long long ncell, int K, int B, const double *rho,
-                              const double *sigma_s, const double *G, const double *cellw,
-                              double ghost, T *src, const int *active) {
+__global__ void source_kernel(int dim, long long ncell, int K, int B, int nx, int ny,
+                              const double *rho, const double *sigma_t, const double *sigma_s,
+                              const double *G, const double *cellw, double ghost, const int *offA,
+                              const int *offB, T *src, const int *active) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)B * ncell) return;
     const int b = (int)(t / ncell);
@@ -240,10 +374,9 @@ __global__ void source_kernel(long long ncell, int K, int B, const double *rho,
     const long long cell = t - (long long)b * ncell;
     const double ss = sigma_s[t];
     const double g0 = G[t] * (cellw ? sqrt(cellw[cell]) : ghost);
-    for (int k = 0; k < K; ++k) {
-        const double v = ss * rho[t * K + k] + (k == 0 ? g0 : 0.0);
-        src[t * K + k] = (T)v;
-    }
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < K; ++k) v[k] = ss * rho[t * K + k] + (k == 0 ? g0 : 0.0);
+    write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, offA, offB, v, sigma_t[t], src);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -257,21 +390,44 @@ __device__ __forceinline__ void max_update(unsigned long long *dst, double v) {
     if ((threadIdx.x & 63) == 0 && v > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ void reduce_parts_kernel(long long ndof, int B, int nparts, const double *partial,
-                                    double *rho_star, const double *rho_prev,
-                                    unsigned long long *maxd, unsigned long long *maxr,
-                                    const int *active) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// rho* of one cell (4 dofs) = sum of the partial densities of every quadrant block, each read
+// from its quadrant's diagonal layout, in fixed order
+struct ReduceArgs {
+    long long ncell;
+    int B, nx, ny, nparts;
+    int gq[4];
+    const int *offA, *offB;
+};
+
+__global__ void reduce_parts_kernel(ReduceArgs a, const double *partial, double *rho_star,
+                                    const double *rho_prev, unsigned long long *maxd,
+                                    unsigned long long *maxr, const int *active) {
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int b = (int)(blockIdx.y);
     double d = 0.0, m = 0.0;
-    const bool live = t < ndof && (!active || active[b] != 0);
+    const bool live = cell < a.ncell && (!active || active[b] != 0);
     if (live) {
-        const double *p = partial + (size_t)b * nparts * ndof + t;
-        double s = 0.0;
-        for (int k = 0; k < nparts; ++k) s += p[(size_t)k * ndof];
-        rho_star[(size_t)b * ndof + t] = s;
-        m = fabs(s);
-        if (rho_prev) d = fabs(s - rho_prev[(size_t)b * ndof + t]);
+        const int x = (int)(cell % a.nx), y = (int)(cell / a.nx);
+        const size_t pa = (size_t)pos_a(a.offA, a.nx, a.ny, x, y);
+        const size_t pb = (size_t)pos_b(a.offB, a.nx, a.ny, x, y);
+        const double *base = partial + (size_t)b * a.nparts * a.ncell * 4;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int part = 0;
+        for (int q = 0; q < 4; ++q) {
+            const size_t pos = quad_uses_a(q) ? pa : pb;
+            for (int g = 0; g < a.gq[q]; ++g, ++part) {
+                const double4 v = *reinterpret_cast<const double4 *>(base + ((size_t)part * a.ncell + pos) * 4);
+                s0 += v.x; s1 += v.y; s2 += v.z; s3 += v.w;
+            }
+        }
+        double4 o;
+        o.x = s0; o.y = s1; o.z = s2; o.w = s3;
+        const size_t gi = ((size_t)b * a.ncell + cell) * 4;
+        *reinterpret_cast<double4 *>(rho_star + gi) = o;
+        m = fmax(fmax(fabs(s0), fabs(s1)), fmax(fabs(s2), fabs(s3)));
+        if (rho_prev)
+            d = fmax(fmax(fabs(s0 - rho_prev[gi]), fabs(s1 - rho_prev[gi + 1])),
+                     fmax(fabs(s2 - rho_prev[gi + 2]), fabs(s3 - rho_prev[gi + 3])));
     }
     if (maxd) max_update(maxd + b, d);
     if (maxr) max_update(maxr + b, m);
@@ -316,27 +472,32 @@ hipError_t sweep2d_launch_t(const SweepLaunch &L, hipStream_t s) {
     a.nbands = (p->ny + 63) / 64;
     a.P = p->nx > 64 ? p->nx : 64;
     a.n_dir = p->n_dir;
+    const int W = sweep_waves(p);
     a.nparts = 0;
     for (int q = 0; q < 4; ++q) {
-        a.gq[q] = (p->quad.count[q] + DG - 1) / DG;
+        const int groups = (p->quad.count[q] + DG - 1) / DG;
+        a.gq[q] = (groups + W - 1) / W;
         a.qstart[q] = p->quad.start[q];
+        a.qpad[q] = (p->quad.count[q] + kQuadPad - 1) / kQuadPad * kQuadPad;
         a.nparts += a.gq[q];
     }
     a.ncell = p->ncell;
     a.ghost = sqrt(p->hx * p->hy);
     a.zero_inflow = L.zero_inflow;
     a.dirs = p->d_dirs;
-    a.sigma_t = p->sigma_t;
+    a.offA = p->d_offA;
+    a.offB = p->d_offB;
     a.src = L.src;
     a.inflow = p->inflow;
     a.partial = L.partial;
     a.f_out = L.f_out;
     a.active = L.active;
-    const int wpb = p->tune.wpb;
-    const long long items = (long long)a.B * a.nparts;
-    const unsigned grid = (unsigned)((items + wpb - 1) / wpb);
-    const size_t lds = (size_t)wpb * p->nx * DG * 2 * sizeof(T);
-    hipLaunchKernelGGL((sweep2d_kernel<T, DG>), dim3(grid), dim3(64 * wpb), lds, s, a);
+    const unsigned grid = (unsigned)((long long)a.B * a.nparts);
+    const size_t lds = (size_t)2 * W * 64 * 4 * sizeof(double) + (size_t)W * p->nx * DG * 2 * sizeof(T);
+    if (L.f_out)
+        hipLaunchKernelGGL((sweep2d_kernel<T, DG, true>), dim3(grid), dim3(64 * W), lds, s, a);
+    else
+        hipLaunchKernelGGL((sweep2d_kernel<T, DG, false>), dim3(grid), dim3(64 * W), lds, s, a);
     return hipGetLastError();
 }
 
@@ -380,11 +541,13 @@ hipError_t launch_source(const rte_problem *p, const double *rho, void *src, con
     const double ghost = sqrt(p->hx * p->hy);
     const double *cw = p->dim == 1 ? p->d_widths : nullptr;
     if (fp32)
-        hipLaunchKernelGGL(source_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->ncell,
-                           p->K, p->B, rho, p->sigma_s, p->source, cw, ghost, (float *)src, active);
+        hipLaunchKernelGGL(source_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->dim,
+                           p->ncell, p->K, p->B, p->nx, p->ny, rho, p->sigma_t, p->sigma_s,
+                           p->source, cw, ghost, p->d_offA, p->d_offB, (float *)src, active);
     else
         hipLaunchKernelGGL(source_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                           p->ncell, p->K, p->B, rho, p->sigma_s, p->source, cw, ghost,
+                           p->dim, p->ncell, p->K, p->B, p->nx, p->ny, rho, p->sigma_t,
+                           p->sigma_s, p->source, cw, ghost, p->d_offA, p->d_offB,
                            (double *)src, active);
     return hipGetLastError();
 }
@@ -392,9 +555,19 @@ hipError_t launch_source(const rte_problem *p, const double *rho, void *src, con
 hipError_t launch_reduce_parts(const rte_problem *p, const double *partial, int nparts,
                                double *rho_star, const double *rho_prev, unsigned long long *maxd,
                                unsigned long long *maxr, const int *active, hipStream_t s) {
-    dim3 grid(blocks_for(p->ndof, 256), p->B);
-    hipLaunchKernelGGL(reduce_parts_kernel, grid, dim3(256), 0, s, p->ndof, p->B, nparts, partial,
-                       rho_star, rho_prev, maxd, maxr, active);
+    ReduceArgs a;
+    a.ncell = p->ncell;
+    a.B = p->B;
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nparts = nparts;
+    const int W = p->tune.wpb, DG = p->tune.dg;
+    for (int q = 0; q < 4; ++q) a.gq[q] = ((p->quad.count[q] + DG - 1) / DG + W - 1) / W;
+    a.offA = p->d_offA;
+    a.offB = p->d_offB;
+    dim3 grid(blocks_for(p->ncell, 256), p->B);
+    hipLaunchKernelGGL(reduce_parts_kernel, grid, dim3(256), 0, s, a, partial, rho_star, rho_prev,
+                       maxd, maxr, active);
     return hipGetLastError();
 }
 
@@ -418,4 +591,17 @@ hipError_t launch_check_materials(const rte_problem *p, int *bad, hipStream_t s)
     return hipGetLastError();
 }
 
+}  // namespace rte
+
+namespace rte {
+int sweep_waves(const rte_problem *p) { return p->tune.wpb; }
+int sweep_nparts(const rte_problem *p) {
+    const int W = p->tune.wpb, DG = p->tune.dg;
+    int n = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int groups = (p->quad.count[q] + DG - 1) / DG;
+        n += (groups + W - 1) / W;
+    }
+    return n;
+}
 }  // namespace rte
