@@ -97,6 +97,12 @@ void rte_problem_destroy(rte_problem *p);
  * partial-density order. */
 int rte_problem_create_tuned(const rte_problem_desc *desc, int dg, int wpb, rte_problem **out);
 
+/* Selects the preconditioner of the 2D diffusion CG: on != 0 (default) the two-level
+ * multigrid (block-Jacobi smoothing on the DG space, continuous-Q1 vertex-grid coarse space with
+ * Galerkin operators, one V-cycle); on == 0 block-Jacobi alone.  Changes the workspace size; call
+ * before sizing the workspace and not concurrently with other calls on the handle. */
+int rte_problem_dsa_multigrid(rte_problem *p, int on);
+
 /* Reports the schedule in use: directions per lane, wavefronts per workgroup and the number of
  * per-instance partial densities the 2D sweep produces. */
 int rte_problem_tuning(const rte_problem *p, int *dg, int *wpb, int *nparts);
@@ -196,6 +202,45 @@ typedef struct {
 int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
                    const rte_solve_opts *opts, double *rho_inout, void *f_out,
                    rte_solve_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Offline construction of the correction ROM (Sec. 3.1 POD, Sec. 3.2.1 snapshots, Sec. 3.1.1
+ * reduced affine operators).  Building blocks driven by the Python offline builder; all FP64.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Snapshot columns delta f = f_final - f_iter per instance (Sec. 3.2.1); f_iter == NULL stands
+ * for the zero initial state.  f_final, f_iter: device [B][n_dir][N_DOF];
+ * column b is written at cols + b * stride (stride >= n_dir * N_DOF). */
+int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double *f_iter,
+                      double *cols, long long stride, rte_stream_t stream);
+
+/* G = X^T Y for column-major X [nx][len], Y [ny][len] (device), G [nx][ny] device, on the matrix
+ * cores.  With cell_class != NULL only rows whose cell ((row / K) mod ncell) has class cls are
+ * summed (the material-class restriction of the reduced affine operators).  ws: device
+ * scratch for the split partial sums (ENOMEM if too small for one split). */
+int rte_gram(const double *X, int nx, const double *Y, int ny, long long len,
+             const int *cell_class, int K, long long ncell, int cls, double *G, void *ws,
+             size_t ws_bytes, rte_stream_t stream);
+
+/* Eigen-decomposition of a symmetric n x n device matrix A (n <= 256, overwritten) by cyclic
+ * Jacobi: evals [n] (unsorted), evecs [n][n] with eigenvectors as columns (method of snapshots,
+ * Sec. 3.1: F^T F = V Lambda^2 V^T). */
+int rte_sym_eig(double *A, int n, double *evals, double *evecs, rte_stream_t stream);
+
+/* out[c] = sum_col W[col][c] X[col] for X [ncol][len], W [ncol][r], out [r][len] (device), on
+ * the matrix cores (the basis U = F V Lambda^-1 of the method of snapshots). */
+int rte_combine(const double *X, int ncol, long long len, const double *W, int r, double *out,
+                rte_stream_t stream);
+
+/* y_j = D_j x_j of eq. (dg_matrix_vec) (streaming + upwind flux, no boundary load) for nvec
+ * vectors x, y [nvec][n_dir][N_DOF] (2D). */
+int rte_apply_streaming(const rte_problem *p, const double *x, int nvec, double *y,
+                        rte_stream_t stream);
+
+/* out[v] = sum_j w_j x[v][j] (weighted != 0) or sum_j x[v][j] (weighted == 0) for
+ * x [nvec][n_dir][N_DOF], out [nvec][N_DOF]: U^rho and U^iso of eq. (rho_basis). */
+int rte_direction_sum(const rte_problem *p, const double *x, int nvec, int weighted, double *out,
+                      rte_stream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around every launch of the
  * named kernel group (process-wide; not for concurrent use from several threads).

@@ -30,6 +30,7 @@ namespace {
 constexpr double kS3 = 1.7320508075688772935;
 constexpr double kMipC = 4.0;
 constexpr int kCgBlock = 256;
+constexpr double kOmegaDG = 0.7;      // damping of the block-Jacobi smoother of the multigrid
 
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -369,7 +370,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
                                                             const double *rho_prev, const int *kind,
                                                             int want, double *x, double *r,
                                                             double *z, double *part, int *state,
-                                                            int *iters, int *n_running) {
+                                                            int *iters, int *n_running, int bj) {
     const int b = blockIdx.y;
     const bool mine = !kind || kind[b] == want;
     if (!mine) {
@@ -385,14 +386,19 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
         load4(rho_star, gi, rs);
         load4(rho_prev, gi, rp);
         for (int k = 0; k < 4; ++k) rv[k] = ss * (rs[k] - rp[k]);
-        const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
-        mip_diag(a, b, i, j, A);
-        spd4_solve(A, rv, zv);
         const double zero[4] = {0.0, 0.0, 0.0, 0.0};
         store4(x, gi, zero);
         store4(r, gi, rv);
-        store4(z, gi, zv);
-        for (int k = 0; k < 4; ++k) { rz += rv[k] * zv[k]; bb += rv[k] * rv[k]; }
+        if (bj) {
+            const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+            mip_diag(a, b, i, j, A);
+            spd4_solve(A, rv, zv);
+            if (bj == 2)
+                for (int k = 0; k < 4; ++k) zv[k] *= kOmegaDG;
+            store4(z, gi, zv);
+            for (int k = 0; k < 4; ++k) rz += rv[k] * zv[k];
+        }
+        for (int k = 0; k < 4; ++k) bb += rv[k] * rv[k];
     }
     block_sum2(rz, bb);
     if (threadIdx.x == 0) {
@@ -462,7 +468,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, 
 __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, const double *p,
                                                              const double *q, double *x, double *r,
                                                              double *z, double *part,
-                                                             const int *state) {
+                                                             const int *state, int bj) {
     const int b = blockIdx.y;
     if (state[b] != 1) return;
     const int nb = a.nblk;
@@ -479,17 +485,22 @@ __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, 
         load4(x, gi, xv);
         load4(r, gi, rv);
         for (int k = 0; k < 4; ++k) { xv[k] += alpha * pv[k]; rv[k] -= alpha * qv[k]; }
-        const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
-        mip_diag(a, b, i, j, A);
-        spd4_solve(A, rv, zv);
         store4(x, gi, xv);
         store4(r, gi, rv);
-        store4(z, gi, zv);
-        for (int k = 0; k < 4; ++k) { rz_new += rv[k] * zv[k]; rr += rv[k] * rv[k]; }
+        if (bj) {
+            const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+            mip_diag(a, b, i, j, A);
+            spd4_solve(A, rv, zv);
+            if (bj == 2)
+                for (int k = 0; k < 4; ++k) zv[k] *= kOmegaDG;
+            store4(z, gi, zv);
+            for (int k = 0; k < 4; ++k) rz_new += rv[k] * zv[k];
+        }
+        for (int k = 0; k < 4; ++k) rr += rv[k] * rv[k];
     }
     block_sum2(rz_new, rr);
     if (threadIdx.x == 0) {
-        slot(part, b, it & 1, nb)[blockIdx.x] = rz_new;
+        if (bj == 1) slot(part, b, it & 1, nb)[blockIdx.x] = rz_new;
         slot(part, b, 3, nb)[blockIdx.x] = rr;
     }
 }
@@ -505,6 +516,421 @@ __global__ void cg_finish_kernel(long long ndof, const double *x, double *delta,
 
 __global__ void zero_int_kernel(int *x) {
     if (threadIdx.x == 0) *x = 0;
+}
+
+// ------------------------------------------------------------------------- multigrid
+// Two-level preconditioner for the MIP system: damped block-Jacobi smoothing on the DG space and
+// a coarse correction on continuous Q1 functions (vertex values, interpolated into every cell:
+// the embedding P), whose operator P^T A P and the operators of coarser vertex grids
+// (bilinear interpolation, Galerkin R A P with R = P^T) are computed by probing with nine
+// colourings of the vertices; the vertex-grid problem is solved approximately by one V-cycle
+// with damped point-Jacobi smoothing.  Every smoother is symmetric, so the preconditioner is.
+constexpr double kOmegaV = 2.0 / 3.0;
+
+struct VG {
+    int nvx, nvy;
+    long long nv;
+};
+
+// DG coefficients of the bilinear interpolant of the vertex values around cell (i, j)
+__device__ __forceinline__ void p_cell(const double *xv, int nvx, int i, int j, double sqa,
+                                       double c[4]) {
+    const double u00 = xv[(long long)j * nvx + i], u10 = xv[(long long)j * nvx + i + 1];
+    const double u01 = xv[(long long)(j + 1) * nvx + i], u11 = xv[(long long)(j + 1) * nvx + i + 1];
+    c[0] = sqa * 0.25 * (u00 + u10 + u01 + u11);
+    c[1] = sqa * 0.25 * ((u10 + u11) - (u00 + u01)) / kS3;
+    c[2] = sqa * 0.25 * ((u01 + u11) - (u00 + u10)) / kS3;
+    c[3] = sqa * 0.25 * (u11 - u10 - u01 + u00) / 3.0;
+}
+
+// P^T: vertex (x, y) gathers from the (up to four) cells having it as a corner
+__device__ __forceinline__ double pt_vertex(const double *rdg, int nx, int ny, int x, int y,
+                                            double sqa) {
+    double s = 0.0;
+    for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+            const int i = x - 1 + cx, j = y - 1 + cy;     // cell; the vertex is its corner (1-cx, 1-cy)
+            if (i < 0 || j < 0 || i >= nx || j >= ny) continue;
+            const double sx = cx == 0 ? 1.0 : -1.0;       // corner a = 1 - cx: sign +1 if a == 1
+            const double sy = cy == 0 ? 1.0 : -1.0;
+            double r[4];
+            load4(rdg, (long long)j * nx + i, r);
+            s += sqa * (0.25 * r[0] + sx * r[1] / (4.0 * kS3) + sy * r[2] / (4.0 * kS3) + sx * sy * r[3] / 12.0);
+        }
+    return s;
+}
+
+// t = r - A z
+__global__ void mg_resid_dg_kernel(MipArgs a, const int *state, const double *r, const double *z,
+                                   double *t) {
+    const int b = blockIdx.y;
+    if (state[b] != 1) return;
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.ncell) return;
+    const size_t base = (size_t)b * a.ncell;
+    auto zat = [&](long long c, double v[4]) { load4(z, base + c, v); };
+    double y[4], rv[4];
+    mip_apply(a, b, (int)(cell % a.nx), (int)(cell / a.nx), zat, y);
+    load4(r, base + cell, rv);
+    for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
+    store4(t, base + cell, y);
+}
+
+// b0 = P^T t (level-0 vertex grid)
+__global__ void mg_restrict_dg_kernel(MipArgs a, const int *state, const double *t, VG g,
+                                      double *b0) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.nv) return;
+    const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
+    b0[(size_t)b * g.nv + v] = pt_vertex(t + (size_t)b * a.ncell * 4, a.nx, a.ny, x, y, sqrt(a.hx * a.hy));
+}
+
+// ---- vertex grids: 9-point stencils S[b][v][(dy+1)*3 + dx+1]
+__device__ __forceinline__ double stencil_apply(const double *S, const double *x, VG g, int vx,
+                                                int vy) {
+    const double *st = S + (long long)(vy * g.nvx + vx) * 9;
+    double s = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = vy + dy;
+        if (yy < 0 || yy >= g.nvy) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int xx = vx + dx;
+            if (xx < 0 || xx >= g.nvx) continue;
+            s += st[(dy + 1) * 3 + dx + 1] * x[(long long)yy * g.nvx + xx];
+        }
+    }
+    return s;
+}
+
+// mode 0: x_out = omega b / diag; 1: x_out = x_in + omega (b - S x_in)/diag; 2: out = b - S x_in;
+// 3: out = S x_in
+__global__ void mg_vertex_kernel(const int *state, VG g, const double *S, const double *x_in,
+                                 const double *bv, double *out, int mode) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.nv) return;
+    const size_t o = (size_t)b * g.nv;
+    const double *Sb = S + o * 9;
+    const double diag = Sb[v * 9 + 4];
+    const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+    double res;
+    if (mode == 0) res = kOmegaV * bv[o + v] / diag;
+    else if (mode == 1) res = x_in[o + v] + kOmegaV * (bv[o + v] - stencil_apply(Sb, x_in + o, g, vx, vy)) / diag;
+    else if (mode == 2) res = bv[o + v] - stencil_apply(Sb, x_in + o, g, vx, vy);
+    else res = stencil_apply(Sb, x_in + o, g, vx, vy);
+    out[o + v] = res;
+}
+
+// coarse b_c = R r_f (R = transpose of bilinear interpolation)
+__global__ void mg_vrestrict_kernel(const int *state, VG gf, const double *rf, VG gc, double *bc) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= gc.nv) return;
+    const int X = (int)(v % gc.nvx), Y = (int)(v / gc.nvx);
+    const double *r = rf + (size_t)b * gf.nv;
+    double s = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int y = 2 * Y + dy;
+        if (y < 0 || y >= gf.nvy) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int x = 2 * X + dx;
+            if (x < 0 || x >= gf.nvx) continue;
+            s += (dx == 0 ? 1.0 : 0.5) * (dy == 0 ? 1.0 : 0.5) * r[(long long)y * gf.nvx + x];
+        }
+    }
+    bc[(size_t)b * gc.nv + v] = s;
+}
+
+// fine x_f (+)= P x_c (bilinear); add = 0 overwrites
+__global__ void mg_vprolong_kernel(const int *state, VG gc, const double *xc, VG gf, double *xf,
+                                   int add) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= gf.nv) return;
+    const int x = (int)(v % gf.nvx), y = (int)(v / gf.nvx);
+    const double *c = xc + (size_t)b * gc.nv;
+    const int X0 = x / 2, Y0 = y / 2;
+    const int X1 = (x & 1) ? X0 + 1 : X0, Y1 = (y & 1) ? Y0 + 1 : Y0;
+    const double val = 0.25 * (c[(long long)Y0 * gc.nvx + X0] + c[(long long)Y0 * gc.nvx + X1] +
+                               c[(long long)Y1 * gc.nvx + X0] + c[(long long)Y1 * gc.nvx + X1]);
+    const size_t o = (size_t)b * gf.nv + v;
+    xf[o] = add ? xf[o] + val : val;
+}
+
+// probing: e = indicator of the vertices of colour (cx, cy) (coordinates mod 3)
+__global__ void mg_colour_kernel(const int *state, VG g, int cx, int cy, double *e) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.nv) return;
+    const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
+    e[(size_t)b * g.nv + v] = (x % 3 == cx && y % 3 == cy) ? 1.0 : 0.0;
+}
+
+// t = A (P e) on the DG space
+__global__ void mg_probe_dg_kernel(MipArgs a, const int *state, const double *e, VG g, double *t) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.ncell) return;
+    const double sqa = sqrt(a.hx * a.hy);
+    const double *eb = e + (size_t)b * g.nv;
+    auto pat = [&](long long c, double v[4]) { p_cell(eb, g.nvx, (int)(c % a.nx), (int)(c / a.nx), sqa, v); };
+    double y[4];
+    mip_apply(a, b, (int)(cell % a.nx), (int)(cell / a.nx), pat, y);
+    store4(t, (size_t)b * a.ncell + cell, y);
+}
+
+// S[v][offset to the colour-(cx,cy) vertex of v's 3x3 neighbourhood] = z[v]
+__global__ void mg_scatter_kernel(const int *state, VG g, int cx, int cy, const double *z,
+                                  double *S) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.nv) return;
+    const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
+    const int mx = ((cx - x) % 3 + 3) % 3, my = ((cy - y) % 3 + 3) % 3;
+    const int dx = mx == 2 ? -1 : mx, dy = my == 2 ? -1 : my;
+    if (x + dx < 0 || x + dx >= g.nvx || y + dy < 0 || y + dy >= g.nvy) return;
+    S[((size_t)b * g.nv + v) * 9 + (dy + 1) * 3 + dx + 1] = z[(size_t)b * g.nv + v];
+}
+
+__global__ void mg_zero_kernel(const int *state, long long n, double *x) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[(size_t)b * n + t] = 0.0;
+}
+
+// coarsest grid: nsweep damped Jacobi sweeps from zero, one workgroup per instance, vectors in LDS
+__global__ void __launch_bounds__(256) mg_coarse_kernel(const int *state, VG g, const double *S,
+                                                        const double *bv, double *x, int nsweep) {
+    extern __shared__ double sh[];
+    const int b = blockIdx.x;
+    if (state[b] != 1) return;
+    double *xa = sh, *xb = sh + g.nv;
+    const size_t o = (size_t)b * g.nv;
+    const double *Sb = S + o * 9;
+    for (long long v = threadIdx.x; v < g.nv; v += blockDim.x) xa[v] = kOmegaV * bv[o + v] / Sb[v * 9 + 4];
+    __syncthreads();
+    for (int k = 1; k < nsweep; ++k) {
+        for (long long v = threadIdx.x; v < g.nv; v += blockDim.x) {
+            const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+            xb[v] = xa[v] + kOmegaV * (bv[o + v] - stencil_apply(Sb, xa, g, vx, vy)) / Sb[v * 9 + 4];
+        }
+        __syncthreads();
+        double *t = xa; xa = xb; xb = t;
+    }
+    for (long long v = threadIdx.x; v < g.nv; v += blockDim.x) x[o + v] = xa[v];
+}
+
+
+// ---- fused multigrid steps (fewer launches, no intermediate vectors)
+// coarse correction, post-smoothing and (r, z) in one pass:
+//   z' = z + P x0,  z_out = z' + omega D^-1 (r - A z'),  partial of (r, z_out) into slot s.
+// z' of the neighbour cells is formed on the fly; z_out must not alias z (other workgroups read z).
+__global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const int *state,
+                                                              const double *r, const double *x0,
+                                                              VG g, const double *z, double *z_out,
+                                                              double *part, int s) {
+    const int b = blockIdx.y;
+    if (state[b] != 1) return;
+    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    double rz = 0.0, dummy = 0.0;
+    const size_t base = (size_t)b * a.ncell;
+    if (cell < a.ncell) {
+        const double sqa = sqrt(a.hx * a.hy);
+        const double *xb = x0 + (size_t)b * g.nv;
+        auto zat = [&](long long c, double v[4]) {
+            double pc[4];
+            load4(z, base + c, v);
+            p_cell(xb, g.nvx, (int)(c % a.nx), (int)(c / a.nx), sqa, pc);
+            for (int k = 0; k < 4; ++k) v[k] += pc[k];
+        };
+        double y[4], zc[4], rv[4], dz[4], zn[4], A[16];
+        const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+        mip_apply(a, b, i, j, zat, y);
+        zat(cell, zc);
+        load4(r, base + cell, rv);
+        for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
+        mip_diag(a, b, i, j, A);
+        spd4_solve(A, y, dz);
+        for (int k = 0; k < 4; ++k) { zn[k] = zc[k] + kOmegaDG * dz[k]; rz += rv[k] * zn[k]; }
+        store4(z_out, base + cell, zn);
+    }
+    block_sum2(rz, dummy);
+    if (threadIdx.x == 0) slot(part, b, s, a.nblk)[blockIdx.x] = rz;
+}
+
+// two damped Jacobi sweeps from zero: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - S x1)
+__global__ void mg_vpre_kernel(const int *state, VG g, const double *S, const double *bv, double *x2) {
+    const int b = blockIdx.y;
+    if (state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.nv) return;
+    const size_t o = (size_t)b * g.nv;
+    const double *Sb = S + o * 9;
+    const double *bb = bv + o;
+    const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+    const double *st = Sb + v * 9;
+    double sx1 = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = vy + dy;
+        if (yy < 0 || yy >= g.nvy) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int xx = vx + dx;
+            if (xx < 0 || xx >= g.nvx) continue;
+            const long long w = (long long)yy * g.nvx + xx;
+            sx1 += st[(dy + 1) * 3 + dx + 1] * (kOmegaV * bb[w] / Sb[w * 9 + 4]);
+        }
+    }
+    const double x1 = kOmegaV * bb[v] / st[4];
+    x2[o + v] = x1 + kOmegaV * (bb[v] - sx1) / st[4];
+}
+
+__device__ __forceinline__ double prolong_at(const double *c, VG gc, int x, int y) {
+    const int X0 = x / 2, Y0 = y / 2;
+    const int X1 = (x & 1) ? X0 + 1 : X0, Y1 = (y & 1) ? Y0 + 1 : Y0;
+    return 0.25 * (c[(long long)Y0 * gc.nvx + X0] + c[(long long)Y0 * gc.nvx + X1] +
+                   c[(long long)Y1 * gc.nvx + X0] + c[(long long)Y1 * gc.nvx + X1]);
+}
+
+// x3 = x2 + P x_c, x4 = x3 + w D^-1 (b - S x3)
+__global__ void mg_vpost1_kernel(const int *state, VG g, const double *S, const double *bv,
+                                 const double *x2, VG gc, const double *xc, double *x4) {
+    const int b = blockIdx.y;
+    if (state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.nv) return;
+    const size_t o = (size_t)b * g.nv;
+    const double *Sb = S + o * 9;
+    const double *cb = xc + (size_t)b * gc.nv;
+    const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+    const double *st = Sb + v * 9;
+    double sx3 = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = vy + dy;
+        if (yy < 0 || yy >= g.nvy) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int xx = vx + dx;
+            if (xx < 0 || xx >= g.nvx) continue;
+            const long long w = (long long)yy * g.nvx + xx;
+            sx3 += st[(dy + 1) * 3 + dx + 1] * (x2[o + w] + prolong_at(cb, gc, xx, yy));
+        }
+    }
+    const double x3 = x2[o + v] + prolong_at(cb, gc, vx, vy);
+    x4[o + v] = x3 + kOmegaV * (bv[o + v] - sx3) / st[4];
+}
+
+
+// V-cycle over the small coarse levels ls..L-1 of one instance in one workgroup, all vectors in
+// LDS: same smoothing, restriction, prolongation and coarsest sweeps as the per-level kernels.
+struct SmallLevels {
+    int n;
+    int nvx[kMaxLevels], nvy[kMaxLevels];
+    long long nv[kMaxLevels];
+    const double *S[kMaxLevels];
+};
+
+__global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state, SmallLevels sl,
+                                                               const double *b_top, double *x_top,
+                                                               int nsweep) {
+    extern __shared__ double sh[];
+    const int b = blockIdx.x;
+    if (state[b] != 1) return;
+    double *xa[kMaxLevels], *xb[kMaxLevels], *bv[kMaxLevels], *rv[kMaxLevels];
+    double *q = sh;
+    for (int l = 0; l < sl.n; ++l) {
+        xa[l] = q; q += sl.nv[l];
+        xb[l] = q; q += sl.nv[l];
+        bv[l] = q; q += sl.nv[l];
+        rv[l] = q; q += sl.nv[l];
+    }
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (long long v = t; v < sl.nv[0]; v += nt) bv[0][v] = b_top[(size_t)b * sl.nv[0] + v];
+    __syncthreads();
+    auto grid_of = [&](int l) { VG g; g.nvx = sl.nvx[l]; g.nvy = sl.nvy[l]; g.nv = sl.nv[l]; return g; };
+    auto S_of = [&](int l) { return sl.S[l] + (size_t)b * sl.nv[l] * 9; };
+    // down: two pre-smoothing sweeps, residual, restriction
+    for (int l = 0; l < sl.n - 1; ++l) {
+        const VG g = grid_of(l);
+        const double *S = S_of(l);
+        for (long long v = t; v < g.nv; v += nt) xa[l][v] = kOmegaV * bv[l][v] / S[v * 9 + 4];
+        __syncthreads();
+        for (long long v = t; v < g.nv; v += nt) {
+            const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+            xb[l][v] = xa[l][v] + kOmegaV * (bv[l][v] - stencil_apply(S, xa[l], g, vx, vy)) / S[v * 9 + 4];
+        }
+        __syncthreads();
+        for (long long v = t; v < g.nv; v += nt) {
+            const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+            rv[l][v] = bv[l][v] - stencil_apply(S, xb[l], g, vx, vy);
+        }
+        __syncthreads();
+        const VG gc = grid_of(l + 1);
+        for (long long v = t; v < gc.nv; v += nt) {
+            const int X = (int)(v % gc.nvx), Y = (int)(v / gc.nvx);
+            double acc = 0.0;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int y = 2 * Y + dy;
+                if (y < 0 || y >= g.nvy) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int x = 2 * X + dx;
+                    if (x < 0 || x >= g.nvx) continue;
+                    acc += (dx == 0 ? 1.0 : 0.5) * (dy == 0 ? 1.0 : 0.5) * rv[l][(long long)y * g.nvx + x];
+                }
+            }
+            bv[l + 1][v] = acc;
+        }
+        __syncthreads();
+    }
+    // coarsest: damped Jacobi sweeps from zero; the result ends in xb
+    {
+        const int l = sl.n - 1;
+        const VG g = grid_of(l);
+        const double *S = S_of(l);
+        for (long long v = t; v < g.nv; v += nt) xb[l][v] = kOmegaV * bv[l][v] / S[v * 9 + 4];
+        __syncthreads();
+        for (int k = 1; k < nsweep; ++k) {
+            for (long long v = t; v < g.nv; v += nt) {
+                const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+                xa[l][v] = xb[l][v] + kOmegaV * (bv[l][v] - stencil_apply(S, xb[l], g, vx, vy)) / S[v * 9 + 4];
+            }
+            __syncthreads();
+            for (long long v = t; v < g.nv; v += nt) xb[l][v] = xa[l][v];
+            __syncthreads();
+        }
+    }
+    // up: prolongation-correction, two post-smoothing sweeps (result in xb)
+    for (int l = sl.n - 2; l >= 0; --l) {
+        const VG g = grid_of(l), gc = grid_of(l + 1);
+        const double *S = S_of(l);
+        for (long long v = t; v < g.nv; v += nt) {
+            const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
+            const int X0 = x / 2, Y0 = y / 2;
+            const int X1 = (x & 1) ? X0 + 1 : X0, Y1 = (y & 1) ? Y0 + 1 : Y0;
+            const double *c = xb[l + 1];
+            xb[l][v] += 0.25 * (c[(long long)Y0 * gc.nvx + X0] + c[(long long)Y0 * gc.nvx + X1] +
+                                c[(long long)Y1 * gc.nvx + X0] + c[(long long)Y1 * gc.nvx + X1]);
+        }
+        __syncthreads();
+        for (long long v = t; v < g.nv; v += nt) {
+            const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+            xa[l][v] = xb[l][v] + kOmegaV * (bv[l][v] - stencil_apply(S, xb[l], g, vx, vy)) / S[v * 9 + 4];
+        }
+        __syncthreads();
+        for (long long v = t; v < g.nv; v += nt) {
+            const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+            xb[l][v] = xa[l][v] + kOmegaV * (bv[l][v] - stencil_apply(S, xa[l], g, vx, vy)) / S[v * 9 + 4];
+        }
+        __syncthreads();
+    }
+    for (long long v = t; v < sl.nv[0]; v += nt) x_top[(size_t)b * sl.nv[0] + v] = xb[0][v];
 }
 
 MipArgs mip_args(const rte_problem *p, int nblk) {
@@ -527,6 +953,144 @@ MipArgs mip_args(const rte_problem *p, int nblk) {
 
 }  // namespace
 
+int mg_levels(int nx, int ny, int *nvx, int *nvy) {
+    // coarsen by two while both cell counts are even and the coarser grid keeps >= 2 cells
+    if (nx < 2 || ny < 2) return 0;
+    int L = 0, cx = nx, cy = ny;
+    while (L < kMaxLevels) {
+        if (nvx) nvx[L] = cx + 1;
+        if (nvy) nvy[L] = cy + 1;
+        ++L;
+        if ((cx & 1) || (cy & 1) || cx < 4 || cy < 4) break;
+        cx /= 2;
+        cy /= 2;
+    }
+    return L;
+}
+
+namespace {
+VG vg_of(const MGLevel &l) {
+    VG g;
+    g.nvx = l.nvx;
+    g.nvy = l.nvy;
+    g.nv = l.nv;
+    return g;
+}
+constexpr int kCoarseSweeps = 30;
+
+constexpr long long kSmallLds = 64 * 1024;
+
+// first level whose V-cycle tail (it and all coarser levels, 4 vectors each) fits in LDS
+int small_start(const CGSpace &c) {
+    long long tail = 0;
+    int ls = c.mg.L;
+    for (int l = c.mg.L - 1; l >= 0; --l) {
+        tail += 4 * c.mg.lv[l].nv * (long long)sizeof(double);
+        if (tail > kSmallLds) break;
+        ls = l;
+    }
+    return ls;
+}
+
+// one V-cycle on level l for the right-hand side lv[l].bv; returns the buffer holding x_l
+double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
+    const MGLevel &L = c.mg.lv[l];
+    const VG g = vg_of(L);
+    const dim3 grid(blocks_for(L.nv, 256), p->B);
+    const int ls = small_start(c);
+    if (l == ls && ls < c.mg.L) {
+        SmallLevels sl;
+        sl.n = c.mg.L - ls;
+        long long lds = 0;
+        for (int k = 0; k < sl.n; ++k) {
+            const MGLevel &M = c.mg.lv[ls + k];
+            sl.nvx[k] = M.nvx;
+            sl.nvy[k] = M.nvy;
+            sl.nv[k] = M.nv;
+            sl.S[k] = M.S;
+            lds += 4 * M.nv * (long long)sizeof(double);
+        }
+        hipLaunchKernelGGL(mg_small_vcycle_kernel, dim3(p->B), dim3(1024), (size_t)lds, s, c.state,
+                           sl, L.bv, L.xb, kCoarseSweeps);
+        return L.xb;
+    }
+    if (l == c.mg.L - 1) {
+        if (L.nv <= 4096) {
+            hipLaunchKernelGGL(mg_coarse_kernel, dim3(p->B), dim3(256), 2 * L.nv * sizeof(double), s,
+                               c.state, g, L.S, L.bv, L.xa, kCoarseSweeps);
+            return L.xa;
+        }
+        hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xa, L.bv, L.xa, 0);
+        double *cur = L.xa, *nxt = L.xb;
+        for (int k = 1; k < kCoarseSweeps; ++k) {
+            hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, cur, L.bv, nxt, 1);
+            double *t = cur; cur = nxt; nxt = t;
+        }
+        return cur;
+    }
+    const MGLevel &C = c.mg.lv[l + 1];
+    const VG gcv = vg_of(C);
+    // two pre-smoothing sweeps from zero, residual, restriction
+    hipLaunchKernelGGL(mg_vpre_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.bv, L.xb);
+    hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xb, L.bv, L.rv, 2);
+    hipLaunchKernelGGL(mg_vrestrict_kernel, dim3(blocks_for(C.nv, 256), p->B), dim3(256), 0, s,
+                       c.state, g, L.rv, gcv, C.bv);
+    double *xc = vcycle(p, c, l + 1, s);
+    // coarse correction with the first post-smoothing sweep, then the second sweep
+    hipLaunchKernelGGL(mg_vpost1_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.bv, L.xb, gcv, xc, L.xa);
+    hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xa, L.bv, L.xb, 1);
+    return L.xb;
+}
+}  // namespace
+
+hipError_t launch_mg_build(const rte_problem *p, const CGSpace &c, hipStream_t s) {
+    const MipArgs a = mip_args(p, c.nblk);
+    const int *all = nullptr;     // the hierarchy is built for every instance of the batch
+    const dim3 gc(blocks_for(p->ncell, 256), p->B);
+    for (int l = 0; l < c.mg.L; ++l) {
+        const MGLevel &L = c.mg.lv[l];
+        const VG g = vg_of(L);
+        const dim3 gv(blocks_for(L.nv, 256), p->B);
+        hipLaunchKernelGGL(mg_zero_kernel, dim3(blocks_for(L.nv * 9, 256), p->B), dim3(256), 0, s,
+                           all, L.nv * 9, L.S);
+        for (int cy = 0; cy < 3; ++cy)
+            for (int cx = 0; cx < 3; ++cx) {
+                if (l == 0) {
+                    hipLaunchKernelGGL(mg_colour_kernel, gv, dim3(256), 0, s, all, g, cx, cy, c.mg.e);
+                    hipLaunchKernelGGL(mg_probe_dg_kernel, gc, dim3(256), 0, s, a, all, c.mg.e, g, c.mg.t);
+                    hipLaunchKernelGGL(mg_restrict_dg_kernel, gv, dim3(256), 0, s, a, all, c.mg.t, g, L.rv);
+                } else {
+                    const MGLevel &F = c.mg.lv[l - 1];
+                    const VG gf = vg_of(F);
+                    const dim3 gfv(blocks_for(F.nv, 256), p->B);
+                    hipLaunchKernelGGL(mg_colour_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.xa);
+                    hipLaunchKernelGGL(mg_vprolong_kernel, gfv, dim3(256), 0, s, all, g, L.xa, gf, F.xa, 0);
+                    hipLaunchKernelGGL(mg_vertex_kernel, gfv, dim3(256), 0, s, all, gf, F.S, F.xa, F.bv, F.rv, 3);
+                    hipLaunchKernelGGL(mg_vrestrict_kernel, gv, dim3(256), 0, s, all, gf, F.rv, g, L.rv);
+                }
+                hipLaunchKernelGGL(mg_scatter_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.rv, L.S);
+            }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot_id, hipStream_t s) {
+    const MipArgs a = mip_args(p, c.nblk);
+    const dim3 gc(blocks_for(p->ncell, 256), p->B);
+    const MGLevel &L0 = c.mg.lv[0];
+    const VG g0 = vg_of(L0);
+    // c.z holds the pre-smoothed z = omega D^-1 r (written with r by the CG kernels);
+    // residual t = r - A z and the coarse right-hand side P^T t
+    hipLaunchKernelGGL(mg_resid_dg_kernel, gc, dim3(256), 0, s, a, c.state, c.r, c.z, c.mg.t);
+    hipLaunchKernelGGL(mg_restrict_dg_kernel, dim3(blocks_for(L0.nv, 256), p->B), dim3(256), 0, s,
+                       a, c.state, c.mg.t, g0, L0.bv);
+    const double *x0 = vcycle(p, c, 0, s);
+    // coarse correction and post-smoothing; the preconditioned residual goes to c.mg.t
+    hipLaunchKernelGGL(mg_post_dg_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, c.state,
+                       c.r, x0, g0, c.z, c.mg.t, c.part, slot_id);
+    return hipGetLastError();
+}
+
 size_t cg_blocks_per_instance(const rte_problem *p) {
     return (size_t)((p->ncell + kCgBlock - 1) / kCgBlock);
 }
@@ -545,9 +1109,12 @@ hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double 
                            hipStream_t s) {
     const MipArgs a = mip_args(p, c.nblk);
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, c.n_running);
+    // bj = 1: block-Jacobi preconditioner; bj = 2: first smoothing step of the multigrid one
+    const int bj = c.mg.L == 0 ? 1 : 2;
     hipLaunchKernelGGL(cg_setup_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, rho_star,
                        rho_prev, kind, want_kind, c.x, c.r, c.z, c.part, c.state, c.iters,
-                       c.n_running);
+                       c.n_running, bj);
+    if (bj == 2) return launch_mg_precond(p, c, 0, s);    // hierarchy built by launch_mg_build
     return hipGetLastError();
 }
 
@@ -556,11 +1123,14 @@ hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, d
     const MipArgs a = mip_args(p, c.nblk);
     double *p_new = (it & 1) ? c.p1 : c.p0;
     const double *p_old = (it & 1) ? c.p0 : c.p1;
+    const double *z = c.mg.L == 0 ? c.z : c.mg.t;    // preconditioned residual
     hipLaunchKernelGGL(cg_matvec_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, it,
-                       rtol * rtol, maxit, c.z, p_old, p_new, c.q, c.part, c.state, c.iters,
+                       rtol * rtol, maxit, z, p_old, p_new, c.q, c.part, c.state, c.iters,
                        c.n_running);
+    const int bj = c.mg.L == 0 ? 1 : 2;
     hipLaunchKernelGGL(cg_update_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, it, p_new,
-                       c.q, c.x, c.r, c.z, c.part, c.state);
+                       c.q, c.x, c.r, c.z, c.part, c.state, bj);
+    if (bj == 2) return launch_mg_precond(p, c, it & 1, s);
     return hipGetLastError();
 }
 

@@ -1,0 +1,329 @@
+// Offline construction of the correction ROM on the device (Sec. 3.1 POD, Sec. 3.2.1 snapshot
+// generation, Sec. 3.1.1 reduced affine operators).
+//
+//   snapshot columns   delta f = f^mu - f^(mu,l)                         (pod_snapshot_kernel)
+//   Gram matrix        G = X^T Y over long columns, optionally restricted to one material class
+//                      (v_mfma_f64_16x16x4f64, split over the rows, fixed-order split sum)
+//   eigenpairs of G    cyclic Jacobi, one workgroup (the method of snapshots: F = U S V^T with
+//                      F^T F = V S^2 V^T, U = F V S^-1)
+//   basis              U = X W for a small W (v_mfma_f64_16x16x4f64)
+//   streaming operator y_j = D_j x_j of eq. (dg_matrix_vec) (upwind DG, no boundary load)
+//   direction sums     sum_j w_j x_j (density of a basis vector) and sum_j x_j (isotropic
+//                      projection), eq. (rho_basis)
+#include <cmath>
+#include <vector>
+
+#include "rte_internal.h"
+
+namespace rte {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr double kS3 = 1.7320508075688772935;
+
+inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+__global__ void pod_snapshot_kernel(long long len, int B, const double *f_final, const double *f_l,
+                                    double *cols, long long stride) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (t >= len) return;
+    const double a = f_final[(size_t)b * len + t];
+    cols[(size_t)b * stride + t] = f_l ? a - f_l[(size_t)b * len + t] : a;
+}
+
+// G_part[split][i][j] = sum over rows in the split of X[i][row] Y[j][row] (row in class cls)
+__global__ void __launch_bounds__(64) gram_kernel(const double *X, int nxc, const double *Y,
+                                                  int nyc, long long len, long long per_split,
+                                                  const int *cell_class, int K, long long ncell,
+                                                  int cls, double *part) {
+    const int lane = threadIdx.x;
+    const int split = blockIdx.x, ti = blockIdx.y, tj = blockIdx.z;
+    const int n = lane & 15, kq = lane >> 4;
+    const int ci = ti * 16 + n, cj = tj * 16 + n;
+    const bool li = ci < nxc, lj = cj < nyc;
+    const long long k_begin = (long long)split * per_split;
+    long long k_end = k_begin + per_split;
+    if (k_end > len) k_end = len;
+    v4d acc = {0, 0, 0, 0};
+    for (long long k0 = k_begin; k0 < k_end; k0 += 16) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const long long k = k0 + 4 * kq + s;
+            bool in = k < k_end;
+            if (in && cell_class) in = cell_class[(k / K) % ncell] == cls;
+            av[s] = (in && li) ? X[(size_t)ci * len + k] : 0.0;
+            bv[s] = (in && lj) ? Y[(size_t)cj * len + k] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gi = ti * 16 + kq + 4 * i, gj = tj * 16 + n;   // D row = q + 4 i (f64)
+        if (gi < nxc && gj < nyc) part[((size_t)split * nxc + gi) * nyc + gj] = acc[i];
+    }
+}
+
+__global__ void sum_splits_kernel(const double *part, int nsplit, long long n, double *out) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n + t];
+    out[t] = s;
+}
+
+// Cyclic Jacobi for a symmetric n x n matrix (n <= 256) in global memory, one workgroup.
+// Parallel ordering: in every round the n (padded to even) indices are paired by the
+// round-robin tournament, the n/2 rotations are independent.  On exit A is diagonal
+// (eigenvalues), V holds the eigenvectors as columns.
+__global__ void __launch_bounds__(256) jacobi_kernel(double *A, int n, double *V, double *evals,
+                                                     int sweeps) {
+    __shared__ double cs[128], sn[128];
+    __shared__ int pp[128], qq[128];
+    __shared__ double off_s[256];
+    const int t = threadIdx.x;
+    const int m = n + (n & 1);           // padded size (dummy index m-1 when n is odd)
+    for (int i = t; i < n * n; i += blockDim.x) V[i] = (i / n == i % n) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; ++sw) {
+        // convergence: off-diagonal norm vs diagonal norm
+        double o = 0.0, d = 0.0;
+        for (int i = t; i < n * n; i += blockDim.x) {
+            const double v = A[i];
+            if (i / n == i % n) d += v * v; else o += v * v;
+        }
+        off_s[t] = o;
+        __syncthreads();
+        if (t == 0) {
+            double so = 0.0;
+            for (int k = 0; k < (int)blockDim.x; ++k) so += off_s[k];
+            off_s[0] = so;
+        }
+        __syncthreads();
+        const double offn = off_s[0];
+        __syncthreads();
+        off_s[t] = d;
+        __syncthreads();
+        if (t == 0) {
+            double sd = 0.0;
+            for (int k = 0; k < (int)blockDim.x; ++k) sd += off_s[k];
+            off_s[1] = sd;
+        }
+        __syncthreads();
+        const double dn = off_s[1];
+        __syncthreads();
+        if (offn <= 1e-30 * dn || offn == 0.0) break;
+        for (int round = 0; round < m - 1; ++round) {
+            // pairs of the round-robin tournament: fixed element m-1, the others rotate
+            if (t < m / 2) {
+                int a, b;
+                if (t == 0) { a = m - 1; b = round; }
+                else {
+                    a = (round + t) % (m - 1);
+                    b = (round - t + (m - 1)) % (m - 1);
+                }
+                int p = a < b ? a : b, q = a < b ? b : a;
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = A[p * n + q];
+                    if (apq != 0.0) {
+                        const double app = A[p * n + p], aqq = A[q * n + q];
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        s = tt * c;
+                    }
+                }
+                pp[t] = p; qq[t] = q < n ? q : p; cs[t] = c; sn[t] = (q < n) ? s : 0.0;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int idx = t; idx < (m / 2) * n; idx += blockDim.x) {
+                const int k = idx / n, col = idx % n;
+                const int p = pp[k], q = qq[k];
+                if (p == q) continue;
+                const double c = cs[k], s = sn[k];
+                const double ap = A[p * n + col], aq = A[q * n + col];
+                A[p * n + col] = c * ap - s * aq;
+                A[q * n + col] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int idx = t; idx < (m / 2) * n; idx += blockDim.x) {
+                const int k = idx / n, row = idx % n;
+                const int p = pp[k], q = qq[k];
+                if (p == q) continue;
+                const double c = cs[k], s = sn[k];
+                const double ap = A[row * n + p], aq = A[row * n + q];
+                A[row * n + p] = c * ap - s * aq;
+                A[row * n + q] = s * ap + c * aq;
+                const double vp = V[row * n + p], vq = V[row * n + q];
+                V[row * n + p] = c * vp - s * vq;
+                V[row * n + q] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = t; i < n; i += blockDim.x) evals[i] = A[i * n + i];
+}
+
+// out[c][row] = sum_col W[col][c] X[col][row]; one wave per (16 rows x 16 outputs) tile.
+__global__ void __launch_bounds__(64) combine_kernel(const double *X, int ncol, long long len,
+                                                     const double *W, int r, double *out) {
+    const int lane = threadIdx.x;
+    const int n = lane & 15, kq = lane >> 4;
+    const long long m0 = (long long)blockIdx.x * 16;
+    const int c0 = blockIdx.y * 16;
+    v4d acc = {0, 0, 0, 0};
+    const int kpad = (ncol + 3) & ~3;
+    for (int k0 = 0; k0 < kpad; k0 += 4) {
+        const int kk = k0 + kq;
+        const long long row = m0 + n;
+        const double a = (kk < ncol && row < len) ? X[(size_t)kk * len + row] : 0.0;
+        const double b = (kk < ncol && c0 + n < r) ? W[(size_t)kk * r + c0 + n] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const long long row = m0 + kq + 4 * i;
+        const int c = c0 + n;
+        if (row < len && c < r) out[(size_t)c * len + row] = acc[i];
+    }
+}
+
+// y_j = D_j x_j for every vector and direction (upwind DG streaming operator, no boundary load),
+// in the reflected coordinates of the direction's quadrant: D = a (A (x) I) + b (I (x) A) minus
+// the inflow coupling to the upwind neighbours' outgoing traces.
+__global__ void apply_streaming_kernel(int nx, int ny, int n_dir, int nvec, const double *vx,
+                                       const double *vy, double hx, double hy, const double *x,
+                                       double *y) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long ncell = (long long)nx * ny;
+    const long long tot = (long long)nvec * n_dir * ncell;
+    if (t >= tot) return;
+    const long long cell = t % ncell;
+    const long long vj = t / ncell;                  // vector * n_dir + direction
+    const int j = (int)(vj % n_dir);
+    const int ix = (int)(cell % nx), iy = (int)(cell / nx);
+    const double sx = vx[j] < 0 ? -1.0 : 1.0, sy = vy[j] < 0 ? -1.0 : 1.0;
+    const double a = fabs(vx[j]) / hx, b = fabs(vy[j]) / hy, c = kS3;
+    const double *xv = x + (size_t)vj * ncell * 4;
+    auto load = [&](long long cc, double f[4]) {
+        const double4 v = *reinterpret_cast<const double4 *>(xv + cc * 4);
+        f[0] = v.x; f[1] = sx * v.y; f[2] = sy * v.z; f[3] = sx * sy * v.w;   // reflected
+    };
+    double f[4];
+    load(cell, f);
+    // a (A (x) I) f + b (I (x) A) f, A = [[1, c], [-c, 3]], dof k = a + 2 b
+    double o[4];
+    o[0] = a * (f[0] + c * f[1]) + b * (f[0] + c * f[2]);
+    o[1] = a * (-c * f[0] + 3.0 * f[1]) + b * (f[1] + c * f[3]);
+    o[2] = a * (f[2] + c * f[3]) + b * (-c * f[0] + 3.0 * f[2]);
+    o[3] = a * (-c * f[2] + 3.0 * f[3]) + b * (-c * f[1] + 3.0 * f[3]);
+    // inflow coupling from the upwind neighbours (interior only)
+    const int ux = ix - (int)sx, uy = iy - (int)sy;
+    if (ux >= 0 && ux < nx) {
+        double g[4];
+        load((long long)iy * nx + ux, g);
+        const double T0 = g[0] + c * g[1], T1 = g[2] + c * g[3];     // traces at its + face
+        o[0] -= a * T0; o[1] += a * c * T0; o[2] -= a * T1; o[3] += a * c * T1;
+    }
+    if (uy >= 0 && uy < ny) {
+        double g[4];
+        load((long long)uy * nx + ix, g);
+        const double T0 = g[0] + c * g[2], T1 = g[1] + c * g[3];
+        o[0] -= b * T0; o[2] += b * c * T0; o[1] -= b * T1; o[3] += b * c * T1;
+    }
+    double4 r;
+    r.x = o[0]; r.y = sx * o[1]; r.z = sy * o[2]; r.w = sx * sy * o[3];
+    *reinterpret_cast<double4 *>(y + (size_t)vj * ncell * 4 + cell * 4) = r;
+}
+
+__global__ void direction_sum_kernel(long long ndof, int n_dir, int nvec, const double *w,
+                                     const double *x, double *out) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (t >= ndof) return;
+    const double *xv = x + (size_t)v * n_dir * ndof + t;
+    double s = 0.0;
+    for (int j = 0; j < n_dir; ++j) s += (w ? w[j] : 1.0) * xv[(size_t)j * ndof];
+    out[(size_t)v * ndof + t] = s;
+}
+
+}  // namespace
+}  // namespace rte
+
+using namespace rte;
+
+extern "C" {
+
+int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double *f_iter,
+                      double *cols, long long stride, rte_stream_t stream) {
+    if (!p || !f_final || !cols) return RTE_EINVAL;
+    const long long len = (long long)p->n_dir * p->ndof;
+    if (stride < len) return RTE_EINVAL;
+    hipLaunchKernelGGL(pod_snapshot_kernel, dim3(cdiv(len, 256), p->B), dim3(256), 0,
+                       (hipStream_t)stream, len, p->B, f_final, f_iter, cols, stride);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_gram(const double *X, int nxc, const double *Y, int nyc, long long len,
+             const int *cell_class, int K, long long ncell, int cls, double *G, void *ws,
+             size_t ws_bytes, rte_stream_t stream) {
+    if (!X || !Y || !G || nxc < 1 || nyc < 1 || len < 1 || !ws) return RTE_EINVAL;
+    if (cell_class && (K < 1 || ncell < 1)) return RTE_EINVAL;
+    const long long tiles = (long long)cdiv(nxc, 16) * cdiv(nyc, 16);
+    long long nsplit = (4096 + tiles - 1) / tiles;
+    const long long maxs = (len + 4095) / 4096;
+    if (nsplit > maxs) nsplit = maxs;
+    if (nsplit < 1) nsplit = 1;
+    while ((size_t)nsplit * nxc * nyc * 8 > ws_bytes && nsplit > 1) nsplit /= 2;
+    if ((size_t)nsplit * nxc * nyc * 8 > ws_bytes) return RTE_ENOMEM;
+    long long per = (len + nsplit - 1) / nsplit;
+    per = (per + 15) / 16 * 16;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(gram_kernel, dim3((unsigned)nsplit, cdiv(nxc, 16), cdiv(nyc, 16)), dim3(64),
+                       0, s, X, nxc, Y, nyc, len, per, cell_class, K, ncell, cls, (double *)ws);
+    const long long n = (long long)nxc * nyc;
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, (const double *)ws,
+                       (int)nsplit, n, G);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_sym_eig(double *A, int n, double *evals, double *evecs, rte_stream_t stream) {
+    if (!A || !evals || !evecs || n < 1 || n > 256) return RTE_EINVAL;
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, A, n, evecs,
+                       evals, 30);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_combine(const double *X, int ncol, long long len, const double *W, int r, double *out,
+                rte_stream_t stream) {
+    if (!X || !W || !out || ncol < 1 || r < 1 || len < 1) return RTE_EINVAL;
+    hipLaunchKernelGGL(combine_kernel, dim3(cdiv(len, 16), cdiv(r, 16)), dim3(64), 0,
+                       (hipStream_t)stream, X, ncol, len, W, r, out);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_apply_streaming(const rte_problem *p, const double *x, int nvec, double *y,
+                        rte_stream_t stream) {
+    if (!p || !x || !y || nvec < 1 || p->dim != 2) return RTE_EINVAL;
+    const long long tot = (long long)nvec * p->n_dir * p->ncell;
+    hipLaunchKernelGGL(apply_streaming_kernel, dim3(cdiv(tot, 256)), dim3(256), 0,
+                       (hipStream_t)stream, p->nx, p->ny, p->n_dir, nvec, p->d_vxy,
+                       p->d_vxy + p->n_dir, p->hx, p->hy, x, y);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_direction_sum(const rte_problem *p, const double *x, int nvec, int weighted, double *out,
+                      rte_stream_t stream) {
+    if (!p || !x || !out || nvec < 1) return RTE_EINVAL;
+    hipLaunchKernelGGL(direction_sum_kernel, dim3(cdiv(p->ndof, 256), nvec), dim3(256), 0,
+                       (hipStream_t)stream, p->ndof, p->n_dir, nvec, weighted ? p->d_w : nullptr,
+                       x, out);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+}  // extern "C"

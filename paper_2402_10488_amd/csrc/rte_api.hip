@@ -86,6 +86,23 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
             L.cg.iters = c.take<int>(B);
             L.cg.state = c.take<int>(B);
             L.cg.n_running = c.take<int>(1);
+            int nvx[kMaxLevels], nvy[kMaxLevels];
+            L.cg.mg.L = p->dsa_mg ? mg_levels(p->nx, p->ny, nvx, nvy) : 0;
+            for (int l = 0; l < L.cg.mg.L; ++l) {
+                MGLevel &g = L.cg.mg.lv[l];
+                g.nvx = nvx[l];
+                g.nvy = nvy[l];
+                g.nv = (long long)nvx[l] * nvy[l];
+                g.S = c.take<double>(B * (size_t)g.nv * 9);
+                g.xa = c.take<double>(B * (size_t)g.nv);
+                g.xb = c.take<double>(B * (size_t)g.nv);
+                g.bv = c.take<double>(B * (size_t)g.nv);
+                g.rv = c.take<double>(B * (size_t)g.nv);
+            }
+            if (L.cg.mg.L > 0) {
+                L.cg.mg.t = c.take<double>(B * nd);
+                L.cg.mg.e = c.take<double>(B * (size_t)L.cg.mg.lv[0].nv);
+            }
         } else {
             L.dsa1d = c.take<double>(B * (size_t)p->nx * 20);
             L.cg.iters = c.take<int>(B);
@@ -286,6 +303,8 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
     p->d_dirs = nullptr;
     p->d_mu = p->d_w = p->d_widths = nullptr;
     p->d_offA = p->d_offB = nullptr;
+    p->d_vxy = nullptr;
+    p->dsa_mg = 1;
     // quadrant-sorted, padded direction table (2D)
     std::vector<DirEntry> table;
     for (int q = 0; q < 4; ++q) p->quad.count[q] = 0;
@@ -350,6 +369,10 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
         ok = ok && hipMalloc(&p->d_offB, sizeof(int) * nd) == hipSuccess;
         ok = ok && hipMemcpy(p->d_offA, offA.data(), sizeof(int) * nd, hipMemcpyHostToDevice) == hipSuccess;
         ok = ok && hipMemcpy(p->d_offB, offB.data(), sizeof(int) * nd, hipMemcpyHostToDevice) == hipSuccess;
+        std::vector<double> vxy(2 * (size_t)p->n_dir);
+        for (int j = 0; j < p->n_dir; ++j) { vxy[j] = p->vx[j]; vxy[p->n_dir + j] = p->vy[j]; }
+        ok = ok && hipMalloc(&p->d_vxy, sizeof(double) * vxy.size()) == hipSuccess;
+        ok = ok && hipMemcpy(p->d_vxy, vxy.data(), sizeof(double) * vxy.size(), hipMemcpyHostToDevice) == hipSuccess;
     }
     if (!ok) {
         rte_problem_destroy(p);
@@ -367,7 +390,14 @@ void rte_problem_destroy(rte_problem *p) {
     if (p->d_widths) (void)hipFree(p->d_widths);
     if (p->d_offA) (void)hipFree(p->d_offA);
     if (p->d_offB) (void)hipFree(p->d_offB);
+    if (p->d_vxy) (void)hipFree(p->d_vxy);
     delete p;
+}
+
+int rte_problem_dsa_multigrid(rte_problem *p, int on) {
+    if (!p) return RTE_EINVAL;
+    p->dsa_mg = on != 0;
+    return RTE_OK;
 }
 
 int rte_problem_tuning(const rte_problem *p, int *dg, int *wpb, int *nparts) {
@@ -505,12 +535,15 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
         HIPCHK(launch_dsa1d(p, rho_star, rho_prev, delta, kind, want, L.dsa1d, s));
         return RTE_OK;
     }
+    // the multigrid hierarchy depends only on the materials: built by the caller once
     HIPCHK(launch_cg_setup(p, L.cg, rho_star, rho_prev, kind, want, rtol, s));
-    const int poll = 8;
+    // the host looks at the number of running instances every few iterations only: a look
+    // drains the queue, and iterations launched after every instance stopped return at once
+    const int poll = 4;
     int running = 1;
     for (int it = 1; it <= maxit + 1; ++it) {
         HIPCHK(launch_cg_iteration(p, L.cg, it, rtol, maxit, s));
-        if (it == 1 || it % poll == 0 || it == maxit + 1) {
+        if ((it >= 8 && it % poll == 0) || it == maxit + 1) {
             HIPCHK(hipMemcpyAsync(&running, L.cg.n_running, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             if (running == 0) break;
@@ -557,6 +590,7 @@ int rte_dsa_correct(const rte_problem *p, const double *rho_star, const double *
     Layout L = carve(c, p, RTE_SI_DSA, nullptr, RTE_FP64, 1);
     if (!c.ok) return RTE_ENOMEM;
     int failed = 0;
+    if (p->dim == 2 && L.cg.mg.L > 0) HIPCHK(launch_mg_build(p, L.cg, s));
     int rc = do_dsa(p, L, rho_star, rho_prev, delta_rho, nullptr, 0, cg_rtol, cg_maxit,
                     cg_iters_out, &failed, s);
     if (rc) return rc;
@@ -602,6 +636,7 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     const int poll = o->poll_every > 0 ? o->poll_every : 1;
 
     HIPCHK(launch_init_state(p, L.st, max_iter, s));
+    if (mode != RTE_SI && p->dim == 2 && L.cg.mg.L > 0) HIPCHK(launch_mg_build(p, L.cg, s));
     HIPCHK(launch_source(p, rho, L.src, nullptr, fp32, s));
     int iterations = 0;
     bool cg_failed = false;

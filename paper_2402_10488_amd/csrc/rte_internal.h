@@ -56,6 +56,8 @@ struct rte_problem {
     double *d_w;              // device [n_dir] weights (caller order)
     double *d_widths;         // 1D: device [nx]
     int *d_offA, *d_offB;     // 2D: device [nx+ny-1] diagonal offsets of the sweep layouts
+    double *d_vxy;            // 2D: device [2][n_dir] directions in caller order
+    int dsa_mg;               // 2D diffusion CG preconditioner: 1 multigrid, 0 block-Jacobi
     int nparts() const;       // 2D sweep partial-sum slots per instance for the current tuning
 };
 
@@ -169,7 +171,25 @@ hipError_t launch_dsa1d(const rte_problem *p, const double *rho_star, const doub
                         double *delta, const int *kind, int want_kind, double *scratch,
                         hipStream_t s);
 
+// vertex-grid hierarchy of the multigrid preconditioner of the 2D diffusion CG
+constexpr int kMaxLevels = 12;
+struct MGLevel {
+    int nvx, nvy;          // vertices per axis
+    long long nv;
+    double *S;             // [B][nv][9] Galerkin stencils
+    double *xa, *xb, *bv, *rv;   // [B][nv]
+};
+struct MGSpace {
+    int L;                 // number of vertex levels (0 = multigrid off: block-Jacobi PCG)
+    MGLevel lv[kMaxLevels];
+    double *t;             // [B][ndof] DG scratch
+    double *e;             // [B][nv0] probe vector
+};
+// levels for an nx x ny mesh (0 when the mesh is too small for a coarse space)
+int mg_levels(int nx, int ny, int *nvx, int *nvy);
+
 struct CGSpace {
+    MGSpace mg;
     double *x, *r, *z, *p0, *p1, *q;   // [B][ndof]
     double *part;                      // [B][5][nblk] partial sums
     double *scal;                      // [B][8] per-instance scalars
@@ -181,6 +201,10 @@ struct CGSpace {
 hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double *rho_star,
                            const double *rho_prev, const int *kind, int want_kind, double rtol,
                            hipStream_t s);
+// Galerkin vertex operators for the instances whose CG state is running (after cg_setup)
+hipError_t launch_mg_build(const rte_problem *p, const CGSpace &c, hipStream_t s);
+// z = M^-1 r and the partial sums of (r, z) in parity slot `slot`
+hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot, hipStream_t s);
 hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, double rtol,
                                int maxit, hipStream_t s);
 hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delta, int *iters_out,

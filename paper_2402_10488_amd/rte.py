@@ -88,6 +88,7 @@ def _load():
                                   _vp]
     L.rte_sisa_solve.argtypes = [P, ctypes.c_int, P, _vp, ctypes.POINTER(SolveOpts), _vp, _vp,
                                  ctypes.POINTER(SolveStats), _vp, ctypes.c_size_t, _vp]
+    L.rte_problem_dsa_multigrid.argtypes = [P, ctypes.c_int]
     L.rte_profile_enable.argtypes = [ctypes.c_int]
     L.rte_profile_read.argtypes = [ctypes.c_int, _D, ctypes.POINTER(ctypes.c_longlong)]
     return L
@@ -99,7 +100,8 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_problem_tuning", "rte_problem_check", "rte_rom_create", "rte_rom_destroy",
             "rte_workspace_size", "rte_sweep", "rte_scalar_flux", "rte_dsa_correct",
             "rte_rom_correct", "rte_sisa_solve", "rte_strerror", "rte_profile_enable",
-            "rte_profile_read"]
+            "rte_profile_read", "rte_problem_dsa_multigrid", "rte_pod_snapshots", "rte_gram",
+            "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum"]
 
 PROF = {"sweep2d": 0, "reduce": 1, "dsa": 2, "rom": 3, "sweep1d": 4}
 
@@ -180,6 +182,10 @@ class Problem:
         _check(lib.rte_problem_tuning(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "rte_problem_tuning")
         return {"dg": a.value, "wpb": b.value, "nparts": c.value}
+
+    def dsa_multigrid(self, on=True):
+        """Multigrid (default) or block-Jacobi preconditioning of the 2D diffusion CG."""
+        _check(lib.rte_problem_dsa_multigrid(self.handle, int(bool(on))), "rte_problem_dsa_multigrid")
 
     def workspace_bytes(self, mode="si", rom=None, precision="fp64", max_iter=1):
         n = ctypes.c_size_t()

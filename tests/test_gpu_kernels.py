@@ -127,22 +127,29 @@ def test_dsa1d_matches_appendix_b(R):
         assert rel_err(delta[b], ref) < 1e-12
 
 
-@pytest.mark.parametrize("nx,ny,L", [(11, 7, 1.0), (40, 33, 10.0), (16, 16, 0.05)])
-def test_dsa2d_matches_mip_direct_solve(R, nx, ny, L):
+@pytest.mark.parametrize("nx,ny,L,mg", [(11, 7, 1.0, True), (40, 33, 10.0, True),
+                                        (16, 16, 0.05, True), (64, 48, 3.0, True),
+                                        (32, 32, 30.0, True), (40, 33, 10.0, False),
+                                        (16, 16, 0.05, False)])
+def test_dsa2d_matches_mip_direct_solve(R, nx, ny, L, mg):
     import torch
     rte, problems = R
     plane = W.random_plane(40 + nx, nx=nx, ny=ny, n_phi=8, B=3, Lx=L, Ly=0.8 * L)
-    say(f"dsa2d {nx}x{ny} L={L}")
+    say(f"dsa2d {nx}x{ny} L={L} multigrid={mg}")
     P = problems.plane_problem(plane)
+    P.dsa_multigrid(mg)
     discs = [discretize(plane, b) for b in range(3)]
     rng = np.random.default_rng(9)
     rs = rng.uniform(0, 1, (3, P.ndof))
     rp = rng.uniform(0, 1, (3, P.ndof))
     delta = torch.zeros((3, P.ndof), dtype=torch.float64, device="cuda")
     iters = torch.zeros(3, dtype=torch.int32, device="cuda")
-    rte.dsa_correct(P, dev(rs), dev(rp), delta, cg_rtol=1e-14, cg_maxit=20000, iters_out=iters)
+    rte.dsa_correct(P, dev(rs), dev(rp), delta, cg_rtol=1e-14, cg_maxit=20000, iters_out=iters,
+                    ws=P.workspace("si_dsa"))
     delta = host(delta)
-    assert np.all(host(iters) > 0)
+    it = host(iters)
+    say(f"  cg iterations {it}")
+    assert np.all(it > 0)
     for b, d in enumerate(discs):
         ref = odsa.MIPDSA2D(d).correct(d.apply_Ss(rs[b] - rp[b]))
         assert rel_err(delta[b], ref) < 1e-10, rel_err(delta[b], ref)
