@@ -161,8 +161,17 @@ struct MipArgs {
     int nx, ny, B, nblk;
     long long ncell;
     double hx, hy, cxx, cyy, kx, ky;
+    double ihx, ihy;                  // 1/h
+    double th_x, th_y;                // s3/h^2
+    double vol_x, vol_y;              // 12/h^2
     const double *sigma_t, *sigma_s;
+    // per-cell data of the operator, computed once per solve by mip_prepare_kernel:
+    //   cf   [B][5][ncell]  sigma_a, Dx, Dy, kappa of the right face, kappa of the top face
+    //   binv [B][10][ncell] inverse of the diagonal 4x4 block (upper triangle, row-major)
+    const double *cf, *binv;
 };
+constexpr int kCf = 5;
+constexpr int kBinv = 10;
 
 __device__ __forceinline__ double kap_int(double Dm, double Dp, double h, double kmin) {
     return fmax(kmin, 0.5 * kMipC * (Dm + Dp) / h);
@@ -171,24 +180,24 @@ __device__ __forceinline__ double kap_bnd(double D, double h, double kmin) {
     return fmax(kmin, kMipC * D / h);
 }
 
-// 2x2 face blocks (row-major [a][a'])
-__device__ __forceinline__ void face_plus(double kap, double D, double h, double M[4]) {
-    const double s3 = kS3, t = D * s3 / (h * h), k = kap / h;
+// 2x2 face blocks (row-major [a][a']) in terms of k = kappa/h and t = D s3/h^2
+__device__ __forceinline__ void face_plus(double k, double t, double M[4]) {
+    const double s3 = kS3;
     M[0] = k; M[1] = k * s3 - t; M[2] = k * s3 - t; M[3] = 3.0 * k - 2.0 * s3 * t;
 }
-__device__ __forceinline__ void face_minus(double kap, double D, double h, double M[4]) {
-    const double s3 = kS3, t = D * s3 / (h * h), k = kap / h;
+__device__ __forceinline__ void face_minus(double k, double t, double M[4]) {
+    const double s3 = kS3;
     M[0] = k; M[1] = -k * s3 + t; M[2] = -k * s3 + t; M[3] = 3.0 * k - 2.0 * s3 * t;
 }
-// row = '-' cell, column = '+' cell
-__device__ __forceinline__ void couple_mp(double kap, double Dm, double Dp, double h, double M[4]) {
-    const double s3 = kS3, k = kap / h, tp = Dp * s3 / (h * h), tm = Dm * s3 / (h * h);
+// row = '-' cell, column = '+' cell (tm, tp: t of the '-' and '+' cells)
+__device__ __forceinline__ void couple_mp(double k, double tm, double tp, double M[4]) {
+    const double s3 = kS3;
     M[0] = -k; M[1] = k * s3 - tp; M[2] = -k * s3 + tm; M[3] = 3.0 * k - s3 * tp - s3 * tm;
 }
 // row = '+' cell, column = '-' cell: transpose of couple_mp
-__device__ __forceinline__ void couple_pm(double kap, double Dm, double Dp, double h, double M[4]) {
+__device__ __forceinline__ void couple_pm(double k, double tm, double tp, double M[4]) {
     double T[4];
-    couple_mp(kap, Dm, Dp, h, T);
+    couple_mp(k, tm, tp, T);
     M[0] = T[0]; M[1] = T[2]; M[2] = T[1]; M[3] = T[3];
 }
 
@@ -229,12 +238,12 @@ __device__ __forceinline__ CellCoef coef_at(const MipArgs &a, int b, long long c
     return c;
 }
 
-// Diagonal 4x4 block of the MIP operator at cell (i, j).
+// Diagonal 4x4 block of the MIP operator at cell (i, j), from the material data (prepare only).
 __device__ void mip_diag(const MipArgs &a, int b, int i, int j, double A[16]) {
     const long long cell = (long long)j * a.nx + i;
     const CellCoef cc = coef_at(a, b, cell);
     for (int k = 0; k < 16; ++k) A[k] = 0.0;
-    const double vx = 12.0 * cc.Dx / (a.hx * a.hx), vy = 12.0 * cc.Dy / (a.hy * a.hy);
+    const double vx = a.vol_x * cc.Dx, vy = a.vol_y * cc.Dy;
     A[0] = cc.sa;
     A[5] = cc.sa + vx;
     A[10] = cc.sa + vy;
@@ -244,10 +253,11 @@ __device__ void mip_diag(const MipArgs &a, int b, int i, int j, double A[16]) {
     const double kr = i + 1 < a.nx ? kap_int(cc.Dx, coef_at(a, b, cell + 1).Dx, a.hx, a.kx) : kap_bnd(cc.Dx, a.hx, a.kx);
     const double kb = j > 0 ? kap_int(coef_at(a, b, cell - a.nx).Dy, cc.Dy, a.hy, a.ky) : kap_bnd(cc.Dy, a.hy, a.ky);
     const double kt = j + 1 < a.ny ? kap_int(cc.Dy, coef_at(a, b, cell + a.nx).Dy, a.hy, a.ky) : kap_bnd(cc.Dy, a.hy, a.ky);
-    face_minus(kl, cc.Dx, a.hx, M); addx_mat(M, A);
-    face_plus(kr, cc.Dx, a.hx, M);  addx_mat(M, A);
-    face_minus(kb, cc.Dy, a.hy, M); addy_mat(M, A);
-    face_plus(kt, cc.Dy, a.hy, M);  addy_mat(M, A);
+    const double tx = a.th_x * cc.Dx, ty = a.th_y * cc.Dy;
+    face_minus(kl * a.ihx, tx, M); addx_mat(M, A);
+    face_plus(kr * a.ihx, tx, M);  addx_mat(M, A);
+    face_minus(kb * a.ihy, ty, M); addy_mat(M, A);
+    face_plus(kt * a.ihy, ty, M);  addy_mat(M, A);
 }
 
 // solve the SPD 4x4 system A z = r (Cholesky)
@@ -288,54 +298,101 @@ __device__ __forceinline__ void store4(double *v, long long idx, const double x[
     *reinterpret_cast<double4 *>(v + idx * 4) = t;
 }
 
-// y = A x at cell (i,j), with x read through a functor (to form p = z + beta p_old on the fly)
+__device__ __forceinline__ double cfv(const MipArgs &a, int b, int k, long long cell) {
+    return a.cf[((size_t)b * kCf + k) * a.ncell + cell];
+}
+
+// z = B^-1 r with the stored inverse of the diagonal block (symmetric by construction)
+__device__ __forceinline__ void binv_apply(const MipArgs &a, int b, long long cell, const double r[4],
+                                           double z[4]) {
+    const double *q = a.binv + (size_t)b * kBinv * a.ncell + cell;
+    const long long n = a.ncell;
+    const double m00 = q[0], m01 = q[n], m02 = q[2 * n], m03 = q[3 * n], m11 = q[4 * n],
+                 m12 = q[5 * n], m13 = q[6 * n], m22 = q[7 * n], m23 = q[8 * n], m33 = q[9 * n];
+    z[0] = m00 * r[0] + m01 * r[1] + m02 * r[2] + m03 * r[3];
+    z[1] = m01 * r[0] + m11 * r[1] + m12 * r[2] + m13 * r[3];
+    z[2] = m02 * r[0] + m12 * r[1] + m22 * r[2] + m23 * r[3];
+    z[3] = m03 * r[0] + m13 * r[1] + m23 * r[2] + m33 * r[3];
+}
+
+// y = A x at cell (i,j), with x read through a functor (to form p = z + beta p_old on the fly);
+// the operator's coefficients come from the per-cell planes (no divisions here)
 template <typename F>
 __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y[4]) {
     const long long cell = (long long)j * a.nx + i;
-    const CellCoef cc = coef_at(a, b, cell);
+    const double sa = cfv(a, b, 0, cell), Dx = cfv(a, b, 1, cell), Dy = cfv(a, b, 2, cell);
     double xc[4], xn[4], M[4];
     xat(cell, xc);
-    const double vx = 12.0 * cc.Dx / (a.hx * a.hx), vy = 12.0 * cc.Dy / (a.hy * a.hy);
-    y[0] = cc.sa * xc[0];
-    y[1] = (cc.sa + vx) * xc[1];
-    y[2] = (cc.sa + vy) * xc[2];
-    y[3] = (cc.sa + vx + vy) * xc[3];
+    const double vx = a.vol_x * Dx, vy = a.vol_y * Dy;
+    const double tx = a.th_x * Dx, ty = a.th_y * Dy;
+    y[0] = sa * xc[0];
+    y[1] = (sa + vx) * xc[1];
+    y[2] = (sa + vy) * xc[2];
+    y[3] = (sa + vx + vy) * xc[3];
     if (i > 0) {
-        const double Dl = coef_at(a, b, cell - 1).Dx;
-        const double k = kap_int(Dl, cc.Dx, a.hx, a.kx);
-        face_minus(k, cc.Dx, a.hx, M); addx(M, xc, y);
+        const double tl = a.th_x * cfv(a, b, 1, cell - 1);
+        const double k = cfv(a, b, 3, cell - 1) * a.ihx;
+        face_minus(k, tx, M); addx(M, xc, y);
         xat(cell - 1, xn);
-        couple_pm(k, Dl, cc.Dx, a.hx, M); addx(M, xn, y);
+        couple_pm(k, tl, tx, M); addx(M, xn, y);
     } else {
-        face_minus(kap_bnd(cc.Dx, a.hx, a.kx), cc.Dx, a.hx, M); addx(M, xc, y);
+        face_minus(fmax(a.kx, kMipC * Dx * a.ihx) * a.ihx, tx, M); addx(M, xc, y);
     }
     if (i + 1 < a.nx) {
-        const double Dr = coef_at(a, b, cell + 1).Dx;
-        const double k = kap_int(cc.Dx, Dr, a.hx, a.kx);
-        face_plus(k, cc.Dx, a.hx, M); addx(M, xc, y);
+        const double tr = a.th_x * cfv(a, b, 1, cell + 1);
+        const double k = cfv(a, b, 3, cell) * a.ihx;
+        face_plus(k, tx, M); addx(M, xc, y);
         xat(cell + 1, xn);
-        couple_mp(k, cc.Dx, Dr, a.hx, M); addx(M, xn, y);
+        couple_mp(k, tx, tr, M); addx(M, xn, y);
     } else {
-        face_plus(kap_bnd(cc.Dx, a.hx, a.kx), cc.Dx, a.hx, M); addx(M, xc, y);
+        face_plus(fmax(a.kx, kMipC * Dx * a.ihx) * a.ihx, tx, M); addx(M, xc, y);
     }
     if (j > 0) {
-        const double Db = coef_at(a, b, cell - a.nx).Dy;
-        const double k = kap_int(Db, cc.Dy, a.hy, a.ky);
-        face_minus(k, cc.Dy, a.hy, M); addy(M, xc, y);
+        const double tb = a.th_y * cfv(a, b, 2, cell - a.nx);
+        const double k = cfv(a, b, 4, cell - a.nx) * a.ihy;
+        face_minus(k, ty, M); addy(M, xc, y);
         xat(cell - a.nx, xn);
-        couple_pm(k, Db, cc.Dy, a.hy, M); addy(M, xn, y);
+        couple_pm(k, tb, ty, M); addy(M, xn, y);
     } else {
-        face_minus(kap_bnd(cc.Dy, a.hy, a.ky), cc.Dy, a.hy, M); addy(M, xc, y);
+        face_minus(fmax(a.ky, kMipC * Dy * a.ihy) * a.ihy, ty, M); addy(M, xc, y);
     }
     if (j + 1 < a.ny) {
-        const double Dt = coef_at(a, b, cell + a.nx).Dy;
-        const double k = kap_int(cc.Dy, Dt, a.hy, a.ky);
-        face_plus(k, cc.Dy, a.hy, M); addy(M, xc, y);
+        const double tt = a.th_y * cfv(a, b, 2, cell + a.nx);
+        const double k = cfv(a, b, 4, cell) * a.ihy;
+        face_plus(k, ty, M); addy(M, xc, y);
         xat(cell + a.nx, xn);
-        couple_mp(k, cc.Dy, Dt, a.hy, M); addy(M, xn, y);
+        couple_mp(k, ty, tt, M); addy(M, xn, y);
     } else {
-        face_plus(kap_bnd(cc.Dy, a.hy, a.ky), cc.Dy, a.hy, M); addy(M, xc, y);
+        face_plus(fmax(a.ky, kMipC * Dy * a.ihy) * a.ihy, ty, M); addy(M, xc, y);
     }
+}
+
+// per-cell operator data and the inverse of the diagonal block, once per solve
+__global__ void mip_prepare_kernel(MipArgs a, double *cf, double *binv) {
+    const int b = blockIdx.y;
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.ncell) return;
+    const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+    const CellCoef cc = coef_at(a, b, cell);
+    const double kr = i + 1 < a.nx ? kap_int(cc.Dx, coef_at(a, b, cell + 1).Dx, a.hx, a.kx) : 0.0;
+    const double kt = j + 1 < a.ny ? kap_int(cc.Dy, coef_at(a, b, cell + a.nx).Dy, a.hy, a.ky) : 0.0;
+    double *c = cf + (size_t)b * kCf * a.ncell + cell;
+    c[0] = cc.sa;
+    c[1 * a.ncell] = cc.Dx;
+    c[2 * a.ncell] = cc.Dy;
+    c[3 * a.ncell] = kr;
+    c[4 * a.ncell] = kt;
+    double A[16], col[4][4];
+    mip_diag(a, b, i, j, A);
+    for (int k = 0; k < 4; ++k) {
+        double e[4] = {0.0, 0.0, 0.0, 0.0};
+        e[k] = 1.0;
+        spd4_solve(A, e, col[k]);        // column k of A^-1
+    }
+    double *q = binv + (size_t)b * kBinv * a.ncell + cell;
+    int idx = 0;
+    for (int r = 0; r < 4; ++r)
+        for (int k = r; k < 4; ++k) q[(idx++) * a.ncell] = col[k][r];
 }
 
 // fixed-order block sum of two values; thread 0 returns the totals
@@ -382,7 +439,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
     if (cell < a.ncell) {
         const long long gi = (long long)b * a.ncell + cell;
         const double ss = a.sigma_s[gi];
-        double rs[4], rp[4], rv[4], zv[4], A[16];
+        double rs[4], rp[4], rv[4], zv[4];
         load4(rho_star, gi, rs);
         load4(rho_prev, gi, rp);
         for (int k = 0; k < 4; ++k) rv[k] = ss * (rs[k] - rp[k]);
@@ -390,9 +447,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
         store4(x, gi, zero);
         store4(r, gi, rv);
         if (bj) {
-            const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
-            mip_diag(a, b, i, j, A);
-            spd4_solve(A, rv, zv);
+            binv_apply(a, b, cell, rv, zv);
             if (bj == 2)
                 for (int k = 0; k < 4; ++k) zv[k] *= kOmegaDG;
             store4(z, gi, zv);
@@ -479,7 +534,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, 
     double rz_new = 0.0, rr = 0.0;
     if (cell < a.ncell) {
         const long long gi = (long long)b * a.ncell + cell;
-        double pv[4], qv[4], xv[4], rv[4], zv[4], A[16];
+        double pv[4], qv[4], xv[4], rv[4], zv[4];
         load4(p, gi, pv);
         load4(q, gi, qv);
         load4(x, gi, xv);
@@ -488,9 +543,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, 
         store4(x, gi, xv);
         store4(r, gi, rv);
         if (bj) {
-            const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
-            mip_diag(a, b, i, j, A);
-            spd4_solve(A, rv, zv);
+            binv_apply(a, b, cell, rv, zv);
             if (bj == 2)
                 for (int k = 0; k < 4; ++k) zv[k] *= kOmegaDG;
             store4(z, gi, zv);
@@ -587,10 +640,17 @@ __global__ void mg_restrict_dg_kernel(MipArgs a, const int *state, const double 
     b0[(size_t)b * g.nv + v] = pt_vertex(t + (size_t)b * a.ncell * 4, a.nx, a.ny, x, y, sqrt(a.hx * a.hy));
 }
 
-// ---- vertex grids: 9-point stencils S[b][v][(dy+1)*3 + dx+1]
-__device__ __forceinline__ double stencil_apply(const double *S, const double *x, VG g, int vx,
+// ---- vertex grids: 9-point stencils in planes, S[b][(dy+1)*3 + dx+1][v], and a tenth plane
+// S[b][9][v] = omega / diagonal (kStencilPlanes planes of nv values per instance)
+__device__ __forceinline__ const double *st_of(const double *S, int b, long long nv) {
+    return S + (size_t)b * kStencilPlanes * nv;
+}
+__device__ __forceinline__ double *st_of(double *S, int b, long long nv) {
+    return S + (size_t)b * kStencilPlanes * nv;
+}
+__device__ __forceinline__ double stencil_apply(const double *Sb, const double *x, VG g, int vx,
                                                 int vy) {
-    const double *st = S + (long long)(vy * g.nvx + vx) * 9;
+    const double *st = Sb + (long long)vy * g.nvx + vx;
     double s = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int yy = vy + dy;
@@ -598,7 +658,7 @@ __device__ __forceinline__ double stencil_apply(const double *S, const double *x
         for (int dx = -1; dx <= 1; ++dx) {
             const int xx = vx + dx;
             if (xx < 0 || xx >= g.nvx) continue;
-            s += st[(dy + 1) * 3 + dx + 1] * x[(long long)yy * g.nvx + xx];
+            s += st[((dy + 1) * 3 + dx + 1) * g.nv] * x[(long long)yy * g.nvx + xx];
         }
     }
     return s;
@@ -613,12 +673,12 @@ __global__ void mg_vertex_kernel(const int *state, VG g, const double *S, const 
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
-    const double *Sb = S + o * 9;
-    const double diag = Sb[v * 9 + 4];
+    const double *Sb = st_of(S, b, g.nv);
+    const double wd = Sb[9 * g.nv + v];
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
     double res;
-    if (mode == 0) res = kOmegaV * bv[o + v] / diag;
-    else if (mode == 1) res = x_in[o + v] + kOmegaV * (bv[o + v] - stencil_apply(Sb, x_in + o, g, vx, vy)) / diag;
+    if (mode == 0) res = wd * bv[o + v];
+    else if (mode == 1) res = x_in[o + v] + wd * (bv[o + v] - stencil_apply(Sb, x_in + o, g, vx, vy));
     else if (mode == 2) res = bv[o + v] - stencil_apply(Sb, x_in + o, g, vx, vy);
     else res = stencil_apply(Sb, x_in + o, g, vx, vy);
     out[o + v] = res;
@@ -697,7 +757,17 @@ __global__ void mg_scatter_kernel(const int *state, VG g, int cx, int cy, const 
     const int mx = ((cx - x) % 3 + 3) % 3, my = ((cy - y) % 3 + 3) % 3;
     const int dx = mx == 2 ? -1 : mx, dy = my == 2 ? -1 : my;
     if (x + dx < 0 || x + dx >= g.nvx || y + dy < 0 || y + dy >= g.nvy) return;
-    S[((size_t)b * g.nv + v) * 9 + (dy + 1) * 3 + dx + 1] = z[(size_t)b * g.nv + v];
+    st_of(S, b, g.nv)[((dy + 1) * 3 + dx + 1) * g.nv + v] = z[(size_t)b * g.nv + v];
+}
+
+// omega / diagonal plane of the smoother
+__global__ void mg_wdiag_kernel(const int *state, VG g, double *S) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.nv) return;
+    double *Sb = st_of(S, b, g.nv);
+    Sb[9 * g.nv + v] = kOmegaV / Sb[4 * g.nv + v];
 }
 
 __global__ void mg_zero_kernel(const int *state, long long n, double *x) {
@@ -715,13 +785,14 @@ __global__ void __launch_bounds__(256) mg_coarse_kernel(const int *state, VG g, 
     if (state[b] != 1) return;
     double *xa = sh, *xb = sh + g.nv;
     const size_t o = (size_t)b * g.nv;
-    const double *Sb = S + o * 9;
-    for (long long v = threadIdx.x; v < g.nv; v += blockDim.x) xa[v] = kOmegaV * bv[o + v] / Sb[v * 9 + 4];
+    const double *Sb = st_of(S, b, g.nv);
+    const double *wd = Sb + 9 * g.nv;
+    for (long long v = threadIdx.x; v < g.nv; v += blockDim.x) xa[v] = wd[v] * bv[o + v];
     __syncthreads();
     for (int k = 1; k < nsweep; ++k) {
         for (long long v = threadIdx.x; v < g.nv; v += blockDim.x) {
             const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-            xb[v] = xa[v] + kOmegaV * (bv[o + v] - stencil_apply(Sb, xa, g, vx, vy)) / Sb[v * 9 + 4];
+            xb[v] = xa[v] + wd[v] * (bv[o + v] - stencil_apply(Sb, xa, g, vx, vy));
         }
         __syncthreads();
         double *t = xa; xa = xb; xb = t;
@@ -752,14 +823,13 @@ __global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const i
             p_cell(xb, g.nvx, (int)(c % a.nx), (int)(c / a.nx), sqa, pc);
             for (int k = 0; k < 4; ++k) v[k] += pc[k];
         };
-        double y[4], zc[4], rv[4], dz[4], zn[4], A[16];
+        double y[4], zc[4], rv[4], dz[4], zn[4];
         const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
         mip_apply(a, b, i, j, zat, y);
         zat(cell, zc);
         load4(r, base + cell, rv);
         for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
-        mip_diag(a, b, i, j, A);
-        spd4_solve(A, y, dz);
+        binv_apply(a, b, cell, y, dz);
         for (int k = 0; k < 4; ++k) { zn[k] = zc[k] + kOmegaDG * dz[k]; rz += rv[k] * zn[k]; }
         store4(z_out, base + cell, zn);
     }
@@ -774,10 +844,11 @@ __global__ void mg_vpre_kernel(const int *state, VG g, const double *S, const do
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
-    const double *Sb = S + o * 9;
+    const double *Sb = st_of(S, b, g.nv);
+    const double *wd = Sb + 9 * g.nv;
     const double *bb = bv + o;
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-    const double *st = Sb + v * 9;
+    const double *st = Sb + v;
     double sx1 = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int yy = vy + dy;
@@ -786,11 +857,11 @@ __global__ void mg_vpre_kernel(const int *state, VG g, const double *S, const do
             const int xx = vx + dx;
             if (xx < 0 || xx >= g.nvx) continue;
             const long long w = (long long)yy * g.nvx + xx;
-            sx1 += st[(dy + 1) * 3 + dx + 1] * (kOmegaV * bb[w] / Sb[w * 9 + 4]);
+            sx1 += st[((dy + 1) * 3 + dx + 1) * g.nv] * (wd[w] * bb[w]);
         }
     }
-    const double x1 = kOmegaV * bb[v] / st[4];
-    x2[o + v] = x1 + kOmegaV * (bb[v] - sx1) / st[4];
+    const double x1 = wd[v] * bb[v];
+    x2[o + v] = x1 + wd[v] * (bb[v] - sx1);
 }
 
 __device__ __forceinline__ double prolong_at(const double *c, VG gc, int x, int y) {
@@ -808,10 +879,10 @@ __global__ void mg_vpost1_kernel(const int *state, VG g, const double *S, const 
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
-    const double *Sb = S + o * 9;
+    const double *Sb = st_of(S, b, g.nv);
     const double *cb = xc + (size_t)b * gc.nv;
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-    const double *st = Sb + v * 9;
+    const double *st = Sb + v;
     double sx3 = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int yy = vy + dy;
@@ -820,11 +891,11 @@ __global__ void mg_vpost1_kernel(const int *state, VG g, const double *S, const 
             const int xx = vx + dx;
             if (xx < 0 || xx >= g.nvx) continue;
             const long long w = (long long)yy * g.nvx + xx;
-            sx3 += st[(dy + 1) * 3 + dx + 1] * (x2[o + w] + prolong_at(cb, gc, xx, yy));
+            sx3 += st[((dy + 1) * 3 + dx + 1) * g.nv] * (x2[o + w] + prolong_at(cb, gc, xx, yy));
         }
     }
     const double x3 = x2[o + v] + prolong_at(cb, gc, vx, vy);
-    x4[o + v] = x3 + kOmegaV * (bv[o + v] - sx3) / st[4];
+    x4[o + v] = x3 + Sb[9 * g.nv + v] * (bv[o + v] - sx3);
 }
 
 
@@ -855,16 +926,17 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
     for (long long v = t; v < sl.nv[0]; v += nt) bv[0][v] = b_top[(size_t)b * sl.nv[0] + v];
     __syncthreads();
     auto grid_of = [&](int l) { VG g; g.nvx = sl.nvx[l]; g.nvy = sl.nvy[l]; g.nv = sl.nv[l]; return g; };
-    auto S_of = [&](int l) { return sl.S[l] + (size_t)b * sl.nv[l] * 9; };
+    auto S_of = [&](int l) { return st_of(sl.S[l], b, sl.nv[l]); };
     // down: two pre-smoothing sweeps, residual, restriction
     for (int l = 0; l < sl.n - 1; ++l) {
         const VG g = grid_of(l);
         const double *S = S_of(l);
-        for (long long v = t; v < g.nv; v += nt) xa[l][v] = kOmegaV * bv[l][v] / S[v * 9 + 4];
+        const double *wd = S + 9 * g.nv;
+        for (long long v = t; v < g.nv; v += nt) xa[l][v] = wd[v] * bv[l][v];
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
             const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-            xb[l][v] = xa[l][v] + kOmegaV * (bv[l][v] - stencil_apply(S, xa[l], g, vx, vy)) / S[v * 9 + 4];
+            xb[l][v] = xa[l][v] + wd[v] * (bv[l][v] - stencil_apply(S, xa[l], g, vx, vy));
         }
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
@@ -894,12 +966,13 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
         const int l = sl.n - 1;
         const VG g = grid_of(l);
         const double *S = S_of(l);
-        for (long long v = t; v < g.nv; v += nt) xb[l][v] = kOmegaV * bv[l][v] / S[v * 9 + 4];
+        const double *wd = S + 9 * g.nv;
+        for (long long v = t; v < g.nv; v += nt) xb[l][v] = wd[v] * bv[l][v];
         __syncthreads();
         for (int k = 1; k < nsweep; ++k) {
             for (long long v = t; v < g.nv; v += nt) {
                 const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-                xa[l][v] = xb[l][v] + kOmegaV * (bv[l][v] - stencil_apply(S, xb[l], g, vx, vy)) / S[v * 9 + 4];
+                xa[l][v] = xb[l][v] + wd[v] * (bv[l][v] - stencil_apply(S, xb[l], g, vx, vy));
             }
             __syncthreads();
             for (long long v = t; v < g.nv; v += nt) xb[l][v] = xa[l][v];
@@ -910,6 +983,7 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
     for (int l = sl.n - 2; l >= 0; --l) {
         const VG g = grid_of(l), gc = grid_of(l + 1);
         const double *S = S_of(l);
+        const double *wd = S + 9 * g.nv;
         for (long long v = t; v < g.nv; v += nt) {
             const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
             const int X0 = x / 2, Y0 = y / 2;
@@ -921,12 +995,12 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
             const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-            xa[l][v] = xb[l][v] + kOmegaV * (bv[l][v] - stencil_apply(S, xb[l], g, vx, vy)) / S[v * 9 + 4];
+            xa[l][v] = xb[l][v] + wd[v] * (bv[l][v] - stencil_apply(S, xb[l], g, vx, vy));
         }
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
             const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-            xb[l][v] = xa[l][v] + kOmegaV * (bv[l][v] - stencil_apply(S, xa[l], g, vx, vy)) / S[v * 9 + 4];
+            xb[l][v] = xa[l][v] + wd[v] * (bv[l][v] - stencil_apply(S, xa[l], g, vx, vy));
         }
         __syncthreads();
     }
@@ -946,8 +1020,22 @@ MipArgs mip_args(const rte_problem *p, int nblk) {
     a.cyy = p->cyy;
     a.kx = p->kmin_x;
     a.ky = p->kmin_y;
+    a.ihx = 1.0 / p->hx;
+    a.ihy = 1.0 / p->hy;
+    a.th_x = kS3 / (p->hx * p->hx);
+    a.th_y = kS3 / (p->hy * p->hy);
+    a.vol_x = 12.0 / (p->hx * p->hx);
+    a.vol_y = 12.0 / (p->hy * p->hy);
     a.sigma_t = p->sigma_t;
     a.sigma_s = p->sigma_s;
+    a.cf = nullptr;
+    a.binv = nullptr;
+    return a;
+}
+MipArgs mip_args(const rte_problem *p, const CGSpace &c) {
+    MipArgs a = mip_args(p, c.nblk);
+    a.cf = c.cf;
+    a.binv = c.binv;
     return a;
 }
 
@@ -1043,16 +1131,17 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
 }
 }  // namespace
 
-hipError_t launch_mg_build(const rte_problem *p, const CGSpace &c, hipStream_t s) {
-    const MipArgs a = mip_args(p, c.nblk);
-    const int *all = nullptr;     // the hierarchy is built for every instance of the batch
+hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, hipStream_t s) {
+    const MipArgs a = mip_args(p, c);
+    const int *all = nullptr;     // built for every instance of the batch
     const dim3 gc(blocks_for(p->ncell, 256), p->B);
+    hipLaunchKernelGGL(mip_prepare_kernel, gc, dim3(256), 0, s, a, c.cf, c.binv);
     for (int l = 0; l < c.mg.L; ++l) {
         const MGLevel &L = c.mg.lv[l];
         const VG g = vg_of(L);
         const dim3 gv(blocks_for(L.nv, 256), p->B);
-        hipLaunchKernelGGL(mg_zero_kernel, dim3(blocks_for(L.nv * 9, 256), p->B), dim3(256), 0, s,
-                           all, L.nv * 9, L.S);
+        hipLaunchKernelGGL(mg_zero_kernel, dim3(blocks_for(L.nv * kStencilPlanes, 256), p->B),
+                           dim3(256), 0, s, all, L.nv * kStencilPlanes, L.S);
         for (int cy = 0; cy < 3; ++cy)
             for (int cx = 0; cx < 3; ++cx) {
                 if (l == 0) {
@@ -1070,12 +1159,13 @@ hipError_t launch_mg_build(const rte_problem *p, const CGSpace &c, hipStream_t s
                 }
                 hipLaunchKernelGGL(mg_scatter_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.rv, L.S);
             }
+        hipLaunchKernelGGL(mg_wdiag_kernel, gv, dim3(256), 0, s, all, g, L.S);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot_id, hipStream_t s) {
-    const MipArgs a = mip_args(p, c.nblk);
+    const MipArgs a = mip_args(p, c);
     const dim3 gc(blocks_for(p->ncell, 256), p->B);
     const MGLevel &L0 = c.mg.lv[0];
     const VG g0 = vg_of(L0);
@@ -1107,20 +1197,20 @@ hipError_t launch_dsa1d(const rte_problem *p, const double *rho_star, const doub
 hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double *rho_star,
                            const double *rho_prev, const int *kind, int want_kind, double rtol,
                            hipStream_t s) {
-    const MipArgs a = mip_args(p, c.nblk);
+    const MipArgs a = mip_args(p, c);
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, c.n_running);
     // bj = 1: block-Jacobi preconditioner; bj = 2: first smoothing step of the multigrid one
     const int bj = c.mg.L == 0 ? 1 : 2;
     hipLaunchKernelGGL(cg_setup_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, rho_star,
                        rho_prev, kind, want_kind, c.x, c.r, c.z, c.part, c.state, c.iters,
                        c.n_running, bj);
-    if (bj == 2) return launch_mg_precond(p, c, 0, s);    // hierarchy built by launch_mg_build
+    if (bj == 2) return launch_mg_precond(p, c, 0, s);    // hierarchy built by launch_dsa_build
     return hipGetLastError();
 }
 
 hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, double rtol,
                                int maxit, hipStream_t s) {
-    const MipArgs a = mip_args(p, c.nblk);
+    const MipArgs a = mip_args(p, c);
     double *p_new = (it & 1) ? c.p1 : c.p0;
     const double *p_old = (it & 1) ? c.p0 : c.p1;
     const double *z = c.mg.L == 0 ? c.z : c.mg.t;    // preconditioned residual

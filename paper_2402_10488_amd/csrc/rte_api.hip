@@ -86,6 +86,8 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
             L.cg.iters = c.take<int>(B);
             L.cg.state = c.take<int>(B);
             L.cg.n_running = c.take<int>(1);
+            L.cg.cf = c.take<double>(B * (size_t)p->ncell * 5);
+            L.cg.binv = c.take<double>(B * (size_t)p->ncell * 10);
             int nvx[kMaxLevels], nvy[kMaxLevels];
             L.cg.mg.L = p->dsa_mg ? mg_levels(p->nx, p->ny, nvx, nvy) : 0;
             for (int l = 0; l < L.cg.mg.L; ++l) {
@@ -93,7 +95,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
                 g.nvx = nvx[l];
                 g.nvy = nvy[l];
                 g.nv = (long long)nvx[l] * nvy[l];
-                g.S = c.take<double>(B * (size_t)g.nv * 9);
+                g.S = c.take<double>(B * (size_t)g.nv * kStencilPlanes);
                 g.xa = c.take<double>(B * (size_t)g.nv);
                 g.xb = c.take<double>(B * (size_t)g.nv);
                 g.bv = c.take<double>(B * (size_t)g.nv);
@@ -590,7 +592,7 @@ int rte_dsa_correct(const rte_problem *p, const double *rho_star, const double *
     Layout L = carve(c, p, RTE_SI_DSA, nullptr, RTE_FP64, 1);
     if (!c.ok) return RTE_ENOMEM;
     int failed = 0;
-    if (p->dim == 2 && L.cg.mg.L > 0) HIPCHK(launch_mg_build(p, L.cg, s));
+    if (p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, s));
     int rc = do_dsa(p, L, rho_star, rho_prev, delta_rho, nullptr, 0, cg_rtol, cg_maxit,
                     cg_iters_out, &failed, s);
     if (rc) return rc;
@@ -636,7 +638,7 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     const int poll = o->poll_every > 0 ? o->poll_every : 1;
 
     HIPCHK(launch_init_state(p, L.st, max_iter, s));
-    if (mode != RTE_SI && p->dim == 2 && L.cg.mg.L > 0) HIPCHK(launch_mg_build(p, L.cg, s));
+    if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, s));
     HIPCHK(launch_source(p, rho, L.src, nullptr, fp32, s));
     int iterations = 0;
     bool cg_failed = false;

@@ -188,8 +188,13 @@ struct MGSpace {
 // levels for an nx x ny mesh (0 when the mesh is too small for a coarse space)
 int mg_levels(int nx, int ny, int *nvx, int *nvy);
 
+// planes per instance of a vertex-grid operator: the 9 stencil entries and omega / diagonal
+constexpr int kStencilPlanes = 10;
+
 struct CGSpace {
     MGSpace mg;
+    double *cf;                        // [B][5][ncell] per-cell operator data (2D)
+    double *binv;                      // [B][10][ncell] inverse diagonal blocks (2D)
     double *x, *r, *z, *p0, *p1, *q;   // [B][ndof]
     double *part;                      // [B][5][nblk] partial sums
     double *scal;                      // [B][8] per-instance scalars
@@ -201,8 +206,9 @@ struct CGSpace {
 hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double *rho_star,
                            const double *rho_prev, const int *kind, int want_kind, double rtol,
                            hipStream_t s);
-// Galerkin vertex operators for the instances whose CG state is running (after cg_setup)
-hipError_t launch_mg_build(const rte_problem *p, const CGSpace &c, hipStream_t s);
+// per-cell operator data, inverse diagonal blocks and (multigrid) the Galerkin vertex operators,
+// for every instance; once per solve, before any CG call
+hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, hipStream_t s);
 // z = M^-1 r and the partial sums of (r, z) in parity slot `slot`
 hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot, hipStream_t s);
 hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, double rtol,
