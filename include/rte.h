@@ -204,6 +204,36 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
                    rte_solve_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Resumable solve for serving (continuous batching).  The problem's B instances are slots; the
+ * workspace keeps every slot's Alg. 1 state between calls, so requests can be admitted into free
+ * slots while others are mid-iteration.  Each slot counts its own sweeps l (stop test, ROMSAD
+ * window 1 <= l <= theta and max_iter are per slot), so a request's result does not depend on
+ * when it was admitted or on what shares the batch.  mode, rom, opts and the workspace must be
+ * the same in every call of one session; sigma_t, sigma_s, source and inflow rows of a slot (the
+ * problem's device arrays) and its psi row may be rewritten by the caller while the slot is free.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Marks every slot free.  Call once per workspace before the first rte_sisa_admit. */
+int rte_sisa_begin(const rte_problem *p, rte_mode mode, const rte_rom *rom,
+                   const rte_solve_opts *opts, void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* Starts Alg. 1 in the listed slots (host array of n_slots distinct indices in [0, B)): resets
+ * their state, builds their diffusion operators (DSA modes) and forms their first sweep input
+ * from rho (device [B][N_DOF]; the slots' rows are the initial guesses).  Synchronises with the
+ * stream before returning.  RTE_EINVAL for an index out of range. */
+int rte_sisa_admit(const rte_problem *p, rte_mode mode, const rte_rom *rom,
+                   const rte_solve_opts *opts, const int *slots, int n_slots, const double *rho,
+                   void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* Runs up to n_iter outer iterations of every running slot (fewer if all stop), then fills
+ * active_out (host [B], nullable: 1 while a slot still iterates) and stats (n_sweep, status,
+ * change, kind per slot).  A slot that stopped holds rho^(l,*) in its row of rho.  Slots that
+ * are still running are not an error: returns RTE_OK unless a call fails. */
+int rte_sisa_iterate(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
+                     const rte_solve_opts *opts, double *rho, int n_iter, int *active_out,
+                     rte_solve_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* ------------------------------------------------------------------------------------------
  * Offline construction of the correction ROM (Sec. 3.1 POD, Sec. 3.2.1 snapshots, Sec. 3.1.1
  * reduced affine operators).  Building blocks driven by the Python offline builder; all FP64.
  * ------------------------------------------------------------------------------------------ */

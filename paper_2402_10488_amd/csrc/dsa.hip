@@ -368,8 +368,9 @@ __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y
 }
 
 // per-cell operator data and the inverse of the diagonal block, once per solve
-__global__ void mip_prepare_kernel(MipArgs a, double *cf, double *binv) {
+__global__ void mip_prepare_kernel(MipArgs a, const int *mask, double *cf, double *binv) {
     const int b = blockIdx.y;
+    if (mask && mask[b] != 1) return;
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
@@ -1131,11 +1132,12 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
 }
 }  // namespace
 
-hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, hipStream_t s) {
+hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *mask,
+                            hipStream_t s) {
     const MipArgs a = mip_args(p, c);
-    const int *all = nullptr;     // built for every instance of the batch
+    const int *all = mask;        // the selected instances (every instance if null)
     const dim3 gc(blocks_for(p->ncell, 256), p->B);
-    hipLaunchKernelGGL(mip_prepare_kernel, gc, dim3(256), 0, s, a, c.cf, c.binv);
+    hipLaunchKernelGGL(mip_prepare_kernel, gc, dim3(256), 0, s, a, mask, c.cf, c.binv);
     for (int l = 0; l < c.mg.L; ++l) {
         const MGLevel &L = c.mg.lv[l];
         const VG g = vg_of(L);

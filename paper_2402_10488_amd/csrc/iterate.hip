@@ -8,15 +8,17 @@ namespace {
 
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// kind codes written per instance after sweep l:
+// kind codes written per instance after its sweep l (l counts that instance's own sweeps, so
+// instances admitted at different times each follow Alg. 1 from their own start):
 //   0 no correction (SI), 1 DSA, 2 ROMSA, -1 converged at l, -2 stopped at max_iter
-__global__ void decide_kernel(int B, int l, int max_iter, double eps, int relative, int mode,
+__global__ void decide_kernel(int B, int max_iter, double eps, int relative, int mode,
                               int theta, double eps_romsad, unsigned long long *maxd,
                               unsigned long long *maxr, int *active, int *kind, int *n_sweep,
                               int *status, double *change, int *kinds, int *n_active) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     if (!active[b]) { kind[b] = -3; return; }
+    const int l = n_sweep[b] + 1;
     const double md = __longlong_as_double((long long)maxd[b]);
     const double mr = __longlong_as_double((long long)maxr[b]);
     maxd[b] = 0ull;
@@ -67,19 +69,20 @@ __global__ void update_kernel(int dim, long long ncell, int K, int B, int nx, in
     write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, offA, offB, v, sigma_t[t], src);
 }
 
-__global__ void init_state_kernel(int B, int max_iter, unsigned long long *maxd,
-                                  unsigned long long *maxr, int *active, int *kind, int *n_sweep,
-                                  int *status, double *change, int *kinds) {
+// start (run = 1) or idle (run = 0) the instances selected by mask (all when mask is null)
+__global__ void init_state_kernel(int B, int max_iter, const int *mask, int run,
+                                  unsigned long long *maxd, unsigned long long *maxr, int *active,
+                                  int *kind, int *n_sweep, int *status, double *change, int *kinds) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < B) {
+    if (t < B && (!mask || mask[t])) {
         maxd[t] = 0ull;
         maxr[t] = 0ull;
-        active[t] = 1;
-        kind[t] = 0;
+        active[t] = run;
+        kind[t] = run ? 0 : -3;
         n_sweep[t] = 0;
-        status[t] = RTE_ENOCONV;
+        status[t] = run ? RTE_ENOCONV : RTE_OK;
     }
-    if (t < (long long)B * max_iter) {
+    if (t < (long long)B * max_iter && (!mask || mask[t / max_iter])) {
         change[t] = 0.0;
         kinds[t] = 0;
     }
@@ -97,11 +100,10 @@ __global__ void fill_int_kernel(int *x, long long n, int v) {
 
 }  // namespace
 
-hipError_t launch_decide(const rte_problem *p, const IterState &st, int l, int max_iter,
-                         double eps, int relative, int mode, int theta, double eps_romsad,
-                         hipStream_t s) {
+hipError_t launch_decide(const rte_problem *p, const IterState &st, int max_iter, double eps,
+                         int relative, int mode, int theta, double eps_romsad, hipStream_t s) {
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, st.n_active, 1ll, 0);
-    hipLaunchKernelGGL(decide_kernel, dim3(blocks_for(p->B, 256)), dim3(256), 0, s, p->B, l,
+    hipLaunchKernelGGL(decide_kernel, dim3(blocks_for(p->B, 256)), dim3(256), 0, s, p->B,
                        max_iter, eps, relative, mode, theta, eps_romsad, st.maxd, st.maxr,
                        st.active, st.kind, st.n_sweep, st.status, st.change, st.kinds,
                        st.n_active);
@@ -127,10 +129,10 @@ hipError_t launch_update(const rte_problem *p, const IterState &st, const double
 }
 
 hipError_t launch_init_state(const rte_problem *p, const IterState &st, int max_iter,
-                             hipStream_t s) {
+                             const int *mask, int run, hipStream_t s) {
     const long long n = (long long)p->B * max_iter > p->B ? (long long)p->B * max_iter : p->B;
     hipLaunchKernelGGL(init_state_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->B,
-                       max_iter, st.maxd, st.maxr, st.active, st.kind, st.n_sweep, st.status,
+                       max_iter, mask, run, st.maxd, st.maxr, st.active, st.kind, st.n_sweep, st.status,
                        st.change, st.kinds);
     return hipGetLastError();
 }

@@ -46,6 +46,7 @@ struct Layout {
     int *rom_status;
     long long *cg_total;
     int *flag;
+    int *mask;              // [B] instances selected by rte_sisa_admit
 };
 
 int nparts_for(const rte_problem *p) { return sweep_nparts(p); }
@@ -73,6 +74,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     L.st.n_active = c.take<int>(1);
     L.cg_total = c.take<long long>(1);
     L.flag = c.take<int>(1);
+    L.mask = c.take<int>(B);
     if (mode != RTE_SI) {
         if (p->dim == 2) {
             L.cg.nblk = (int)cg_blocks_per_instance(p);
@@ -556,6 +558,90 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
     return RTE_OK;
 }
 
+
+// psi is checked only where the ROM correction runs (need_psi)
+int check_solve_args(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
+                     bool need_psi, const rte_solve_opts *o) {
+    if (!p || !o) return RTE_EINVAL;
+    if (mode != RTE_SI && mode != RTE_SI_DSA && mode != RTE_ROMSAD) return RTE_EINVAL;
+    if (mode == RTE_ROMSAD && (!rom || rom->ndof != p->ndof)) return RTE_EINVAL;
+    if (mode == RTE_ROMSAD && need_psi && rom->m > 0 && !psi) return RTE_EINVAL;
+    if (!(o->eps >= 0.0) || o->max_iter < 1 || o->theta < 0) return RTE_EINVAL;
+    if (o->precision != RTE_FP64 && o->precision != RTE_MIXED) return RTE_EINVAL;
+    if (mode != RTE_SI && p->dim == 2 && (!(o->cg_rtol > 0.0) || o->cg_maxit < 1)) return RTE_EINVAL;
+    return RTE_OK;
+}
+
+// Up to n_max outer iterations (Alg. 1; Alg. 2 for ROMSAD) of every active instance; returns
+// early once no instance is active (looked at every poll_every iterations).
+int run_iterations(const rte_problem *p, const Layout &L, rte_mode mode, const rte_rom *rom,
+                   const double *psi, const rte_solve_opts *o, double *rho, void *f_out, int n_max,
+                   hipStream_t s, int *iterations, bool *cg_failed) {
+    const int fp32 = o->precision == RTE_MIXED;
+    double eps_romsad = o->eps_romsad;
+    if (mode == RTE_ROMSAD && eps_romsad < 0.0)
+        eps_romsad = 0.1 * std::max(rom->eps_train, rom->eps_pod);   // eq. (romsad_parameters)
+    const int poll = o->poll_every > 0 ? o->poll_every : 1;
+    for (int l = 1; l <= n_max; ++l) {
+        int rc = do_sweep(p, L, L.src, f_out, L.rho_star, rho, L.st.active, 0, fp32, s);
+        if (rc) return rc;
+        HIPCHK(launch_decide(p, L.st, o->max_iter, o->eps, o->relative, (int)mode, o->theta,
+                             eps_romsad, s));
+        const double *delta = nullptr;
+        if (mode == RTE_ROMSAD) {
+            ProfScope ps(RTE_PROF_ROM, s);
+            HIPCHK(launch_rom_correct(p, rom, psi, L.rho_star, rho, L.delta, L.rom_status,
+                                      L.st.kind, 2, L.rom, fp32, s));
+            delta = L.delta;
+        }
+        if (mode != RTE_SI) {
+            int failed = 0;
+            rc = do_dsa(p, L, L.rho_star, rho, L.delta, L.st.kind, 1, o->cg_rtol, o->cg_maxit,
+                        L.cg.iters, &failed, s);
+            if (rc) return rc;
+            *cg_failed = *cg_failed || failed;
+            delta = L.delta;
+        }
+        HIPCHK(launch_update(p, L.st, L.rho_star, delta, rho, L.src, fp32, s));
+        *iterations = l;
+        if (l % poll == 0 || l == n_max) {
+            int n_active = 0;
+            HIPCHK(hipMemcpyAsync(&n_active, L.st.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (n_active == 0) break;
+        }
+    }
+    return RTE_OK;
+}
+
+// host-visible results, copied on the solve's stream only (other streams keep running)
+int finish_stats(const rte_problem *p, const Layout &L, int max_iter, int iterations,
+                 bool cg_failed, int *active_out, rte_solve_stats *stats, hipStream_t s) {
+    std::vector<int> status(p->B);
+    const auto d2h = hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(status.data(), L.st.status, sizeof(int) * p->B, d2h, s));
+    if (active_out) HIPCHK(hipMemcpyAsync(active_out, L.st.active, sizeof(int) * p->B, d2h, s));
+    if (stats) {
+        if (stats->n_sweep)
+            HIPCHK(hipMemcpyAsync(stats->n_sweep, L.st.n_sweep, sizeof(int) * p->B, d2h, s));
+        if (stats->change)
+            HIPCHK(hipMemcpyAsync(stats->change, L.st.change, sizeof(double) * p->B * max_iter, d2h, s));
+        if (stats->kind)
+            HIPCHK(hipMemcpyAsync(stats->kind, L.st.kinds, sizeof(int) * p->B * max_iter, d2h, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    int rc = RTE_OK;
+    for (int b = 0; b < p->B; ++b)
+        if (status[b] != RTE_OK) rc = RTE_ENOCONV;
+    if (stats) {
+        if (stats->status) std::memcpy(stats->status, status.data(), sizeof(int) * p->B);
+        stats->cg_iterations = 0;
+        stats->iterations = iterations;
+    }
+    if (cg_failed && rc == RTE_OK) rc = RTE_ECG;
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -592,7 +678,7 @@ int rte_dsa_correct(const rte_problem *p, const double *rho_star, const double *
     Layout L = carve(c, p, RTE_SI_DSA, nullptr, RTE_FP64, 1);
     if (!c.ok) return RTE_ENOMEM;
     int failed = 0;
-    if (p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, s));
+    if (p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
     int rc = do_dsa(p, L, rho_star, rho_prev, delta_rho, nullptr, 0, cg_rtol, cg_maxit,
                     cg_iters_out, &failed, s);
     if (rc) return rc;
@@ -620,78 +706,77 @@ int rte_rom_correct(const rte_problem *p, const rte_rom *rom, const double *psi,
 int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
                    const rte_solve_opts *o, double *rho, void *f_out, rte_solve_stats *stats,
                    void *ws, size_t ws_bytes, rte_stream_t stream) {
-    if (!p || !o || !rho || !ws) return RTE_EINVAL;
-    if (mode != RTE_SI && mode != RTE_SI_DSA && mode != RTE_ROMSAD) return RTE_EINVAL;
-    if (mode == RTE_ROMSAD && (!rom || (rom->m > 0 && !psi) || rom->ndof != p->ndof)) return RTE_EINVAL;
-    if (!(o->eps >= 0.0) || o->max_iter < 1 || o->theta < 0) return RTE_EINVAL;
-    if (o->precision != RTE_FP64 && o->precision != RTE_MIXED) return RTE_EINVAL;
-    if (mode != RTE_SI && p->dim == 2 && (!(o->cg_rtol > 0.0) || o->cg_maxit < 1)) return RTE_EINVAL;
+    if (!rho || !ws) return RTE_EINVAL;
+    int rc = check_solve_args(p, mode, rom, psi, true, o);
+    if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const int max_iter = o->max_iter;
     Carver c(ws, ws_bytes);
-    Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, max_iter);
+    Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, o->max_iter);
     if (!c.ok) return RTE_ENOMEM;
-    const int fp32 = o->precision == RTE_MIXED;
-    double eps_romsad = o->eps_romsad;
-    if (mode == RTE_ROMSAD && eps_romsad < 0.0)
-        eps_romsad = 0.1 * std::max(rom->eps_train, rom->eps_pod);   // eq. (romsad_parameters)
-    const int poll = o->poll_every > 0 ? o->poll_every : 1;
-
-    HIPCHK(launch_init_state(p, L.st, max_iter, s));
-    if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, s));
-    HIPCHK(launch_source(p, rho, L.src, nullptr, fp32, s));
+    HIPCHK(launch_init_state(p, L.st, o->max_iter, nullptr, 1, s));
+    if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
+    HIPCHK(launch_source(p, rho, L.src, nullptr, o->precision == RTE_MIXED, s));
     int iterations = 0;
     bool cg_failed = false;
-    for (int l = 1; l <= max_iter; ++l) {
-        int rc = do_sweep(p, L, L.src, f_out, L.rho_star, rho, L.st.active, 0, fp32, s);
-        if (rc) return rc;
-        HIPCHK(launch_decide(p, L.st, l, max_iter, o->eps, o->relative, (int)mode, o->theta,
-                             eps_romsad, s));
-        const double *delta = nullptr;
-        if (mode == RTE_ROMSAD) {
-            ProfScope ps(RTE_PROF_ROM, s);
-            HIPCHK(launch_rom_correct(p, rom, psi, L.rho_star, rho, L.delta, L.rom_status,
-                                      L.st.kind, 2, L.rom, fp32, s));
-            delta = L.delta;
-        }
-        if (mode != RTE_SI) {
-            int failed = 0;
-            rc = do_dsa(p, L, L.rho_star, rho, L.delta, L.st.kind, 1, o->cg_rtol, o->cg_maxit,
-                        L.cg.iters, &failed, s);
-            if (rc) return rc;
-            cg_failed = cg_failed || failed;
-            delta = L.delta;
-        }
-        HIPCHK(launch_update(p, L.st, L.rho_star, delta, rho, L.src, fp32, s));
-        iterations = l;
-        if (l % poll == 0 || l == max_iter) {
-            int n_active = 0;
-            HIPCHK(hipMemcpyAsync(&n_active, L.st.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (n_active == 0) break;
-        }
+    rc = run_iterations(p, L, mode, rom, psi, o, rho, f_out, o->max_iter, s, &iterations, &cg_failed);
+    if (rc) return rc;
+    return finish_stats(p, L, o->max_iter, iterations, cg_failed, nullptr, stats, s);
+}
+
+int rte_sisa_begin(const rte_problem *p, rte_mode mode, const rte_rom *rom, const rte_solve_opts *o,
+                   void *ws, size_t ws_bytes, rte_stream_t stream) {
+    if (!ws) return RTE_EINVAL;
+    int rc = check_solve_args(p, mode, rom, nullptr, false, o);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, o->max_iter);
+    if (!c.ok) return RTE_ENOMEM;
+    HIPCHK(launch_init_state(p, L.st, o->max_iter, nullptr, 0, s));
+    return RTE_OK;
+}
+
+int rte_sisa_admit(const rte_problem *p, rte_mode mode, const rte_rom *rom, const rte_solve_opts *o,
+                   const int *slots, int n_slots, const double *rho, void *ws, size_t ws_bytes,
+                   rte_stream_t stream) {
+    if (!ws || !rho || n_slots < 0 || (n_slots > 0 && !slots)) return RTE_EINVAL;
+    int rc = check_solve_args(p, mode, rom, nullptr, false, o);
+    if (rc) return rc;
+    std::vector<int> mask(p->B, 0);
+    for (int k = 0; k < n_slots; ++k) {
+        if (slots[k] < 0 || slots[k] >= p->B) return RTE_EINVAL;
+        mask[slots[k]] = 1;
     }
+    if (n_slots == 0) return RTE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, o->max_iter);
+    if (!c.ok) return RTE_ENOMEM;
+    HIPCHK(hipMemcpyAsync(L.mask, mask.data(), sizeof(int) * p->B, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_init_state(p, L.st, o->max_iter, L.mask, 1, s));
+    if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, L.mask, s));
+    HIPCHK(launch_source(p, rho, L.src, L.mask, o->precision == RTE_MIXED, s));
+    // the host mask must outlive the copy
     HIPCHK(hipStreamSynchronize(s));
-    std::vector<int> status(p->B);
-    HIPCHK(hipMemcpy(status.data(), L.st.status, sizeof(int) * p->B, hipMemcpyDeviceToHost));
-    int rc = RTE_OK;
-    for (int b = 0; b < p->B; ++b)
-        if (status[b] != RTE_OK) rc = RTE_ENOCONV;
-    if (stats) {
-        if (stats->n_sweep)
-            HIPCHK(hipMemcpy(stats->n_sweep, L.st.n_sweep, sizeof(int) * p->B, hipMemcpyDeviceToHost));
-        if (stats->status) std::memcpy(stats->status, status.data(), sizeof(int) * p->B);
-        if (stats->change)
-            HIPCHK(hipMemcpy(stats->change, L.st.change, sizeof(double) * p->B * max_iter,
-                             hipMemcpyDeviceToHost));
-        if (stats->kind)
-            HIPCHK(hipMemcpy(stats->kind, L.st.kinds, sizeof(int) * p->B * max_iter,
-                             hipMemcpyDeviceToHost));
-        stats->cg_iterations = 0;
-        stats->iterations = iterations;
-    }
-    if (cg_failed && rc == RTE_OK) rc = RTE_ECG;
-    return rc;
+    return RTE_OK;
+}
+
+int rte_sisa_iterate(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
+                     const rte_solve_opts *o, double *rho, int n_iter, int *active_out,
+                     rte_solve_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream) {
+    if (!ws || !rho || n_iter < 1) return RTE_EINVAL;
+    int rc = check_solve_args(p, mode, rom, psi, true, o);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, o->max_iter);
+    if (!c.ok) return RTE_ENOMEM;
+    int iterations = 0;
+    bool cg_failed = false;
+    rc = run_iterations(p, L, mode, rom, psi, o, rho, nullptr, n_iter, s, &iterations, &cg_failed);
+    if (rc) return rc;
+    rc = finish_stats(p, L, o->max_iter, iterations, cg_failed, active_out, stats, s);
+    return rc == RTE_ENOCONV ? RTE_OK : rc;     // slots still running are not an error here
 }
 
 }  // extern "C"

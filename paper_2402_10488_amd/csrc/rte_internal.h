@@ -206,9 +206,10 @@ struct CGSpace {
 hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double *rho_star,
                            const double *rho_prev, const int *kind, int want_kind, double rtol,
                            hipStream_t s);
-// per-cell operator data, inverse diagonal blocks and (multigrid) the Galerkin vertex operators,
-// for every instance; once per solve, before any CG call
-hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, hipStream_t s);
+// per-cell operator data, inverse diagonal blocks and (multigrid) the Galerkin vertex operators
+// of the instances with mask[b] == 1 (all if mask is null); once per solve, before any CG call
+hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *mask,
+                            hipStream_t s);
 // z = M^-1 r and the partial sums of (r, z) in parity slot `slot`
 hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot, hipStream_t s);
 hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, double rtol,
@@ -241,15 +242,16 @@ struct IterState {
     int *kinds;                        // [B][max_iter]
     int *n_active;                     // [1]
 };
-hipError_t launch_decide(const rte_problem *p, const IterState &st, int l, int max_iter,
-                         double eps, int relative, int mode, int theta, double eps_romsad,
-                         hipStream_t s);
+// stop test and choice of correction after every active instance's latest sweep
+hipError_t launch_decide(const rte_problem *p, const IterState &st, int max_iter, double eps,
+                         int relative, int mode, int theta, double eps_romsad, hipStream_t s);
 // rho = rho* + delta (delta may be null) for instances corrected at iteration l; converged
 // instances keep rho* ; then src for the next sweep.
 hipError_t launch_update(const rte_problem *p, const IterState &st, const double *rho_star,
                          const double *delta, double *rho, void *src, int fp32, hipStream_t s);
+// start (run = 1) or idle (run = 0) the instances with mask[b] != 0 (all if mask is null)
 hipError_t launch_init_state(const rte_problem *p, const IterState &st, int max_iter,
-                             hipStream_t s);
+                             const int *mask, int run, hipStream_t s);
 hipError_t launch_zero(double *x, long long n, hipStream_t s);
 hipError_t launch_fill_int(int *x, long long n, int v, hipStream_t s);
 

@@ -88,6 +88,14 @@ def _load():
                                   _vp]
     L.rte_sisa_solve.argtypes = [P, ctypes.c_int, P, _vp, ctypes.POINTER(SolveOpts), _vp, _vp,
                                  ctypes.POINTER(SolveStats), _vp, ctypes.c_size_t, _vp]
+    L.rte_sisa_begin.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(SolveOpts), _vp, ctypes.c_size_t,
+                                 _vp]
+    L.rte_sisa_admit.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(SolveOpts),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp, _vp,
+                                 ctypes.c_size_t, _vp]
+    L.rte_sisa_iterate.argtypes = [P, ctypes.c_int, P, _vp, ctypes.POINTER(SolveOpts), _vp,
+                                   ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(SolveStats), _vp, ctypes.c_size_t, _vp]
     L.rte_problem_dsa_multigrid.argtypes = [P, ctypes.c_int]
     L.rte_profile_enable.argtypes = [ctypes.c_int]
     L.rte_profile_read.argtypes = [ctypes.c_int, _D, ctypes.POINTER(ctypes.c_longlong)]
@@ -101,7 +109,8 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_workspace_size", "rte_sweep", "rte_scalar_flux", "rte_dsa_correct",
             "rte_rom_correct", "rte_sisa_solve", "rte_strerror", "rte_profile_enable",
             "rte_profile_read", "rte_problem_dsa_multigrid", "rte_pod_snapshots", "rte_gram",
-            "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum"]
+            "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum",
+            "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate"]
 
 PROF = {"sweep2d": 0, "reduce": 1, "dsa": 2, "rom": 3, "sweep1d": 4}
 
@@ -304,3 +313,64 @@ def sisa_solve(p: Problem, rho_inout, mode="si_dsa", rom: Optional[Rom] = None, 
     if raise_on_error and rc not in (RTE_OK, RTE_ENOCONV):
         raise RteError(rc, "rte_sisa_solve")
     return SolveResult(rc, n_sweep, st, change, kind, stats.iterations)
+
+
+class Session:
+    """Resumable slot-based solve on one problem (rte_sisa_begin / _admit / _iterate).
+
+    The problem's B instances are slots.  Between iterate() calls the caller may rewrite the
+    material rows (problem.sigma_t, sigma_s, G, g) and psi row of a free slot and admit it.
+    ``stream`` (a torch.cuda.Stream or None for the current stream) carries every call.
+    """
+
+    def __init__(self, p: Problem, mode="romsad", rom: Optional[Rom] = None, psi=None, eps=1e-6,
+                 max_iter=500, relative=True, theta=5, eps_romsad=-1.0, cg_rtol=1e-10,
+                 cg_maxit=5000, precision="mixed", poll_every=1, stream=None):
+        import torch
+        self.p, self.mode, self.rom, self.psi = p, mode, rom, psi
+        self.max_iter = int(max_iter)
+        self.stream = stream
+        self.opts = SolveOpts(float(eps), int(max_iter), int(relative), int(theta),
+                              float(eps_romsad), float(cg_rtol), int(cg_maxit),
+                              PRECISIONS[precision], int(poll_every))
+        with self._on_stream():
+            self.ws = p.workspace(mode, rom, precision, max_iter)
+            self.rho = torch.zeros((p.B, p.ndof), dtype=torch.float64, device="cuda")
+            _check(lib.rte_sisa_begin(p.handle, MODES[mode], self._rom(), ctypes.byref(self.opts),
+                                      _ptr(self.ws), self.ws.numel(), _stream()), "rte_sisa_begin")
+        self.n_sweep = np.zeros(p.B, np.int32)
+        self.status = np.zeros(p.B, np.int32)
+        self.active = np.zeros(p.B, np.int32)
+
+    def _rom(self):
+        return self.rom.handle if self.rom else None
+
+    def _on_stream(self):
+        import contextlib
+        import torch
+        return torch.cuda.stream(self.stream) if self.stream is not None else contextlib.nullcontext()
+
+    def admit(self, slots):
+        """Start Alg. 1 in ``slots`` from the initial guesses in their rows of self.rho."""
+        slots = np.ascontiguousarray(slots, dtype=np.int32)
+        with self._on_stream():
+            _check(lib.rte_sisa_admit(self.p.handle, MODES[self.mode], self._rom(),
+                                      ctypes.byref(self.opts),
+                                      slots.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                      len(slots), _ptr(self.rho), _ptr(self.ws), self.ws.numel(),
+                                      _stream()), "rte_sisa_admit")
+        self.active[slots] = 1
+
+    def iterate(self, n_iter=1):
+        """Up to n_iter outer iterations of the running slots; returns the active flags."""
+        stats = SolveStats(self.n_sweep.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           self.status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), None, None,
+                           0, 0)
+        with self._on_stream():
+            _check(lib.rte_sisa_iterate(self.p.handle, MODES[self.mode], self._rom(),
+                                        _ptr(self.psi), ctypes.byref(self.opts), _ptr(self.rho),
+                                        int(n_iter),
+                                        self.active.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                        ctypes.byref(stats), _ptr(self.ws), self.ws.numel(),
+                                        _stream()), "rte_sisa_iterate")
+        return self.active
