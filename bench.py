@@ -5,10 +5,20 @@ parametric lattice batch: 256 instances, 128 x 128 Q1 mesh, 64 directions on the
 per-block sigma_s ~ U[0.5, 50], sigma_a ~ U[0.001, 1], FP32 sweep / FP64 corrections,
 relative tolerance 1e-6.  Inputs are seeded synthetic materials resident in HBM before timing.
 
-Prints one JSON line (see the "metric" field).  The dominant kernel's roofline comes from HIP
-events recorded by the library around every sweep launch inside the timed region.
+Further legs (reported beside the headline value, never as it):
+  - plain single-instance GPU SI-DSA on the same instances (the comparison baseline);
+  - the f-form sweep (rte_sweep writing the FP32 angular flux) against the HBM roofline;
+  - a served stream: seeded Poisson arrivals of lattice requests with meshes {64,128,256}^2 and
+    {32,64,128} directions, ROMSAD with a correction ROM per (mesh, directions) key, continuous
+    batching; solves/s and p50/p99 latency, and the same requests replayed through the plain
+    single-instance GPU SI-DSA;
+  - the CPU oracle on a bounded sample.
+
+Prints one JSON line.  The sweep kernel's roofline comes from HIP events recorded by the library
+around every sweep launch inside the timed region.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +34,12 @@ sys.path.insert(0, ROOT)
 # 8 flops FP64 density accumulation
 SWEEP_FLOPS_PER_CD = 88
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}     # MI355X published vector peaks (FP32, FP64)
+PEAK_HBM_GBS = 8000.0
+METRIC = "cell-dir updates/s; solves/s + p50/p99 latency @1e-6 vs plain GPU SI-DSA"
+# HBM traffic of the sweep kernel measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE),
+# valid only while the kernel source is the one the counters were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep2d_c2_batch_traffic.json")
+SWEEP_SRC = os.path.join(ROOT, "paper_2402_10488_amd", "csrc", "sweep.hip")
 
 
 def log(*a):
@@ -72,6 +88,122 @@ def cpu_baseline(args, mode, rom_arrays):
             "solves_per_s": 1.0 / dt}
 
 
+def sweep_source_hash():
+    with open(SWEEP_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(launch_cd):
+    """HBM bytes per launch from the committed counter summary, scaled to this launch's work
+    (None when the summary is absent or the kernel changed since the counters were taken)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sweep_src_sha256_16") != sweep_source_hash():
+        return None
+    return t["hbm_bytes_per_cd"] * launch_cd
+
+
+def f_form_leg(P, rte, reps=5):
+    """rte_sweep writing the FP32 angular flux of the whole batch: HBM roofline of the f-form."""
+    import torch
+    f = torch.empty((P.B, P.ncell, P.n_dir, P.K), dtype=torch.float32, device="cuda")
+    rho = torch.rand((P.B, P.ndof), dtype=torch.float64, device="cuda")
+    ws = P.workspace("si", None, "mixed")
+    rte.sweep(P, rho, f_out=f, precision="mixed", ws=ws)
+    torch.cuda.synchronize()
+    rte.profile_enable(True)
+    for _ in range(reps):
+        rte.sweep(P, rho, f_out=f, precision="mixed", ws=ws)
+    torch.cuda.synchronize()
+    ms, n = rte.profile_read("sweep2d")
+    rte.profile_enable(False)
+    ms /= max(n, 1)
+    cd = P.B * P.ncell * P.n_dir
+    # algorithmic bytes: the FP32 angular flux (4 dofs x 4 B per cell-direction) plus the sweep
+    # input block read once (source and sigma_t in two diagonal layouts, 10 x 4 B per cell)
+    nbytes = cd * 16 + P.B * P.ncell * 40
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    del f
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "sweep2d_kernel (f-form)",
+            "avg_launch_ms": ms, "bytes_per_launch": nbytes,
+            "cell_dir_updates_per_s": cd / (ms * 1e-3)}
+
+
+SERVE_KEYS = [(n, p) for n in (64, 128, 256) for p in (32, 64, 128)]
+
+
+def serve_capacity(n, n_phi):
+    """Slots of a key's pool: about 32M cell-direction updates per batched sweep, 4..64 slots."""
+    return int(min(64, max(4, (32 << 20) // (n * n * n_phi))))
+
+
+def serving_leg(args, rte):
+    """Seeded Poisson stream through per-key slot pools (continuous batching), ROMSAD at eps."""
+    import torch
+    import rte_workloads as W
+    from paper_2402_10488_amd import offline, serving
+    t0 = time.perf_counter()
+    roms = {}
+    for (n, p) in SERVE_KEYS:
+        train = W.c3_training(n, p, args.serve_train)
+        roms[(n, p)] = offline.build_correction_rom(train, r=args.rank, window=args.window,
+                                                    eps_train=args.eps_train)
+        torch.cuda.empty_cache()
+    t_rom = time.perf_counter() - t0
+    pools = {k: serving.KeyPool(k[0], k[1], serve_capacity(*k), "romsad", roms[k],
+                                precision=args.precision, eps=args.eps, theta=args.theta,
+                                cg_rtol=args.cg_rtol)
+             for k in SERVE_KEYS}
+    stream = W.c3_requests(args.serve_requests + args.serve_warmup, rate=args.serve_rate)
+    reqs = [serving.lattice_request(i, r.arrival, r.n, r.n_phi, r.seed) for i, r in enumerate(stream)]
+    warm, timed = reqs[:args.serve_warmup], reqs[args.serve_warmup:]
+    budget = int(args.serve_budget_gib * 2**30)
+    if warm:
+        serving.Server(pools, budget).run([serving.Request(k, 0.0, r.n, r.n_phi, r.sigma_t,
+                                                           r.sigma_s, r.G, r.g, r.psi)
+                                           for k, r in enumerate(warm)])
+    t_start = timed[0].arrival
+    timed = [serving.Request(k, r.arrival - t_start, r.n, r.n_phi, r.sigma_t, r.sigma_s, r.G,
+                             r.g, r.psi) for k, r in enumerate(timed)]
+    srv = serving.Server(pools, budget)
+    tw = time.perf_counter()
+    res = srv.run(timed)
+    wall = time.perf_counter() - tw
+    out = serving.latency_summary(res, wall)
+    out.update({"rate_req_per_s": args.serve_rate, "keys": len(SERVE_KEYS),
+                "capacity": {f"{k[0]}x{k[0]}/{k[1]}": serve_capacity(*k) for k in SERVE_KEYS},
+                "budget_gib": args.serve_budget_gib, "peak_resident_gib": srv.budget.peak / 2**30,
+                "rom_build_s": t_rom, "rom_rank": args.rank, "rom_train": args.serve_train})
+    # the same requests, one at a time, through the plain single-instance GPU SI-DSA (FCFS)
+    if args.serve_baseline > 0:
+        from paper_2402_10488_amd import quadrature
+        t_sum, cd_sum = 0.0, 0
+        sample = timed[:args.serve_baseline]
+        for q in sample:
+            vx, vy, w = quadrature.chebyshev_circle(q.n_phi)
+            dev = lambda a: torch.as_tensor(np.ascontiguousarray(a[None]), device="cuda")
+            Pi = rte.Problem(2, q.n, q.n, vx, w, dev(q.sigma_t), dev(q.sigma_s), dev(q.G),
+                             dev(q.g), dirs_y=vy)
+            wsi = Pi.workspace("si_dsa", None, args.precision, 500)
+            ri = torch.zeros((1, Pi.ndof), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            rb = rte.sisa_solve(Pi, ri, mode="si_dsa", eps=args.eps, max_iter=500,
+                                cg_rtol=args.cg_rtol, precision=args.precision, ws=wsi)
+            torch.cuda.synchronize()
+            t_sum += time.perf_counter() - tb
+            cd_sum += int(rb.n_sweep[0]) * q.n * q.n * q.n_phi
+        base = len(sample) / t_sum
+        out.update({"plain_gpu_si_dsa_solves_per_s": base,
+                    "plain_gpu_si_dsa_requests_timed": len(sample),
+                    "served_vs_plain_gpu_si_dsa": out["solves_per_s"] / base})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +224,13 @@ def main():
     ap.add_argument("--baseline-instances", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-train", type=int, default=4)
+    ap.add_argument("--no-f-form", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-warmup", type=int, default=40)
+    ap.add_argument("--serve-rate", type=float, default=100.0)
+    ap.add_argument("--serve-train", type=int, default=32)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-baseline", type=int, default=12)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -144,6 +283,7 @@ def main():
     value = cd_total / elapsed
     achieved = cd_total * SWEEP_FLOPS_PER_CD / (sweep_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    traffic = measured_traffic(cd_total / max(sweep_n, 1))
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f}s; sweeps/instance mean {sweeps.mean():.2f}; "
         f"sweep kernel {sweep_ms:.1f} ms over {sweep_n} launches; dsa {dsa_ms:.1f} ms ({dsa_n}); "
         f"rom {rom_ms:.1f} ms ({rom_n}); reduce {red_ms:.1f} ms ({red_n})")
@@ -172,7 +312,7 @@ def main():
                 "plain_instances_timed": n_base}
 
     out = {
-        "metric": "cell-direction updates/s (batched parametric ROMSAD solves)",
+        "metric": METRIC,
         "value": value,
         "unit": "cell-dir updates/s",
         "n_gpus": 1,
@@ -193,14 +333,24 @@ def main():
         "solves_per_s": solves / elapsed,
         "mean_sweeps_per_solve": float(sweeps.mean()),
         "status_not_ok_steps": bad,
+        "batch_latency_ms": {"p50": elapsed / args.steps * 1e3, "p99": elapsed / args.steps * 1e3,
+                             "note": "all instances of a step arrive together and return together"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": "sweep2d_kernel", "avg_launch_ms": sweep_ms / max(sweep_n, 1),
                      "flops_per_cd": SWEEP_FLOPS_PER_CD},
         "time_split_ms": {"sweep": sweep_ms, "reduce": red_ms, "dsa": dsa_ms, "rom": rom_ms,
                           "total": elapsed * 1e3},
     }
     out.update(base)
+    if not args.no_f_form:
+        out["roofline_f_form"] = f_form_leg(P, rte)
+        log(f"[bench] f-form sweep: {out['roofline_f_form']['achieved']:.0f} GB/s")
+    if args.serve_requests > 0:
+        del ws
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(args, rte)
+        log(f"[bench] serving: {json.dumps(out['serving'])}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, args.mode, rom_arrays)
     print(json.dumps(out))

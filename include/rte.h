@@ -17,7 +17,8 @@
  *      local dof        k = a + 2 b                 (a: x-degree, b: y-degree); K = 4 in 2D,
  *                                                   K = 2 in 1D (k = a)
  *      rho, delta_rho   [B][N_DOF], N_DOF = nx * ny * K
- *      angular flux f   [B][n_dir][N_DOF]           (the paper's f = (f_1^T..f_Nv^T)^T per instance)
+ *      angular flux f   [B][ncell][n_dir][K]        (per cell and direction the K coefficients;
+ *                                                   the paper's f_j is f[b][:, j, :])
  *      materials        [B][ny][nx]  cell-constant sigma_t, sigma_s, G
  *      inflow           [B][4]  isotropic g on the sides x=0, x=Lx, y=0, y=Ly (1D: first two)
  *  - Basis: on a cell of size hx x hy, phi_ab = L_a(xi) L_b(eta) / sqrt(hx hy) with
@@ -140,14 +141,15 @@ int rte_workspace_size(const rte_problem *p, rte_mode mode, const rte_rom *rom,
 /* One transport sweep, eq. (transport_sweep): for every instance and direction solve
  * (D_j + Sigma_t) f_j = Sigma_s rho_in + G + g_j^(bc) in upwind order.
  *   rho_in        device [B][N_DOF]
- *   f_out         device [B][n_dir][N_DOF], double (RTE_FP64) or float (RTE_MIXED); may be NULL
+ *   f_out         device [B][ncell][n_dir][K], double (RTE_FP64) or float (RTE_MIXED); may be
+ *                 NULL; 16-byte aligned (32 for double)
  *   rho_star_out  device [B][N_DOF], rho^* = sum_j w_j f_j; may be NULL
  *   zero_inflow   nonzero: use g = 0 (the kinetic correction equation's boundary condition) */
 int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
               int zero_inflow, rte_precision prec, void *ws, size_t ws_bytes, rte_stream_t stream);
 
 /* Quadrature reduction rho = sum_j w_j f_j (definition under eq. (dg_matrix_vec)).
- *   f     device [B][n_dir][N_DOF], double or float per prec;  rho_out device [B][N_DOF] */
+ *   f     device [B][ncell][n_dir][K], double or float per prec;  rho_out device [B][N_DOF] */
 int rte_scalar_flux(const rte_problem *p, const void *f, double *rho_out, rte_precision prec,
                     rte_stream_t stream);
 
@@ -197,7 +199,7 @@ typedef struct {
  *   mode RTE_SI: no correction; RTE_SI_DSA: DSA every iteration; RTE_ROMSAD: Alg. 2 switch.
  *   rho_inout  device [B][N_DOF]: initial guess in, rho^(l,*) of the stopping iteration out
  *   psi        device [B][m] (ROMSAD only)
- *   f_out      device [B][n_dir][N_DOF] angular flux of the last sweep, or NULL
+ *   f_out      device [B][ncell][n_dir][K] angular flux of the last sweep, or NULL
  * Returns RTE_ENOCONV if any instance hit max_iter (per-instance status in stats). */
 int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
                    const rte_solve_opts *opts, double *rho_inout, void *f_out,
@@ -239,7 +241,8 @@ int rte_sisa_iterate(const rte_problem *p, rte_mode mode, const rte_rom *rom, co
  * ------------------------------------------------------------------------------------------ */
 
 /* Snapshot columns delta f = f_final - f_iter per instance (Sec. 3.2.1); f_iter == NULL stands
- * for the zero initial state.  f_final, f_iter: device [B][n_dir][N_DOF];
+ * for the zero initial state.  f_final, f_iter: device [B][ncell][n_dir][K] (the sweep's layout);
+ * columns are written direction-major, entry j * N_DOF + dof;
  * column b is written at cols + b * stride (stride >= n_dir * N_DOF). */
 int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double *f_iter,
                       double *cols, long long stride, rte_stream_t stream);

@@ -45,7 +45,7 @@ __global__ void update_kernel(int dim, long long ncell, int K, int B, int nx, in
                               const int *kind, int *active, const double *rho_star,
                               const double *delta, double *rho, const double *sigma_t,
                               const double *sigma_s, const double *G, const double *cellw,
-                              double ghost, const int *offA, const int *offB, T *src) {
+                              double ghost, T *src) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)B * ncell) return;
     const int b = (int)(t / ncell);
@@ -66,7 +66,7 @@ __global__ void update_kernel(int dim, long long ncell, int K, int B, int nx, in
         rho[t * K + q] = r;
         v[q] = ss * r + (q == 0 ? g0 : 0.0);
     }
-    write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, offA, offB, v, sigma_t[t], src);
+    write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, v, sigma_t[t], src);
 }
 
 // start (run = 1) or idle (run = 0) the instances selected by mask (all when mask is null)
@@ -119,12 +119,12 @@ hipError_t launch_update(const rte_problem *p, const IterState &st, const double
         hipLaunchKernelGGL(update_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            p->dim, p->ncell, p->K, p->B, p->nx, p->ny, st.kind, st.active,
                            rho_star, delta, rho, p->sigma_t, p->sigma_s, p->source, cw, ghost,
-                           p->d_offA, p->d_offB, (float *)src);
+                           (float *)src);
     else
         hipLaunchKernelGGL(update_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            p->dim, p->ncell, p->K, p->B, p->nx, p->ny, st.kind, st.active,
                            rho_star, delta, rho, p->sigma_t, p->sigma_s, p->source, cw, ghost,
-                           p->d_offA, p->d_offB, (double *)src);
+                           (double *)src);
     return hipGetLastError();
 }
 

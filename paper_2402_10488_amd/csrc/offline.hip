@@ -23,13 +23,18 @@ constexpr double kS3 = 1.7320508075688772935;
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
-__global__ void pod_snapshot_kernel(long long len, int B, const double *f_final, const double *f_l,
-                                    double *cols, long long stride) {
+// column entry t = j * ndof + dof (direction-major) from the angular flux [B][cell][n_dir][K]
+__global__ void pod_snapshot_kernel(long long ndof, int K, int n_dir, int B, const double *f_final,
+                                    const double *f_l, double *cols, long long stride) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
+    const long long len = ndof * n_dir;
     if (t >= len) return;
-    const double a = f_final[(size_t)b * len + t];
-    cols[(size_t)b * stride + t] = f_l ? a - f_l[(size_t)b * len + t] : a;
+    const long long j = t / ndof, dof = t - j * ndof;
+    const long long c = dof / K, k = dof - c * K;
+    const size_t src = (((size_t)b * (ndof / K) + c) * n_dir + j) * K + k;
+    const double a = f_final[src];
+    cols[(size_t)b * stride + t] = f_l ? a - f_l[src] : a;
 }
 
 // G_part[split][i][j] = sum over rows in the split of X[i][row] Y[j][row] (row in class cls)
@@ -265,7 +270,8 @@ int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double 
     const long long len = (long long)p->n_dir * p->ndof;
     if (stride < len) return RTE_EINVAL;
     hipLaunchKernelGGL(pod_snapshot_kernel, dim3(cdiv(len, 256), p->B), dim3(256), 0,
-                       (hipStream_t)stream, len, p->B, f_final, f_iter, cols, stride);
+                       (hipStream_t)stream, p->ndof, p->K, p->n_dir, p->B, f_final, f_iter, cols,
+                       stride);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 

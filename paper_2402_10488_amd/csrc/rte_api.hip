@@ -47,6 +47,7 @@ struct Layout {
     long long *cg_total;
     int *flag;
     int *mask;              // [B] instances selected by rte_sisa_admit
+    double *sink;           // [8] target of the sweep's stores from idle lanes
 };
 
 int nparts_for(const rte_problem *p) { return sweep_nparts(p); }
@@ -63,6 +64,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     L.src = c.take<char>(p->dim == 2 ? B * (size_t)p->ncell * 10 * ts : B * nd * ts);
     if (p->dim == 2) L.partial = c.take<double>(B * (size_t)nparts_for(p) * nd);
     else L.fscratch = c.take<char>(B * (size_t)p->n_dir * nd * ts);
+    L.sink = c.take<double>(8);
     L.st.maxd = c.take<unsigned long long>(B);
     L.st.maxr = c.take<unsigned long long>(B);
     L.st.active = c.take<int>(B);
@@ -306,9 +308,19 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
     }
     p->d_dirs = nullptr;
     p->d_mu = p->d_w = p->d_widths = nullptr;
-    p->d_offA = p->d_offB = nullptr;
     p->d_vxy = nullptr;
     p->dsa_mg = 1;
+    {
+        int dev = 0, ncu = 0, lds = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            delete p;
+            return RTE_EDEVICE;
+        }
+        p->n_cu = ncu > 0 ? ncu : 1;
+        p->lds_per_cu = lds > 0 ? lds : 64 * 1024;
+    }
     // quadrant-sorted, padded direction table (2D)
     std::vector<DirEntry> table;
     for (int q = 0; q < 4; ++q) p->quad.count[q] = 0;
@@ -358,21 +370,6 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
         ok = ok && hipMemcpy(p->d_widths, p->widths.data(), sizeof(double) * p->nx, hipMemcpyHostToDevice) == hipSuccess;
     }
     if (d->dim == 2) {
-        // diagonal offsets of the sweep layouts (cells per diagonal, prefix sums)
-        const int nd = p->nx + p->ny - 1, nx = p->nx, ny = p->ny;
-        std::vector<int> offA(nd), offB(nd);
-        int acc_a = 0, acc_b = 0;
-        for (int dd = 0; dd < nd; ++dd) {
-            offA[dd] = acc_a;
-            offB[dd] = acc_b;
-            acc_a += std::min(dd, ny - 1) - std::max(0, dd - nx + 1) + 1;
-            acc_b += std::min(ny - 1, nx + ny - 2 - dd) - std::max(0, ny - 1 - dd) + 1;
-        }
-        ok = ok && acc_a == nx * ny && acc_b == nx * ny;
-        ok = ok && hipMalloc(&p->d_offA, sizeof(int) * nd) == hipSuccess;
-        ok = ok && hipMalloc(&p->d_offB, sizeof(int) * nd) == hipSuccess;
-        ok = ok && hipMemcpy(p->d_offA, offA.data(), sizeof(int) * nd, hipMemcpyHostToDevice) == hipSuccess;
-        ok = ok && hipMemcpy(p->d_offB, offB.data(), sizeof(int) * nd, hipMemcpyHostToDevice) == hipSuccess;
         std::vector<double> vxy(2 * (size_t)p->n_dir);
         for (int j = 0; j < p->n_dir; ++j) { vxy[j] = p->vx[j]; vxy[p->n_dir + j] = p->vy[j]; }
         ok = ok && hipMalloc(&p->d_vxy, sizeof(double) * vxy.size()) == hipSuccess;
@@ -392,8 +389,6 @@ void rte_problem_destroy(rte_problem *p) {
     if (p->d_w) (void)hipFree(p->d_w);
     if (p->d_mu) (void)hipFree(p->d_mu);
     if (p->d_widths) (void)hipFree(p->d_widths);
-    if (p->d_offA) (void)hipFree(p->d_offA);
-    if (p->d_offB) (void)hipFree(p->d_offB);
     if (p->d_vxy) (void)hipFree(p->d_vxy);
     delete p;
 }
@@ -504,6 +499,7 @@ int do_sweep(const rte_problem *p, const Layout &L, const void *src, void *f_out
         a.src = src;
         a.partial = rho_star ? L.partial : nullptr;
         a.f_out = f_out;
+        a.sink = L.sink;
         a.active = active;
         a.zero_inflow = zero_inflow;
         a.fp32 = fp32;

@@ -55,9 +55,10 @@ struct rte_problem {
     double *d_mu;             // 1D: device [n_dir] directions
     double *d_w;              // device [n_dir] weights (caller order)
     double *d_widths;         // 1D: device [nx]
-    int *d_offA, *d_offB;     // 2D: device [nx+ny-1] diagonal offsets of the sweep layouts
     double *d_vxy;            // 2D: device [2][n_dir] directions in caller order
     int dsa_mg;               // 2D diffusion CG preconditioner: 1 multigrid, 0 block-Jacobi
+    int n_cu;                 // compute units of the device the handle was created on
+    int lds_per_cu;           // bytes of LDS per compute unit (and per workgroup)
     int nparts() const;       // 2D sweep partial-sum slots per instance for the current tuning
 };
 
@@ -68,15 +69,26 @@ namespace rte {
 // and outputs diagonal by diagonal, row-ascending, makes those accesses contiguous.
 //   layout A: d = x + y,            row range y in [max(0, d-nx+1), min(d, ny-1)]
 //   layout B: d = x - y + ny - 1,   row range y in [max(0, ny-1-d), min(ny-1, nx+ny-2-d)]
-__device__ __forceinline__ int pos_a(const int *off, int nx, int ny, int x, int y) {
+// cells on the diagonals before diagonal d of an nx x ny grid: diagonal d holds
+// min(d + 1, m, nx + ny - 1 - d) cells (m = min(nx, ny), M = max(nx, ny)); the same count for
+// anti-diagonals (x + y = d) and diagonals (x - y + ny - 1 = d).  Arithmetic only, so a sweep
+// step never waits on a memory load for its position.
+__device__ __forceinline__ int diag_off(int nx, int ny, int d) {
+    const int m = nx < ny ? nx : ny, M = nx < ny ? ny : nx;
+    if (d <= m) return d * (d + 1) / 2;
+    if (d <= M) return m * (m + 1) / 2 + (d - m) * m;
+    const int e = d - M;
+    return m * (m + 1) / 2 + (M - m) * m + e * (m - 1) - e * (e - 1) / 2;
+}
+__device__ __forceinline__ int pos_a(int nx, int ny, int x, int y) {
     const int d = x + y;
     const int ylo = d - nx + 1 > 0 ? d - nx + 1 : 0;
-    return off[d] + y - ylo;
+    return diag_off(nx, ny, d) + y - ylo;
 }
-__device__ __forceinline__ int pos_b(const int *off, int nx, int ny, int x, int y) {
+__device__ __forceinline__ int pos_b(int nx, int ny, int x, int y) {
     const int d = x - y + ny - 1;
     const int ylo = ny - 1 - d > 0 ? ny - 1 - d : 0;
-    return off[d] + y - ylo;
+    return diag_off(nx, ny, d) + y - ylo;
 }
 // quadrant q = (vx<0) | 2 (vy<0): q = 0, 3 sweep anti-diagonals (layout A), q = 1, 2 diagonals (B)
 __device__ __forceinline__ bool quad_uses_a(int q) { return q == 0 || q == 3; }
@@ -87,8 +99,7 @@ struct Vec4 { T x, y, z, w; };
 // sweep input block from rho (2D: both diagonal layouts and sigma_t; 1D: natural order)
 template <typename T>
 __device__ __forceinline__ void write_sweep_input(int dim, long long ncell, int B, int b, int nx,
-                                                  int ny, long long cell, const int *offA,
-                                                  const int *offB, const double v[4], double st,
+                                                  int ny, long long cell, const double v[4], double st,
                                                   T *src) {
     if (dim == 1) {
         T *o = src + ((size_t)b * ncell + cell) * 2;
@@ -98,8 +109,8 @@ __device__ __forceinline__ void write_sweep_input(int dim, long long ncell, int 
     }
     const int x = (int)(cell % nx), y = (int)(cell / nx);
     const size_t nb4 = (size_t)B * ncell * 4;
-    const size_t pa = (size_t)b * ncell + pos_a(offA, nx, ny, x, y);
-    const size_t pb = (size_t)b * ncell + pos_b(offB, nx, ny, x, y);
+    const size_t pa = (size_t)b * ncell + pos_a(nx, ny, x, y);
+    const size_t pb = (size_t)b * ncell + pos_b(nx, ny, x, y);
     Vec4<T> o;
     o.x = (T)v[0]; o.y = (T)v[1]; o.z = (T)v[2]; o.w = (T)v[3];
     *reinterpret_cast<Vec4<T> *>(src + pa * 4) = o;
@@ -135,7 +146,8 @@ struct SweepLaunch {
     const rte_problem *p;
     const void *src;          // sweep input block (see above)
     double *partial;          // [B][nparts][ndof] or nullptr
-    void *f_out;              // [B][n_dir][ndof] T or nullptr
+    void *f_out;              // [B][ncell][n_dir][K] T or nullptr
+    void *sink;               // 64 bytes of workspace: target of the stores of idle lanes
     const int *active;        // [B] or nullptr
     int zero_inflow;
     int fp32;
@@ -145,7 +157,7 @@ hipError_t launch_sweep2d(const SweepLaunch &a, hipStream_t s);
 int sweep_waves(const rte_problem *p);
 int sweep_nparts(const rte_problem *p);
 
-// 1D sweep: writes f (always, T) to f_out [B][n_dir][ndof]; src as in 2D (K = 2).
+// 1D sweep: writes f (always, T) to f_out [B][ncell][n_dir][2]; src as in 2D (K = 2).
 hipError_t launch_sweep1d(const rte_problem *p, const void *src, void *f_out, const int *active,
                           int zero_inflow, int fp32, hipStream_t s);
 

@@ -33,11 +33,15 @@ struct Sweep2DArgs {
     double ghost;            // sqrt(hx hy): coefficient of a unit constant on phi_0
     int zero_inflow;
     const DirEntry *dirs;
-    const int *offA, *offB;  // diagonal offsets of the two sweep layouts
     const void *src;
     const double *inflow;
     double *partial;
     void *f_out;
+    void *sink;              // stores of lanes without a value to write go here
+    int stage;               // f-form: write the angular flux through an LDS stage (see kernel)
+    int stage_off;           // byte offset of the stage values in LDS
+    int stage_idx_off;       // byte offset of its cell / direction index arrays
+    int lg_nd;               // log2(W * DG)
     const int *active;
 };
 
@@ -192,14 +196,30 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
 
     // this quadrant's layout of the sweep inputs (see SweepLaunch)
     const bool la = quad_uses_a(q);
-    const int *off = la ? a.offA : a.offB;
     const size_t nb4 = (size_t)a.B * a.ncell * 4;
     const T *base = reinterpret_cast<const T *>(a.src);
     const T *src = base + (la ? 0 : nb4) + (size_t)b * a.ncell * 4;
     const T *sig_t = base + 2 * nb4 + (la ? 0 : (size_t)a.B * a.ncell) + (size_t)b * a.ncell;
     double *part_out = a.partial ? a.partial + ((size_t)b * a.nparts + gpart) * a.ncell * 4 : nullptr;
+    // angular flux [B][cell][n_dir][4]: a cell's block holds each direction's 4 coefficients;
+    // the directions of one quadrant are contiguous in the original numbering, so at every step
+    // the workgroup writes whole cache lines of each of its cells
     T *fout = WF ? reinterpret_cast<T *>(a.f_out) + (size_t)b * a.n_dir * a.ncell * 4 : nullptr;
-
+    // With a.stage the waves put a step's values in LDS ([64 cells][W*DG directions]) and then
+    // write them back with consecutive lanes on consecutive directions of one cell, so a store
+    // instruction covers whole lines (a few requests) instead of 64 scattered 16-byte pieces.
+    const bool stage_f = WF && a.stage != 0;
+    const int nd_wg = W * DG;
+    Vec4<T> *stage = nullptr;
+    int *st_cell = nullptr, *st_orig = nullptr;
+    if (stage_f) {
+        char *lb = reinterpret_cast<char *>(smem_d);
+        stage = reinterpret_cast<Vec4<T> *>(lb + a.stage_off);
+        st_cell = reinterpret_cast<int *>(lb + a.stage_idx_off);
+        st_orig = st_cell + 64;
+        const int pos = a.qstart[q] + part * nd_wg + (int)threadIdx.x;
+        if ((int)threadIdx.x < nd_wg) st_orig[threadIdx.x] = pos < dend ? a.dirs[pos].orig : -1;
+    }
     T tx0[DG], tx1[DG], ty0[DG], ty1[DG];
 #pragma unroll
     for (int d = 0; d < DG; ++d) { tx0[d] = tx1[d] = ty0[d] = ty1[d] = T(0); }
@@ -207,27 +227,35 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
     // lane position in the pipeline: band k, column i (k P + i = t - lane), tracked
     // incrementally so the loop carries no division
     const int P = a.P, nx = a.nx, ny = a.ny, nb = a.nbands;
-    int k = 0, i = -lane;
     // natural cell index (for f) and position in the diagonal layout (inputs, partials)
     auto cell_of = [&](int kk, int ii, bool &ok, int &pos) -> int {
         const int jr = kk * 64 + lane;
         ok = ii >= 0 && kk < nb && ii < nx && jr < ny;
         const int ip = rx ? nx - 1 - ii : ii;
         const int jp = ry ? ny - 1 - jr : jr;
-        pos = ok ? (la ? pos_a(off, nx, ny, ip, jp) : pos_b(off, nx, ny, ip, jp)) : 0;
+        pos = ok ? (la ? pos_a(nx, ny, ip, jp) : pos_b(nx, ny, ip, jp)) : 0;
         return ok ? jp * nx + ip : 0;
     };
-    bool ok_cur;
-    int pos_cur;
-    int cell_cur = cell_of(k, i, ok_cur, pos_cur);
-    Vec4<T> sv_cur = {T(0), T(0), T(0), T(0)};
-    T sg_cur = T(0);
-    if (ok_cur) {
-        sv_cur = *reinterpret_cast<const Vec4<T> *>(src + (size_t)pos_cur * 4);
-        sg_cur = sig_t[pos_cur];
-    }
-    const int total = nb * P + 63;
-    for (int t = 0; t < total; ++t) {
+    // cell data of one pipeline step: position (band k, column i) and the prefetched inputs
+    struct CellIn {
+        int k, i, cell, pos;
+        bool ok;
+        Vec4<T> sv;
+        T sg;
+    };
+    // Every lane loads (position 0 when outside the domain; such values are never used): a load
+    // under a branch leaves the compiler unsure whether it was issued, and it then waits for it
+    // at once instead of at the step that uses it.
+    auto load_cell = [&](CellIn &c) {
+        c.cell = cell_of(c.k, c.i, c.ok, c.pos);
+        c.sv = *reinterpret_cast<const Vec4<T> *>(src + (size_t)c.pos * 4);
+        c.sg = sig_t[c.pos];
+    };
+    // One step: the lane's cell `cur` is solved while `nxt` is prefetched.  The loop below runs
+    // steps in pairs with the two records swapping roles, so the prefetched data is consumed where
+    // it was loaded (no register copy at the loop edge that would make the load land in its own
+    // step).
+    auto step = [&](int t, const CellIn &cur, CellIn &nxt) __attribute__((always_inline)) {
         T yi0[DG], yi1[DG];
 #pragma unroll
         for (int d = 0; d < DG; ++d) {               // all lanes take part in the shift
@@ -235,33 +263,27 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
             yi1[d] = shfl_up1(ty1[d]);
         }
         // next position and prefetch of its cell data (overlaps this step's arithmetic)
-        int kn = k, in_ = i + 1;
-        if (in_ == P) { in_ = 0; ++kn; }
-        bool ok_next;
-        int pos_next;
-        const int cell_next = cell_of(kn, in_, ok_next, pos_next);
-        Vec4<T> sv_next = {T(0), T(0), T(0), T(0)};
-        T sg_next = T(0);
-        if (ok_next) {
-            sv_next = *reinterpret_cast<const Vec4<T> *>(src + (size_t)pos_next * 4);
-            sg_next = sig_t[pos_next];
-        }
+        nxt.k = cur.k;
+        nxt.i = cur.i + 1;
+        if (nxt.i == P) { nxt.i = 0; ++nxt.k; }
+        load_cell(nxt);
         // the lane's DG directions are summed in T, the groups and quadrants in FP64
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        if (ok_cur) {
+        T fo[WF ? DG : 1][4];
+        if (cur.ok) {
             if (lane == 0) {
 #pragma unroll
                 for (int d = 0; d < DG; ++d) {
-                    if (k == 0) { yi0[d] = gy; yi1[d] = T(0); }
-                    else { yi0[d] = ring[(i * DG + d) * 2]; yi1[d] = ring[(i * DG + d) * 2 + 1]; }
+                    if (cur.k == 0) { yi0[d] = gy; yi1[d] = T(0); }
+                    else { yi0[d] = ring[(cur.i * DG + d) * 2]; yi1[d] = ring[(cur.i * DG + d) * 2 + 1]; }
                 }
             }
-            if (i == 0) {
+            if (cur.i == 0) {
 #pragma unroll
                 for (int d = 0; d < DG; ++d) { tx0[d] = gx; tx1[d] = T(0); }
             }
-            const T s0 = sv_cur.x, s1 = sx * sv_cur.y, s2 = sy * sv_cur.z, s3 = sx * sy * sv_cur.w;
-            const T sig = sg_cur;
+            const T s0 = cur.sv.x, s1 = sx * cur.sv.y, s2 = sy * cur.sv.z, s3 = sx * sy * cur.sv.w;
+            const T sig = cur.sg;
             T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
@@ -279,17 +301,15 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
                 a1 += wt[d] * f1;
                 a2 += wt[d] * f2;
                 a3 += wt[d] * f3;
-                if (WF && orig[d] >= 0) {
-                    Vec4<T> o;
-                    o.x = f0; o.y = sx * f1; o.z = sy * f2; o.w = sx * sy * f3;
-                    *reinterpret_cast<Vec4<T> *>(fout + ((size_t)orig[d] * a.ncell + cell_cur) * 4) = o;
+                if constexpr (WF) {
+                    fo[d][0] = f0; fo[d][1] = sx * f1; fo[d][2] = sy * f2; fo[d][3] = sx * sy * f3;
                 }
             }
             if (lane == 63) {
 #pragma unroll
                 for (int d = 0; d < DG; ++d) {
-                    ring[(i * DG + d) * 2] = ty0[d];
-                    ring[(i * DG + d) * 2 + 1] = ty1[d];
+                    ring[(cur.i * DG + d) * 2] = ty0[d];
+                    ring[(cur.i * DG + d) * 2 + 1] = ty1[d];
                 }
             }
             acc0 = (double)a0;
@@ -297,31 +317,77 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
             acc2 = (double)a2;
             acc3 = (double)a3;
         }
-        if (part_out) {
-            // sum the W wavefronts' partials of this cell in LDS (fixed order), one writer
+        // Every lane issues its DG stores, idle lanes and padding directions into the sink: stores
+        // under a branch would leave the compiler unsure how many are in flight, and it would
+        // then wait for all of them before the next step's prefetched data is used.
+        if constexpr (WF) {
+            if (stage_f) {
+#pragma unroll
+                for (int d = 0; d < DG; ++d) {
+                    Vec4<T> o;
+                    o.x = fo[d][0]; o.y = fo[d][1]; o.z = fo[d][2]; o.w = fo[d][3];
+                    stage[lane * nd_wg + wv * DG + d] = o;
+                }
+                if (wv == 0) st_cell[lane] = cur.ok ? cur.cell : -1;
+            } else {
+                T *fc = fout + (size_t)cur.cell * a.n_dir * 4;
+#pragma unroll
+                for (int d = 0; d < DG; ++d) {
+                    T *dst = (cur.ok && orig[d] >= 0) ? fc + (size_t)orig[d] * 4
+                                                      : reinterpret_cast<T *>(a.sink);
+                    Vec4<T> o;
+                    o.x = fo[d][0]; o.y = fo[d][1]; o.z = fo[d][2]; o.w = fo[d][3];
+                    *reinterpret_cast<Vec4<T> *>(dst) = o;
+                }
+            }
+        }
+        if (part_out || stage_f) {
+            // (1) partial densities of this cell from every wavefront into LDS, (2) one barrier,
+            // (3) the staged angular flux back to memory, (4) the fixed-order sum of the W
+            // partials by wavefront 0, (5) a second barrier before the stage is reused
             double *slot = red + (size_t)(t & 1) * W * 64 * 4;
-            double4 v;
-            v.x = acc0; v.y = acc1; v.z = acc2; v.w = acc3;
-            *reinterpret_cast<double4 *>(slot + ((size_t)wv * 64 + lane) * 4) = v;
+            if (part_out) {
+                double4 v;
+                v.x = acc0; v.y = acc1; v.z = acc2; v.w = acc3;
+                *reinterpret_cast<double4 *>(slot + ((size_t)wv * 64 + lane) * 4) = v;
+            }
             __syncthreads();
-            if (wv == 0 && ok_cur) {
+            if constexpr (WF) {
+                if (stage_f) {
+                    const int mask = nd_wg - 1;
+#pragma unroll
+                    for (int r = 0; r < DG; ++r) {
+                        const int e = (r * W + wv) * 64 + lane;
+                        const int ci = st_cell[e >> a.lg_nd], og = st_orig[e & mask];
+                        T *dst = (ci >= 0 && og >= 0) ? fout + ((size_t)ci * a.n_dir + og) * 4
+                                                      : reinterpret_cast<T *>(a.sink);
+                        *reinterpret_cast<Vec4<T> *>(dst) = stage[e];
+                    }
+                }
+            }
+            if (part_out && wv == 0 && cur.ok) {
                 double4 sum = *reinterpret_cast<const double4 *>(slot + (size_t)lane * 4);
                 for (int w2 = 1; w2 < W; ++w2) {
                     const double4 o = *reinterpret_cast<const double4 *>(slot + ((size_t)w2 * 64 + lane) * 4);
                     sum.x += o.x; sum.y += o.y; sum.z += o.z; sum.w += o.w;
                 }
                 sum.y *= dsx; sum.z *= dsy; sum.w *= dsx * dsy;
-                *reinterpret_cast<double4 *>(part_out + (size_t)pos_cur * 4) = sum;
+                *reinterpret_cast<double4 *>(part_out + (size_t)cur.pos * 4) = sum;
             }
+            if (stage_f) __syncthreads();      // the stage is rewritten at the next step
         }
-        k = kn;
-        i = in_;
-        ok_cur = ok_next;
-        cell_cur = cell_next;
-        pos_cur = pos_next;
-        sv_cur = sv_next;
-        sg_cur = sg_next;
+    };
+    CellIn A, B;
+    A.k = 0;
+    A.i = -lane;
+    load_cell(A);
+    const int total = nb * P + 63;
+    int t = 0;
+    for (; t + 1 < total; t += 2) {
+        step(t, A, B);
+        step(t + 1, B, A);
     }
+    if (t < total) step(t, A, B);
 }
 
 // ------------------------------------------------------------------------------------- 1D
@@ -341,7 +407,7 @@ __global__ void __launch_bounds__(256) sweep1d_kernel(int nc, int n_dir, int B, 
     const T c = T(kS3);
     T edge = zero_inflow ? T(0) : (T)inflow[4 * b + (rev ? 1 : 0)];   // physical inflow value
     const T *s = src + (size_t)b * nc * 2;
-    T *f = f_out + ((size_t)b * n_dir + j) * nc * 2;
+    T *f = f_out + (size_t)b * nc * n_dir * 2 + (size_t)j * 2;    // [B][cell][n_dir][2]
     for (int st = 0; st < nc; ++st) {
         const int cc = rev ? nc - 1 - st : st;
         const T h = (T)widths[cc];
@@ -355,8 +421,8 @@ __global__ void __launch_bounds__(256) sweep1d_kernel(int nc, int n_dir, int B, 
         const T det = tt * tt + T(2) * aa * aa;
         const T f0 = ((T(3) * aa + sig) * r0 - c * aa * r1) / det;
         const T f1 = (c * aa * r0 + (aa + sig) * r1) / det;
-        f[2 * cc] = f0;
-        f[2 * cc + 1] = rev ? -f1 : f1;
+        f[(size_t)cc * n_dir * 2] = f0;
+        f[(size_t)cc * n_dir * 2 + 1] = rev ? -f1 : f1;
         edge = (f0 + c * f1) / sq;                 // outflow trace value
     }
 }
@@ -365,8 +431,8 @@ __global__ void __launch_bounds__(256) sweep1d_kernel(int nc, int n_dir, int B, 
 template <typename T>
 __global__ void source_kernel(int dim, long long ncell, int K, int B, int nx, int ny,
                               const double *rho, const double *sigma_t, const double *sigma_s,
-                              const double *G, const double *cellw, double ghost, const int *offA,
-                              const int *offB, T *src, const int *active) {
+                              const double *G, const double *cellw, double ghost, T *src,
+                              const int *active) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)B * ncell) return;
     const int b = (int)(t / ncell);
@@ -376,7 +442,7 @@ __global__ void source_kernel(int dim, long long ncell, int K, int B, int nx, in
     const double g0 = G[t] * (cellw ? sqrt(cellw[cell]) : ghost);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < K; ++k) v[k] = ss * rho[t * K + k] + (k == 0 ? g0 : 0.0);
-    write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, offA, offB, v, sigma_t[t], src);
+    write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, v, sigma_t[t], src);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -396,7 +462,6 @@ struct ReduceArgs {
     long long ncell;
     int B, nx, ny, nparts;
     int gq[4];
-    const int *offA, *offB;
 };
 
 __global__ void reduce_parts_kernel(ReduceArgs a, const double *partial, double *rho_star,
@@ -408,8 +473,8 @@ __global__ void reduce_parts_kernel(ReduceArgs a, const double *partial, double 
     const bool live = cell < a.ncell && (!active || active[b] != 0);
     if (live) {
         const int x = (int)(cell % a.nx), y = (int)(cell / a.nx);
-        const size_t pa = (size_t)pos_a(a.offA, a.nx, a.ny, x, y);
-        const size_t pb = (size_t)pos_b(a.offB, a.nx, a.ny, x, y);
+        const size_t pa = (size_t)pos_a(a.nx, a.ny, x, y);
+        const size_t pb = (size_t)pos_b(a.nx, a.ny, x, y);
         const double *base = partial + (size_t)b * a.nparts * a.ncell * 4;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int part = 0;
@@ -434,7 +499,7 @@ __global__ void reduce_parts_kernel(ReduceArgs a, const double *partial, double 
 }
 
 template <typename T>
-__global__ void scalar_flux_kernel(long long ndof, int B, int n_dir, const double *w, const T *f,
+__global__ void scalar_flux_kernel(long long ndof, int K, int B, int n_dir, const double *w, const T *f,
                                    double *rho, const double *rho_prev, unsigned long long *maxd,
                                    unsigned long long *maxr, const int *active) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -442,9 +507,10 @@ __global__ void scalar_flux_kernel(long long ndof, int B, int n_dir, const doubl
     double d = 0.0, m = 0.0;
     const bool live = t < ndof && (!active || active[b] != 0);
     if (live) {
-        const T *fb = f + (size_t)b * n_dir * ndof + t;
+        const long long c = t / K, k = t - c * K;              // f: [B][cell][n_dir][K]
+        const T *fb = f + ((size_t)b * (ndof / K) + c) * n_dir * K + k;
         double s = 0.0;
-        for (int j = 0; j < n_dir; ++j) s += w[j] * (double)fb[(size_t)j * ndof];
+        for (int j = 0; j < n_dir; ++j) s += w[j] * (double)fb[(size_t)j * K];
         rho[(size_t)b * ndof + t] = s;
         m = fabs(s);
         if (rho_prev) d = fabs(s - rho_prev[(size_t)b * ndof + t]);
@@ -485,15 +551,48 @@ hipError_t sweep2d_launch_t(const SweepLaunch &L, hipStream_t s) {
     a.ghost = sqrt(p->hx * p->hy);
     a.zero_inflow = L.zero_inflow;
     a.dirs = p->d_dirs;
-    a.offA = p->d_offA;
-    a.offB = p->d_offB;
     a.src = L.src;
     a.inflow = p->inflow;
     a.partial = L.partial;
     a.f_out = L.f_out;
+    a.sink = L.sink;
     a.active = L.active;
     const unsigned grid = (unsigned)((long long)a.B * a.nparts);
-    const size_t lds = (size_t)2 * W * 64 * 4 * sizeof(double) + (size_t)W * p->nx * DG * 2 * sizeof(T);
+    const size_t red = (size_t)2 * W * 64 * 4 * sizeof(double);
+    size_t lds = red + (size_t)W * p->nx * DG * 2 * sizeof(T);
+    a.stage = 0;
+    a.stage_off = 0;
+    a.stage_idx_off = 0;
+    a.lg_nd = 0;
+    const int nd = W * DG;
+    if (L.f_out && DG <= 2 && (nd & (nd - 1)) == 0) {
+        // the f stage: [64][W*DG] values, 64 cell indices, W*DG direction indices; it overlays
+        // the partial-sum buffers when no partial densities are formed.  Used with one or two
+        // directions per lane (where a lane's direct stores are 16 or 32 scattered bytes; with
+        // more the direct stores measured faster) and only when the workgroups still fit on the
+        // device in one round (LDS per workgroup within the CU's share).
+        const size_t st = (size_t)64 * nd * sizeof(Vec4<T>);
+        const size_t idx = 64 * sizeof(int) + (size_t)nd * sizeof(int);
+        size_t off, ioff, total;
+        if (!L.partial && st <= red) {
+            off = 0;
+            ioff = (lds + 15) & ~(size_t)15;
+        } else {
+            off = (lds + 15) & ~(size_t)15;
+            ioff = off + st;
+        }
+        total = ioff + idx;
+        const long long per_cu = ((long long)grid + p->n_cu - 1) / p->n_cu;
+        if (per_cu >= 1 && (long long)total * per_cu <= p->lds_per_cu) {
+            a.stage = 1;
+            a.stage_off = (int)off;
+            a.stage_idx_off = (int)ioff;
+            int lg = 0;
+            while ((1 << lg) < nd) ++lg;
+            a.lg_nd = lg;
+            lds = total;
+        }
+    }
     if (L.f_out)
         hipLaunchKernelGGL((sweep2d_kernel<T, DG, true>), dim3(grid), dim3(64 * W), lds, s, a);
     else
@@ -543,11 +642,11 @@ hipError_t launch_source(const rte_problem *p, const double *rho, void *src, con
     if (fp32)
         hipLaunchKernelGGL(source_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->dim,
                            p->ncell, p->K, p->B, p->nx, p->ny, rho, p->sigma_t, p->sigma_s,
-                           p->source, cw, ghost, p->d_offA, p->d_offB, (float *)src, active);
+                           p->source, cw, ghost, (float *)src, active);
     else
         hipLaunchKernelGGL(source_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            p->dim, p->ncell, p->K, p->B, p->nx, p->ny, rho, p->sigma_t,
-                           p->sigma_s, p->source, cw, ghost, p->d_offA, p->d_offB,
+                           p->sigma_s, p->source, cw, ghost,
                            (double *)src, active);
     return hipGetLastError();
 }
@@ -563,8 +662,6 @@ hipError_t launch_reduce_parts(const rte_problem *p, const double *partial, int 
     a.nparts = nparts;
     const int W = p->tune.wpb, DG = p->tune.dg;
     for (int q = 0; q < 4; ++q) a.gq[q] = ((p->quad.count[q] + DG - 1) / DG + W - 1) / W;
-    a.offA = p->d_offA;
-    a.offB = p->d_offB;
     dim3 grid(blocks_for(p->ncell, 256), p->B);
     hipLaunchKernelGGL(reduce_parts_kernel, grid, dim3(256), 0, s, a, partial, rho_star, rho_prev,
                        maxd, maxr, active);
@@ -576,10 +673,10 @@ hipError_t launch_scalar_flux(const rte_problem *p, const void *f, double *rho, 
                               unsigned long long *maxr, const int *active, hipStream_t s) {
     dim3 grid(blocks_for(p->ndof, 256), p->B);
     if (fp32)
-        hipLaunchKernelGGL(scalar_flux_kernel<float>, grid, dim3(256), 0, s, p->ndof, p->B, p->n_dir,
+        hipLaunchKernelGGL(scalar_flux_kernel<float>, grid, dim3(256), 0, s, p->ndof, p->K, p->B, p->n_dir,
                            p->d_w, (const float *)f, rho, rho_prev, maxd, maxr, active);
     else
-        hipLaunchKernelGGL(scalar_flux_kernel<double>, grid, dim3(256), 0, s, p->ndof, p->B,
+        hipLaunchKernelGGL(scalar_flux_kernel<double>, grid, dim3(256), 0, s, p->ndof, p->K, p->B,
                            p->n_dir, p->d_w, (const double *)f, rho, rho_prev, maxd, maxr, active);
     return hipGetLastError();
 }
