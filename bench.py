@@ -137,8 +137,8 @@ SERVE_KEYS = [(n, p) for n in (64, 128, 256) for p in (32, 64, 128)]
 
 
 def serve_capacity(n, n_phi):
-    """Slots of a key's pool: about 32M cell-direction updates per batched sweep, 4..64 slots."""
-    return int(min(64, max(4, (32 << 20) // (n * n * n_phi))))
+    """Slots of a key's pool: about 256M cell-direction updates per batched sweep, 16..64 slots."""
+    return int(min(64, max(16, (256 << 20) // (n * n * n_phi))))
 
 
 def serving_leg(args, rte):
@@ -158,23 +158,38 @@ def serving_leg(args, rte):
                                 precision=args.precision, eps=args.eps, theta=args.theta,
                                 cg_rtol=args.cg_rtol)
              for k in SERVE_KEYS}
-    stream = W.c3_requests(args.serve_requests + args.serve_warmup, rate=args.serve_rate)
-    reqs = [serving.lattice_request(i, r.arrival, r.n, r.n_phi, r.seed) for i, r in enumerate(stream)]
-    warm, timed = reqs[:args.serve_warmup], reqs[args.serve_warmup:]
     budget = int(args.serve_budget_gib * 2**30)
+    n_all = args.serve_requests + args.serve_warmup
+
+    def stream_at(rate):
+        """The request stream (seeded draws) with Poisson arrivals at ``rate`` (inf: all at 0)."""
+        reqs = W.c3_requests(n_all, rate=rate if np.isfinite(rate) else 1.0)
+        out = [serving.lattice_request(i, r.arrival, r.n, r.n_phi, r.seed) for i, r in enumerate(reqs)]
+        warm, timed = out[:args.serve_warmup], out[args.serve_warmup:]
+        t_start = timed[0].arrival
+        timed = [serving.Request(k, (r.arrival - t_start) if np.isfinite(rate) else 0.0, r.n,
+                                 r.n_phi, r.sigma_t, r.sigma_s, r.G, r.g, r.psi)
+                 for k, r in enumerate(timed)]
+        return warm, timed
+
+    warm, saturated = stream_at(float("inf"))
     if warm:
         serving.Server(pools, budget).run([serving.Request(k, 0.0, r.n, r.n_phi, r.sigma_t,
                                                            r.sigma_s, r.G, r.g, r.psi)
                                            for k, r in enumerate(warm)])
-    t_start = timed[0].arrival
-    timed = [serving.Request(k, r.arrival - t_start, r.n, r.n_phi, r.sigma_t, r.sigma_s, r.G,
-                             r.g, r.psi) for k, r in enumerate(timed)]
+    # capacity: every request queued at t = 0 (closed loop, the pools stay full)
+    srv = serving.Server(pools, budget)
+    tw = time.perf_counter()
+    res_sat = srv.run(saturated)
+    sat = serving.latency_summary(res_sat, time.perf_counter() - tw)
+    # latency: open-loop Poisson arrivals at a rate below capacity
+    rate = args.serve_rate if args.serve_rate > 0 else 0.8 * sat["solves_per_s"]
+    _, timed = stream_at(rate)
     srv = serving.Server(pools, budget)
     tw = time.perf_counter()
     res = srv.run(timed)
-    wall = time.perf_counter() - tw
-    out = serving.latency_summary(res, wall)
-    out.update({"rate_req_per_s": args.serve_rate, "keys": len(SERVE_KEYS),
+    out = serving.latency_summary(res, time.perf_counter() - tw)
+    out.update({"rate_req_per_s": rate, "saturated": sat, "keys": len(SERVE_KEYS),
                 "capacity": {f"{k[0]}x{k[0]}/{k[1]}": serve_capacity(*k) for k in SERVE_KEYS},
                 "budget_gib": args.serve_budget_gib, "peak_resident_gib": srv.budget.peak / 2**30,
                 "rom_build_s": t_rom, "rom_rank": args.rank, "rom_train": args.serve_train})
@@ -200,7 +215,7 @@ def serving_leg(args, rte):
         base = len(sample) / t_sum
         out.update({"plain_gpu_si_dsa_solves_per_s": base,
                     "plain_gpu_si_dsa_requests_timed": len(sample),
-                    "served_vs_plain_gpu_si_dsa": out["solves_per_s"] / base})
+                    "served_vs_plain_gpu_si_dsa": sat["solves_per_s"] / base})
     return out
 
 
@@ -225,9 +240,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-train", type=int, default=4)
     ap.add_argument("--no-f-form", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="copy a buffer of this size before timing (HBM counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=40)
-    ap.add_argument("--serve-rate", type=float, default=100.0)
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="open-loop arrival rate (requests/s); 0: 0.8 x the measured capacity")
     ap.add_argument("--serve-train", type=int, default=32)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-baseline", type=int, default=12)
@@ -241,6 +259,17 @@ def main():
     import torch
     import rte_workloads as W
     from paper_2402_10488_amd import rte, problems
+
+    if args.copy_calibration_gib > 0:
+        # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter readings give the
+        # scale of those counters (bytes moved = known size)
+        n = int(args.copy_calibration_gib * 2**30) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+        torch.cuda.empty_cache()
 
     plane = W.c2_batch(args.batch, args.n, args.nphi)
     P = problems.plane_problem(plane)
@@ -277,6 +306,9 @@ def main():
     red_ms, red_n = rte.profile_read("reduce")
     rte.profile_enable(False)
     bad = [int(r.status) for r in results if r.status != rte.RTE_OK]
+    dsa_corrections = sum(int((r.kind == 1).sum()) for r in results)
+    cg_per_correction = (sum(r.cg_iterations for r in results) / dsa_corrections
+                         if dsa_corrections else None)
     sweeps = np.array([r.n_sweep for r in results])
     cd_total = float(sweeps.sum()) * P.ncell * P.n_dir
     solves = P.B * args.steps
@@ -332,6 +364,8 @@ def main():
                    "theta": args.theta, "tuning": P.tuning()},
         "solves_per_s": solves / elapsed,
         "mean_sweeps_per_solve": float(sweeps.mean()),
+        "dsa_corrections_per_solve": dsa_corrections / solves,
+        "cg_iterations_per_dsa_correction": cg_per_correction,
         "status_not_ok_steps": bad,
         "batch_latency_ms": {"p50": elapsed / args.steps * 1e3, "p99": elapsed / args.steps * 1e3,
                              "note": "all instances of a step arrive together and return together"},

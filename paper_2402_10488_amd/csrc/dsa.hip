@@ -424,9 +424,46 @@ __device__ __forceinline__ double *slot(double *part, int b, int s, int nblk) {
     return part + ((size_t)b * 5 + s) * nblk;
 }
 
+// Warm start, first pass: with d the instance's previous correction, b = Sigma_s (rho* - rho_prev)
+// is stored in r and A d in q, and the partials of (d, b) and (d, A d) go to slots 2 and 3.
+__global__ void __launch_bounds__(kCgBlock) cg_warm_kernel(MipArgs a, const double *rho_star,
+                                                           const double *rho_prev, const int *kind,
+                                                           int want, const double *d, double *r,
+                                                           double *q, double *part) {
+    const int b = blockIdx.y;
+    if (kind && kind[b] != want) return;
+    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    double db = 0.0, dad = 0.0;
+    if (cell < a.ncell) {
+        const size_t base = (size_t)b * a.ncell;
+        const long long gi = (long long)base + cell;
+        const double ss = a.sigma_s[gi];
+        double rs[4], rp[4], bv[4], dc[4], y[4];
+        load4(rho_star, gi, rs);
+        load4(rho_prev, gi, rp);
+        for (int k = 0; k < 4; ++k) bv[k] = ss * (rs[k] - rp[k]);
+        auto dat = [&](long long c, double v[4]) { load4(d, base + c, v); };
+        mip_apply(a, b, (int)(cell % a.nx), (int)(cell / a.nx), dat, y);
+        load4(d, gi, dc);
+        store4(r, gi, bv);
+        store4(q, gi, y);
+        for (int k = 0; k < 4; ++k) { db += dc[k] * bv[k]; dad += dc[k] * y[k]; }
+    }
+    block_sum2(db, dad);
+    if (threadIdx.x == 0) {
+        slot(part, b, 2, a.nblk)[blockIdx.x] = db;
+        slot(part, b, 3, a.nblk)[blockIdx.x] = dad;
+    }
+}
+
+// CG start.  Cold (d == nullptr): x = 0, r = b.  Warm: x = alpha d, r = b - alpha A d with
+// alpha = (d, b) / (d, A d), the multiple of d closest to the solution in the energy norm
+// (alpha = 0 when d = 0 or the quotient is not a positive finite number); r and A d come from
+// cg_warm_kernel.  The stopping test stays relative to ||b||.
 __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const double *rho_star,
                                                             const double *rho_prev, const int *kind,
-                                                            int want, double *x, double *r,
+                                                            int want, const double *d,
+                                                            const double *q, double *x, double *r,
                                                             double *z, double *part, int *state,
                                                             int *iters, int *n_running, int bj) {
     const int b = blockIdx.y;
@@ -435,17 +472,33 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
         if (blockIdx.x == 0 && threadIdx.x == 0) state[b] = 0;
         return;
     }
+    double alpha = 0.0;
+    if (d) {
+        const double db = sum_parts(slot(part, b, 2, a.nblk), a.nblk);
+        const double dad = sum_parts(slot(part, b, 3, a.nblk), a.nblk);
+        alpha = dad > 0.0 ? db / dad : 0.0;
+        if (!(fabs(alpha) < INFINITY)) alpha = 0.0;
+    }
+    // slots 2 and 3 are only read here and slots 0 and 4 only written, so blocks need no order
     const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
     double rz = 0.0, bb = 0.0;
     if (cell < a.ncell) {
         const long long gi = (long long)b * a.ncell + cell;
-        const double ss = a.sigma_s[gi];
-        double rs[4], rp[4], rv[4], zv[4];
-        load4(rho_star, gi, rs);
-        load4(rho_prev, gi, rp);
-        for (int k = 0; k < 4; ++k) rv[k] = ss * (rs[k] - rp[k]);
-        const double zero[4] = {0.0, 0.0, 0.0, 0.0};
-        store4(x, gi, zero);
+        double bv[4], rv[4], xv[4], zv[4];
+        if (d) {
+            double dv[4], qv[4];
+            load4(r, gi, bv);
+            load4(d, gi, dv);
+            load4(q, gi, qv);
+            for (int k = 0; k < 4; ++k) { xv[k] = alpha * dv[k]; rv[k] = bv[k] - alpha * qv[k]; }
+        } else {
+            const double ss = a.sigma_s[gi];
+            double rs[4], rp[4];
+            load4(rho_star, gi, rs);
+            load4(rho_prev, gi, rp);
+            for (int k = 0; k < 4; ++k) { bv[k] = ss * (rs[k] - rp[k]); xv[k] = 0.0; rv[k] = bv[k]; }
+        }
+        store4(x, gi, xv);
         store4(r, gi, rv);
         if (bj) {
             binv_apply(a, b, cell, rv, zv);
@@ -454,7 +507,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
             store4(z, gi, zv);
             for (int k = 0; k < 4; ++k) rz += rv[k] * zv[k];
         }
-        for (int k = 0; k < 4; ++k) bb += rv[k] * rv[k];
+        for (int k = 0; k < 4; ++k) bb += bv[k] * bv[k];
     }
     block_sum2(rz, bb);
     if (threadIdx.x == 0) {
@@ -560,12 +613,13 @@ __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, 
 }
 
 __global__ void cg_finish_kernel(long long ndof, const double *x, double *delta, const int *state,
-                                 const int *iters, int *iters_out, int B) {
+                                 const int *iters, int *iters_out, unsigned long long *total, int B) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (state[b] == 0) return;
     if (t < ndof) delta[(size_t)b * ndof + t] = x[(size_t)b * ndof + t];
     if (t == 0 && iters_out) iters_out[b] = iters[b];
+    if (t == 0 && total) atomicAdd(total, (unsigned long long)iters[b]);
 }
 
 __global__ void zero_int_kernel(int *x) {
@@ -1197,15 +1251,18 @@ hipError_t launch_dsa1d(const rte_problem *p, const double *rho_star, const doub
 }
 
 hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double *rho_star,
-                           const double *rho_prev, const int *kind, int want_kind, double rtol,
-                           hipStream_t s) {
+                           const double *rho_prev, const int *kind, int want_kind,
+                           const double *guess, double rtol, hipStream_t s) {
     const MipArgs a = mip_args(p, c);
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, c.n_running);
+    if (guess)
+        hipLaunchKernelGGL(cg_warm_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, rho_star,
+                           rho_prev, kind, want_kind, guess, c.r, c.q, c.part);
     // bj = 1: block-Jacobi preconditioner; bj = 2: first smoothing step of the multigrid one
     const int bj = c.mg.L == 0 ? 1 : 2;
     hipLaunchKernelGGL(cg_setup_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, rho_star,
-                       rho_prev, kind, want_kind, c.x, c.r, c.z, c.part, c.state, c.iters,
-                       c.n_running, bj);
+                       rho_prev, kind, want_kind, guess, c.q, c.x, c.r, c.z, c.part, c.state,
+                       c.iters, c.n_running, bj);
     if (bj == 2) return launch_mg_precond(p, c, 0, s);    // hierarchy built by launch_dsa_build
     return hipGetLastError();
 }
@@ -1227,10 +1284,10 @@ hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, d
 }
 
 hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delta, int *iters_out,
-                            hipStream_t s) {
+                            unsigned long long *total, hipStream_t s) {
     dim3 grid(blocks_for(p->ndof, 256), p->B);
     hipLaunchKernelGGL(cg_finish_kernel, grid, dim3(256), 0, s, p->ndof, c.x, delta, c.state,
-                       c.iters, iters_out, p->B);
+                       c.iters, iters_out, total, p->B);
     return hipGetLastError();
 }
 

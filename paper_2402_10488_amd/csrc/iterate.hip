@@ -93,6 +93,18 @@ __global__ void zero_kernel(double *x, long long n) {
     if (t < n) x[t] = 0.0;
 }
 
+__global__ void zero_rows_kernel(double *x, long long n, const int *mask) {
+    const int b = blockIdx.y;
+    if (mask && !mask[b]) return;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[(size_t)b * n + t] = 0.0;
+}
+
+__global__ void zero_u64_kernel(unsigned long long *x, long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = 0ull;
+}
+
 __global__ void fill_int_kernel(int *x, long long n, int v) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) x[t] = v;
@@ -140,6 +152,18 @@ hipError_t launch_init_state(const rte_problem *p, const IterState &st, int max_
 hipError_t launch_zero(double *x, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_rows(double *x, int B, long long n, const int *mask, hipStream_t s) {
+    if (n <= 0 || B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_rows_kernel, dim3(blocks_for(n, 256), B), dim3(256), 0, s, x, n, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *x, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n);
     return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ struct Layout {
     double *dsa1d;          // 1D DSA scratch
     RomSpace rom;
     int *rom_status;
-    long long *cg_total;
+    unsigned long long *cg_total;   // CG iterations summed over instances and calls
     int *flag;
     int *mask;              // [B] instances selected by rte_sisa_admit
     double *sink;           // [8] target of the sweep's stores from idle lanes
@@ -74,7 +74,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     L.st.change = c.take<double>(B * (size_t)std::max(max_iter, 1));
     L.st.kinds = c.take<int>(B * (size_t)std::max(max_iter, 1));
     L.st.n_active = c.take<int>(1);
-    L.cg_total = c.take<long long>(1);
+    L.cg_total = c.take<unsigned long long>(1);
     L.flag = c.take<int>(1);
     L.mask = c.take<int>(B);
     if (mode != RTE_SI) {
@@ -527,16 +527,17 @@ int do_sweep(const rte_problem *p, const Layout &L, const void *src, void *f_out
 }
 
 // diffusion correction for the instances whose kind equals `want` (all if kind == nullptr)
+// guess (nullable): each instance's previous correction, the warm-start direction of the CG
 int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const double *rho_prev,
            double *delta, const int *kind, int want, double rtol, int maxit, int *iters_out,
-           int *failed, hipStream_t s) {
+           int *failed, const double *guess, hipStream_t s) {
     ProfScope ps(RTE_PROF_DSA, s);
     if (p->dim == 1) {
         HIPCHK(launch_dsa1d(p, rho_star, rho_prev, delta, kind, want, L.dsa1d, s));
         return RTE_OK;
     }
     // the multigrid hierarchy depends only on the materials: built by the caller once
-    HIPCHK(launch_cg_setup(p, L.cg, rho_star, rho_prev, kind, want, rtol, s));
+    HIPCHK(launch_cg_setup(p, L.cg, rho_star, rho_prev, kind, want, guess, rtol, s));
     // the host looks at the number of running instances every few iterations only: a look
     // drains the queue, and iterations launched after every instance stopped return at once
     const int poll = 4;
@@ -550,7 +551,7 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
         }
     }
     if (failed) *failed = running != 0;
-    HIPCHK(launch_cg_finish(p, L.cg, delta, iters_out, s));
+    HIPCHK(launch_cg_finish(p, L.cg, delta, iters_out, L.cg_total, s));
     return RTE_OK;
 }
 
@@ -592,8 +593,9 @@ int run_iterations(const rte_problem *p, const Layout &L, rte_mode mode, const r
         }
         if (mode != RTE_SI) {
             int failed = 0;
+            // L.delta holds every instance's previous correction (zero before its first)
             rc = do_dsa(p, L, L.rho_star, rho, L.delta, L.st.kind, 1, o->cg_rtol, o->cg_maxit,
-                        L.cg.iters, &failed, s);
+                        L.cg.iters, &failed, L.delta, s);
             if (rc) return rc;
             *cg_failed = *cg_failed || failed;
             delta = L.delta;
@@ -625,13 +627,15 @@ int finish_stats(const rte_problem *p, const Layout &L, int max_iter, int iterat
         if (stats->kind)
             HIPCHK(hipMemcpyAsync(stats->kind, L.st.kinds, sizeof(int) * p->B * max_iter, d2h, s));
     }
+    unsigned long long cg_total = 0;
+    HIPCHK(hipMemcpyAsync(&cg_total, L.cg_total, sizeof(cg_total), d2h, s));
     HIPCHK(hipStreamSynchronize(s));
     int rc = RTE_OK;
     for (int b = 0; b < p->B; ++b)
         if (status[b] != RTE_OK) rc = RTE_ENOCONV;
     if (stats) {
         if (stats->status) std::memcpy(stats->status, status.data(), sizeof(int) * p->B);
-        stats->cg_iterations = 0;
+        stats->cg_iterations = (long long)cg_total;
         stats->iterations = iterations;
     }
     if (cg_failed && rc == RTE_OK) rc = RTE_ECG;
@@ -676,7 +680,7 @@ int rte_dsa_correct(const rte_problem *p, const double *rho_star, const double *
     int failed = 0;
     if (p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
     int rc = do_dsa(p, L, rho_star, rho_prev, delta_rho, nullptr, 0, cg_rtol, cg_maxit,
-                    cg_iters_out, &failed, s);
+                    cg_iters_out, &failed, nullptr, s);
     if (rc) return rc;
     return failed ? RTE_ECG : RTE_OK;
 }
@@ -710,6 +714,8 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, o->max_iter);
     if (!c.ok) return RTE_ENOMEM;
     HIPCHK(launch_init_state(p, L.st, o->max_iter, nullptr, 1, s));
+    HIPCHK(launch_zero_rows(L.delta, p->B, p->ndof, nullptr, s));
+    HIPCHK(launch_zero_u64(L.cg_total, 1, s));
     if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
     HIPCHK(launch_source(p, rho, L.src, nullptr, o->precision == RTE_MIXED, s));
     int iterations = 0;
@@ -729,6 +735,7 @@ int rte_sisa_begin(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, o->max_iter);
     if (!c.ok) return RTE_ENOMEM;
     HIPCHK(launch_init_state(p, L.st, o->max_iter, nullptr, 0, s));
+    HIPCHK(launch_zero_u64(L.cg_total, 1, s));
     return RTE_OK;
 }
 
@@ -750,6 +757,7 @@ int rte_sisa_admit(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     if (!c.ok) return RTE_ENOMEM;
     HIPCHK(hipMemcpyAsync(L.mask, mask.data(), sizeof(int) * p->B, hipMemcpyHostToDevice, s));
     HIPCHK(launch_init_state(p, L.st, o->max_iter, L.mask, 1, s));
+    HIPCHK(launch_zero_rows(L.delta, p->B, p->ndof, L.mask, s));
     if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, L.mask, s));
     HIPCHK(launch_source(p, rho, L.src, L.mask, o->precision == RTE_MIXED, s));
     // the host mask must outlive the copy

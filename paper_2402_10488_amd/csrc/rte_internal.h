@@ -215,9 +215,11 @@ struct CGSpace {
     int *n_running;                    // [1]
     int nblk;                          // blocks per instance
 };
+// CG start for the instances with kind == want_kind (all if kind is null); guess (nullable)
+// is the previous correction, used as a search direction for the initial iterate
 hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double *rho_star,
-                           const double *rho_prev, const int *kind, int want_kind, double rtol,
-                           hipStream_t s);
+                           const double *rho_prev, const int *kind, int want_kind,
+                           const double *guess, double rtol, hipStream_t s);
 // per-cell operator data, inverse diagonal blocks and (multigrid) the Galerkin vertex operators
 // of the instances with mask[b] == 1 (all if mask is null); once per solve, before any CG call
 hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *mask,
@@ -226,8 +228,10 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
 hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot, hipStream_t s);
 hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, double rtol,
                                int maxit, hipStream_t s);
+// delta = x for the instances of the call; iters_out[b] (nullable) and *total (nullable, summed)
+// receive the iteration counts
 hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delta, int *iters_out,
-                            hipStream_t s);
+                            unsigned long long *total, hipStream_t s);
 size_t cg_blocks_per_instance(const rte_problem *p);
 
 // ROM correction
@@ -265,6 +269,9 @@ hipError_t launch_update(const rte_problem *p, const IterState &st, const double
 hipError_t launch_init_state(const rte_problem *p, const IterState &st, int max_iter,
                              const int *mask, int run, hipStream_t s);
 hipError_t launch_zero(double *x, long long n, hipStream_t s);
+// x[b][:] = 0 for the rows with mask[b] != 0 (every row if mask is null), x is [B][n]
+hipError_t launch_zero_rows(double *x, int B, long long n, const int *mask, hipStream_t s);
 hipError_t launch_fill_int(int *x, long long n, int v, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *x, long long n, hipStream_t s);
 
 }  // namespace rte

@@ -290,6 +290,7 @@ class SolveResult:
     change: np.ndarray
     kind: np.ndarray
     iterations: int
+    cg_iterations: int = 0      # diffusion CG iterations summed over instances and corrections
 
 
 def sisa_solve(p: Problem, rho_inout, mode="si_dsa", rom: Optional[Rom] = None, psi=None,
@@ -312,7 +313,7 @@ def sisa_solve(p: Problem, rho_inout, mode="si_dsa", rom: Optional[Rom] = None, 
                             _ptr(ws), ws.numel(), _stream())
     if raise_on_error and rc not in (RTE_OK, RTE_ENOCONV):
         raise RteError(rc, "rte_sisa_solve")
-    return SolveResult(rc, n_sweep, st, change, kind, stats.iterations)
+    return SolveResult(rc, n_sweep, st, change, kind, stats.iterations, stats.cg_iterations)
 
 
 class Session:
