@@ -126,9 +126,25 @@ typedef struct {
     const double *A;          /* host [m][r][r] */
     double eps_pod;           /* truncation tolerance of the basis (eq. (pod_truncation)) */
     double eps_train;         /* SISA tolerance of the training solves */
+    const double *b_inflow;   /* host [4][r] or NULL: sum_j U_j^T b_j for a unit isotropic inflow on
+                                 each side (x=0, x=Lx, y=0, y=Ly); used by rte_rom_initial_guess
+                                 (NULL: no inflow term) */
 } rte_rom_desc;
 
 int rte_rom_create(const rte_problem *p, const rte_rom_desc *desc, rte_rom **out);
+
+/* ROM initial guess (ROMIG, Sec. 3.1, eq. (rom_parametric)) from a parametric ROM, i.e. one whose
+ * basis U spans converged angular fluxes of training parameters (build it like a correction ROM
+ * with a one-iterate window, whose snapshot columns are the solutions themselves).  Per instance:
+ *   (A0 + sum_k psi_k A_k) c = U^T b,  U^T b = (U^iso)^T q_G + sum_sides g_side b_inflow[side],
+ * q_G the isotropic source load (G sqrt(hx hy) on the cell-mean dof), then rho_out = U^rho c.
+ *   rho_out     device [B][N_DOF]; rows of instances whose reduced system is singular are left
+ *               unchanged (status_out 1), so callers pass zeros there
+ *   status_out  device [B] or NULL; 0 ok, 1 singular
+ * 2D only (RTE_EUNSUPPORTED otherwise).  Workspace as for RTE_ROMSAD with this rom. */
+int rte_rom_initial_guess(const rte_problem *p, const rte_rom *rom, const double *psi,
+                          double *rho_out, int *status_out, void *ws, size_t ws_bytes,
+                          rte_stream_t stream);
 void rte_rom_destroy(rte_rom *rom);
 
 /* Bytes of device workspace the calls below need for (problem, mode, rom, precision) and an
@@ -272,6 +288,12 @@ int rte_apply_streaming(const rte_problem *p, const double *x, int nvec, double 
 
 /* out[v] = sum_j w_j x[v][j] (weighted != 0) or sum_j x[v][j] (weighted == 0) for
  * x [nvec][n_dir][N_DOF], out [nvec][N_DOF]: U^rho and U^iso of eq. (rho_basis). */
+/* out[side][k] = sum_j U_k,j^T b_side,j: projections of the load of a unit isotropic inflow on each
+ * side (x=0, x=Lx, y=0, y=Ly; eq. (dg_matrix_vec)) on the basis vectors U [nvec][n_dir][N_DOF]
+ * (device, direction-major).  out: device [4][nvec].  2D only. */
+int rte_inflow_loads(const rte_problem *p, const double *U, int nvec, double *out,
+                     rte_stream_t stream);
+
 int rte_direction_sum(const rte_problem *p, const double *x, int nvec, int weighted, double *out,
                       rte_stream_t stream);
 

@@ -1120,6 +1120,9 @@ VG vg_of(const MGLevel &l) {
     return g;
 }
 constexpr int kCoarseSweeps = 30;
+// damped Jacobi sweeps before and after the coarse correction on the vertex levels that run as
+// separate launches (the LDS-resident small levels always use two)
+constexpr int kVertexSweeps = 1;
 
 constexpr long long kSmallLds = 64 * 1024;
 
@@ -1174,13 +1177,17 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
     const MGLevel &C = c.mg.lv[l + 1];
     const VG gcv = vg_of(C);
     // two pre-smoothing sweeps from zero, residual, restriction
-    hipLaunchKernelGGL(mg_vpre_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.bv, L.xb);
+    if (kVertexSweeps == 2)
+        hipLaunchKernelGGL(mg_vpre_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.bv, L.xb);
+    else
+        hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xb, L.bv, L.xb, 0);
     hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xb, L.bv, L.rv, 2);
     hipLaunchKernelGGL(mg_vrestrict_kernel, dim3(blocks_for(C.nv, 256), p->B), dim3(256), 0, s,
                        c.state, g, L.rv, gcv, C.bv);
     double *xc = vcycle(p, c, l + 1, s);
     // coarse correction with the first post-smoothing sweep, then the second sweep
     hipLaunchKernelGGL(mg_vpost1_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.bv, L.xb, gcv, xc, L.xa);
+    if (kVertexSweeps == 1) return L.xa;
     hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xa, L.bv, L.xb, 1);
     return L.xb;
 }

@@ -257,6 +257,45 @@ __global__ void direction_sum_kernel(long long ndof, int n_dir, int nvec, const 
     out[(size_t)v * ndof + t] = s;
 }
 
+// out[side][v] = sum_j sum_{cells on the side} U[v][j][cell] . load_j: the load of a unit
+// isotropic inflow on a side (eq. (dg_matrix_vec)) enters the cells next to it for the
+// directions entering there, |v.n| g (h_t / sqrt(hx hy)) L_a(-+1) on the face-normal index a
+// (tangential index 0), h_t the face length.  One workgroup per (vector, side), fixed-order sum.
+__global__ void __launch_bounds__(256) inflow_load_kernel(int nx, int ny, long long ndof, int n_dir,
+                                                         const double *vxy, double hx, double hy,
+                                                         const double *U, int nvec, double *out) {
+    const int v = blockIdx.x, side = blockIdx.y;
+    const bool xs = side < 2;                      // x = 0 / x = Lx faces
+    const int nface = xs ? ny : nx;                // cells along the side
+    const double scale = xs ? sqrt(hy / hx) : sqrt(hx / hy);
+    const double s3 = kS3;
+    double acc = 0.0;
+    for (long long t = threadIdx.x; t < (long long)n_dir * nface; t += blockDim.x) {
+        const int j = (int)(t / nface), m = (int)(t - (long long)j * nface);
+        const double vn = xs ? vxy[j] : vxy[n_dir + j];
+        const bool enters = (side == 0 || side == 2) ? vn > 0.0 : vn < 0.0;
+        if (!enters) continue;
+        int cell;
+        if (side == 0) cell = m * nx;
+        else if (side == 1) cell = m * nx + nx - 1;
+        else if (side == 2) cell = m;
+        else cell = (ny - 1) * nx + m;
+        // trace of the face-normal Legendre index on the face: -sqrt(3) at the low, +sqrt(3) at
+        // the high face of the cell (dof 1 for x faces, dof 2 for y faces)
+        const double tr = (side == 0 || side == 2) ? -s3 : s3;
+        const double *u = U + ((size_t)v * n_dir + j) * ndof + (size_t)cell * 4;
+        acc += fabs(vn) * scale * (u[0] + tr * (xs ? u[1] : u[2]));
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[side * nvec + v] = sh[0];
+}
+
 }  // namespace
 }  // namespace rte
 
@@ -320,6 +359,15 @@ int rte_apply_streaming(const rte_problem *p, const double *x, int nvec, double 
     hipLaunchKernelGGL(apply_streaming_kernel, dim3(cdiv(tot, 256)), dim3(256), 0,
                        (hipStream_t)stream, p->nx, p->ny, p->n_dir, nvec, p->d_vxy,
                        p->d_vxy + p->n_dir, p->hx, p->hy, x, y);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_inflow_loads(const rte_problem *p, const double *U, int nvec, double *out,
+                     rte_stream_t stream) {
+    if (!p || !U || !out || nvec < 1) return RTE_EINVAL;
+    if (p->dim != 2) return RTE_EUNSUPPORTED;
+    hipLaunchKernelGGL(inflow_load_kernel, dim3(nvec, 4), dim3(256), 0, (hipStream_t)stream,
+                       p->nx, p->ny, p->ndof, p->n_dir, p->d_vxy, p->hx, p->hy, U, nvec, out);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 

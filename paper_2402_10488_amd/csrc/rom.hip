@@ -201,6 +201,27 @@ __global__ void __launch_bounds__(64) rom_lift_kernel(long long ndof, int B, int
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+// Reduced load of the ROM initial guess, split over cells like the projections:
+//   ypart[b][split][k] = ghost * sum_{cells of the split} U_iso[cell K][k] G[b][cell]
+//                        (+ sum_side g[b][side] b_in[side][k] in split 0),
+// the isotropic source load being G sqrt(hx hy) on the cell-mean dof of every direction.
+__global__ void __launch_bounds__(64) romig_load_kernel(long long ncell, int K, int r, int nsplit,
+                                                        long long per_split, const double *U_iso,
+                                                        const double *G, double ghost,
+                                                        const double *inflow, const double *b_in,
+                                                        double *ypart) {
+    const int split = blockIdx.x, b = blockIdx.y, k = threadIdx.x;
+    if (k >= r) return;
+    const long long c0 = (long long)split * per_split;
+    const long long c1 = c0 + per_split < ncell ? c0 + per_split : ncell;
+    double s = 0.0;
+    for (long long c = c0; c < c1; ++c) s += U_iso[(size_t)(c * K) * r + k] * G[(size_t)b * ncell + c];
+    s *= ghost;
+    if (split == 0)
+        for (int side = 0; side < 4; ++side) s += inflow[4 * b + side] * b_in[side * r + k];
+    ypart[((size_t)b * nsplit + split) * r + k] = s;
+}
+
 }  // namespace
 
 size_t rom_split(const rte_problem *p, const rte_rom *rom) {
@@ -211,6 +232,23 @@ size_t rom_split(const rte_problem *p, const rte_rom *rom) {
     if (want > maxs) want = maxs;
     if (want < 1) want = 1;
     return (size_t)want;
+}
+
+hipError_t launch_rom_initial_guess(const rte_problem *p, const rte_rom *rom, const double *psi,
+                                    double *rho, int *status, const RomSpace &w, hipStream_t s) {
+    const int r = rom->r;
+    const int nsplit = w.nsplit;
+    long long per_split = (p->ncell + nsplit - 1) / nsplit;
+    hipLaunchKernelGGL(romig_load_kernel, dim3(nsplit, p->B), dim3(64), 0, s, p->ncell, p->K, r,
+                       nsplit, per_split, rom->d_U_iso, p->source, sqrt(p->hx * p->hy),
+                       p->inflow, rom->d_b_in, w.ypart);
+    hipLaunchKernelGGL(rom_solve_kernel, dim3(p->B), dim3(64), 0, s, p->B, r, rom->m, nsplit,
+                       w.ypart, rom->d_A0, rom->d_A, psi, (int *)nullptr, 0, status, w.dc);
+    const int tiles = 4;
+    dim3 gl(cdiv(p->ndof, 16 * tiles), cdiv(p->B, 16));
+    hipLaunchKernelGGL(rom_lift_kernel<double>, gl, dim3(64), 0, s, p->ndof, p->B, r, tiles,
+                       rom->d_U_rho, w.dc, (const int *)nullptr, 0, status, rho);
+    return hipGetLastError();
 }
 
 hipError_t launch_rom_correct(const rte_problem *p, const rte_rom *rom, const double *psi,

@@ -447,7 +447,7 @@ int rte_rom_create(const rte_problem *p, const rte_rom_desc *d, rte_rom **out) {
     r->ndof = p->ndof;
     r->eps_pod = d->eps_pod;
     r->eps_train = d->eps_train;
-    r->d_U_rho = r->d_U_iso = r->d_A0 = r->d_A = nullptr;
+    r->d_U_rho = r->d_U_iso = r->d_A0 = r->d_A = r->d_b_in = nullptr;
     r->d_U_rho_f = r->d_U_iso_f = nullptr;
     std::vector<float> tmp(nu);
     bool ok = true;
@@ -457,6 +457,13 @@ int rte_rom_create(const rte_problem *p, const rte_rom_desc *d, rte_rom **out) {
     ok = ok && hipMalloc(&r->d_U_iso_f, nu * 4) == hipSuccess;
     ok = ok && hipMalloc(&r->d_A0, (size_t)d->r * d->r * 8) == hipSuccess;
     ok = ok && hipMalloc(&r->d_A, std::max<size_t>(1, (size_t)d->m * d->r * d->r) * 8) == hipSuccess;
+    ok = ok && hipMalloc(&r->d_b_in, (size_t)4 * d->r * 8) == hipSuccess;
+    {
+        std::vector<double> bin((size_t)4 * d->r, 0.0);
+        if (d->b_inflow)
+            for (size_t i = 0; i < bin.size(); ++i) bin[i] = d->b_inflow[i];
+        ok = ok && hipMemcpy(r->d_b_in, bin.data(), bin.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    }
     ok = ok && hipMemcpy(r->d_U_rho, d->U_rho, nu * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(r->d_U_iso, d->U_iso, nu * 8, hipMemcpyHostToDevice) == hipSuccess;
     for (size_t i = 0; ok && i < nu; ++i) tmp[i] = (float)d->U_rho[i];
@@ -478,6 +485,7 @@ void rte_rom_destroy(rte_rom *r) {
     if (!r) return;
     if (r->d_U_rho) (void)hipFree(r->d_U_rho);
     if (r->d_U_iso) (void)hipFree(r->d_U_iso);
+    if (r->d_b_in) (void)hipFree(r->d_b_in);
     if (r->d_U_rho_f) (void)hipFree(r->d_U_rho_f);
     if (r->d_U_iso_f) (void)hipFree(r->d_U_iso_f);
     if (r->d_A0) (void)hipFree(r->d_A0);
@@ -683,6 +691,22 @@ int rte_dsa_correct(const rte_problem *p, const double *rho_star, const double *
                     cg_iters_out, &failed, nullptr, s);
     if (rc) return rc;
     return failed ? RTE_ECG : RTE_OK;
+}
+
+int rte_rom_initial_guess(const rte_problem *p, const rte_rom *rom, const double *psi,
+                          double *rho_out, int *status_out, void *ws, size_t ws_bytes,
+                          rte_stream_t stream) {
+    if (!p || !rom || !rho_out || !ws) return RTE_EINVAL;
+    if (rom->m > 0 && !psi) return RTE_EINVAL;
+    if (rom->ndof != p->ndof) return RTE_EINVAL;
+    if (p->dim != 2) return RTE_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, RTE_ROMSAD, rom, RTE_FP64, 1);
+    if (!c.ok) return RTE_ENOMEM;
+    HIPCHK(launch_rom_initial_guess(p, rom, psi, rho_out, status_out ? status_out : L.rom_status,
+                                    L.rom, s));
+    return RTE_OK;
 }
 
 int rte_rom_correct(const rte_problem *p, const rte_rom *rom, const double *psi,

@@ -131,6 +131,7 @@ struct rte_rom {
     float *d_U_iso_f;
     double *d_A0;      // device [r][r]
     double *d_A;       // device [m][r][r]
+    double *d_b_in;    // device [4][r] reduced unit-inflow loads (zeros when not given)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -246,6 +247,9 @@ hipError_t launch_rom_correct(const rte_problem *p, const rte_rom *rom, const do
                               int *status, const int *kind, int want_kind, const RomSpace &w,
                               int fp32, hipStream_t s);
 size_t rom_split(const rte_problem *p, const rte_rom *rom);
+// ROM initial guess: rho = U^rho c, (A0 + sum psi_k A_k) c = (U^iso)^T q_G + sum g_side b_in[side]
+hipError_t launch_rom_initial_guess(const rte_problem *p, const rte_rom *rom, const double *psi,
+                                    double *rho, int *status, const RomSpace &w, hipStream_t s);
 
 // Alg. 1 / Alg. 2 bookkeeping
 struct IterState {

@@ -26,6 +26,7 @@ lib.rte_sym_eig.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
 lib.rte_combine.argtypes = [_vp, ctypes.c_int, ctypes.c_longlong, _vp, ctypes.c_int, _vp, _vp]
 lib.rte_apply_streaming.argtypes = [_vp, _vp, ctypes.c_int, _vp, _vp]
 lib.rte_direction_sum.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
+lib.rte_inflow_loads.argtypes = [_vp, _vp, ctypes.c_int, _vp, _vp]
 
 
 @dataclass
@@ -38,6 +39,7 @@ class RomArrays:
     eps_pod: float
     eps_train: float
     n_sweep_train: np.ndarray
+    b_inflow: np.ndarray = None   # [4, r] reduced loads of unit side inflows (initial guess)
 
 
 def gram(X, Y, cell_class=None, K=4, ncell=1, cls=0, scratch=None):
@@ -78,6 +80,15 @@ def apply_streaming(P, x):
     _check(lib.rte_apply_streaming(P.handle, _ptr(x), x.shape[0], _ptr(y), _stream()),
            "rte_apply_streaming")
     return y
+
+
+def inflow_loads(P, U3):
+    """[4, nvec] projections of unit side-inflow loads on U3 [nvec][n_dir][N_DOF]."""
+    import torch
+    out = torch.empty((4, U3.shape[0]), dtype=torch.float64, device=U3.device)
+    _check(lib.rte_inflow_loads(P.handle, _ptr(U3.contiguous()), U3.shape[0], _ptr(out), _stream()),
+           "rte_inflow_loads")
+    return out
 
 
 def direction_sum(P, x, weighted):
@@ -162,6 +173,17 @@ def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=N
     At = [gram(dU, dU, cls_d, 4, P.ncell, k, scratch) for k in range(ncls)]
     As = [-gram(U_iso, U_rho, cls_d, 4, P.ncell, k, scratch) for k in range(ncls)]
     A = torch.stack(At + As).cpu().numpy()
+    b_in = inflow_loads(P, dU3).cpu().numpy()
     torch.cuda.synchronize()
     return RomArrays(U_rho.T.contiguous().cpu().numpy(), U_iso.T.contiguous().cpu().numpy(),
-                     A0.cpu().numpy(), A, sv, eps_eff, eps_train, np.asarray(n_sweep))
+                     A0.cpu().numpy(), A, sv, eps_eff, eps_train, np.asarray(n_sweep), b_in)
+
+
+def build_parametric_rom(train_plane, r=20, eps_train=1e-10, eps_pod=None, cg_rtol=1e-12,
+                         classes=None) -> RomArrays:
+    """Parametric ROM of Sec. 3.1 for the ROM initial guess (eq. (rom_parametric)): POD of the
+    converged angular fluxes of the training parameters.  Those are the snapshot columns of the
+    correction ROM with a one-iterate window (f - f^(0) = f), so the same construction applies;
+    the reduced unit-inflow loads come with it."""
+    return build_correction_rom(train_plane, r=r, window=1, eps_train=eps_train, eps_pod=eps_pod,
+                                cg_rtol=cg_rtol, classes=classes)

@@ -44,7 +44,7 @@ class ProblemDesc(ctypes.Structure):
 class RomDesc(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int), ("m", ctypes.c_int), ("U_rho", _D), ("U_iso", _D),
                 ("A0", _D), ("A", _D), ("eps_pod", ctypes.c_double),
-                ("eps_train", ctypes.c_double)]
+                ("eps_train", ctypes.c_double), ("b_inflow", _D)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -96,6 +96,7 @@ def _load():
     L.rte_sisa_iterate.argtypes = [P, ctypes.c_int, P, _vp, ctypes.POINTER(SolveOpts), _vp,
                                    ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(SolveStats), _vp, ctypes.c_size_t, _vp]
+    L.rte_rom_initial_guess.argtypes = [P, P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.rte_problem_dsa_multigrid.argtypes = [P, ctypes.c_int]
     L.rte_profile_enable.argtypes = [ctypes.c_int]
     L.rte_profile_read.argtypes = [ctypes.c_int, _D, ctypes.POINTER(ctypes.c_longlong)]
@@ -110,7 +111,8 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_rom_correct", "rte_sisa_solve", "rte_strerror", "rte_profile_enable",
             "rte_profile_read", "rte_problem_dsa_multigrid", "rte_pod_snapshots", "rte_gram",
             "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum",
-            "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate"]
+            "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
+            "rte_inflow_loads"]
 
 PROF = {"sweep2d": 0, "reduce": 1, "dsa": 2, "rom": 3, "sweep1d": 4}
 
@@ -225,9 +227,10 @@ class Problem:
 
 
 class Rom:
-    """Correction ROM operators (host arrays, copied to the device at creation)."""
+    """ROM operators (host arrays, copied to the device at creation): a correction ROM for ROMSA,
+    or a parametric one (with b_inflow [4][r]) for the ROM initial guess."""
 
-    def __init__(self, problem: Problem, U_rho, U_iso, A0, A, eps_pod, eps_train):
+    def __init__(self, problem: Problem, U_rho, U_iso, A0, A, eps_pod, eps_train, b_inflow=None):
         self._u_rho, pur = _host(U_rho)
         self._u_iso, pui = _host(U_iso)
         self._a0, pa0 = _host(A0)
@@ -236,7 +239,10 @@ class Rom:
         self.r = int(self._a0.shape[0])
         self.m = int(A.shape[0])
         assert self._u_rho.shape == (problem.ndof, self.r)
-        d = RomDesc(self.r, self.m, pur, pui, pa0, pa, float(eps_pod), float(eps_train))
+        pb = None
+        if b_inflow is not None:
+            self._b_in, pb = _host(np.asarray(b_inflow).reshape(4, self.r))
+        d = RomDesc(self.r, self.m, pur, pui, pa0, pa, float(eps_pod), float(eps_train), pb)
         h = ctypes.c_void_p()
         _check(lib.rte_rom_create(problem.handle, ctypes.byref(d), ctypes.byref(h)), "rte_rom_create")
         self.handle = h
@@ -272,6 +278,14 @@ def dsa_correct(p: Problem, rho_star, rho_prev, delta_out, cg_rtol=1e-10, cg_max
     _check(lib.rte_dsa_correct(p.handle, _ptr(rho_star), _ptr(rho_prev), _ptr(delta_out),
                                float(cg_rtol), int(cg_maxit), _ptr(iters_out), _ptr(ws), ws.numel(),
                                _stream()), "rte_dsa_correct")
+
+
+def rom_initial_guess(p: Problem, rom: Rom, psi, rho_out, status_out=None, ws=None):
+    """ROMIG: rho_out = U^rho c with the reduced parametric system of every instance."""
+    ws = ws if ws is not None else p.workspace("romsad", rom, "fp64")
+    _check(lib.rte_rom_initial_guess(p.handle, rom.handle, _ptr(psi), _ptr(rho_out),
+                                     _ptr(status_out), _ptr(ws), ws.numel(), _stream()),
+           "rte_rom_initial_guess")
 
 
 def rom_correct(p: Problem, rom: Rom, psi, rho_star, rho_prev, delta_out, status_out=None,
