@@ -93,6 +93,9 @@ class PlaneDisc:
             self.vx, self.vy, self.w = (np.asarray(a, dtype=np.float64) for a in dirs)
         elif kind == "cheb":
             self.vx, self.vy, self.w = quadrature.chebyshev_circle(n)
+        elif kind == "cl":
+            # CL(N_phi, N_vz) on the sphere (Sec. 2.1); X-Y geometry sees (vx, vy) only
+            self.vx, self.vy, _, self.w = quadrature.chebyshev_legendre(*n)
         else:
             raise ValueError(kind)
         self.nv = len(self.vx)

@@ -12,9 +12,7 @@ def _dev(a, device="cuda"):
 
 def plane_problem(plane, device="cuda", dg=0, wpb=0) -> Problem:
     """Problem handle for every instance of a 2D description (materials uploaded to ``device``)."""
-    kind, n = plane.quad
-    assert kind == "cheb"
-    vx, vy, w = quadrature.chebyshev_circle(n)
+    vx, vy, w = quadrature.plane_rule(plane.quad)
     return Problem(2, plane.nx, plane.ny, vx, w, _dev(plane.sigma_t, device), _dev(plane.sigma_s, device),
                    _dev(plane.G, device), _dev(plane.g, device), dirs_y=vy, lx=plane.Lx, ly=plane.Ly,
                    dg=dg, wpb=wpb)

@@ -25,6 +25,7 @@ __all__ = [
     "Slab", "Plane", "slab_uniform", "c0_slab", "cross_regime", "two_material",
     "window_demo", "plane_uniform", "c1_checkerboard", "c2_lattice", "c2_batch",
     "c2_training", "c3_requests", "c4_multiscale", "c4_training", "random_plane",
+    "homogeneous_medium", "lattice_medium",
     "random_slab", "Request",
 ]
 
@@ -148,7 +149,8 @@ class Plane:
     ``block`` maps every cell to a material block id ([ny, nx], shared by the
     batch) and ``block_sigma_t``/``block_sigma_s`` are the per-instance block
     values [B, nblocks] the cell arrays were filled from (affine parameters).
-    ``quad = ("cheb", N_phi)`` is the normalized Chebyshev rule on the unit circle.
+    ``quad = ("cheb", N_phi)`` is the normalized Chebyshev rule on the unit circle,
+    ``("cl", (N_phi, N_vz))`` the Chebyshev-Legendre rule on the sphere.
     """
     nx: int
     ny: int
@@ -161,7 +163,7 @@ class Plane:
     block: np.ndarray
     block_sigma_t: np.ndarray
     block_sigma_s: np.ndarray
-    quad: Tuple[str, int] = ("cheb", 64)
+    quad: Tuple = ("cheb", 64)
     name: str = "plane"
     seeds: Tuple[int, ...] = field(default_factory=tuple)
 
@@ -220,6 +222,39 @@ def _central_source(n: int, lo: float = 0.375, hi: float = 0.625) -> np.ndarray:
     xc = (np.arange(n) + 0.5) / n
     inside = (xc > lo) & (xc < hi)
     return (inside[:, None] & inside[None, :]).astype(np.float64)
+
+
+def homogeneous_medium(mu_s: Sequence[float], n: int = 80, quad=("cl", (30, 6))) -> Plane:
+    """Stand-in for the paper's homogeneous-medium family (Sec. 4.3.1): [0,1]^2, vacuum,
+    sigma_a = 0, sigma_s = mu_s, G = exp(-100 |x - (0.5, 0.5)|^2) taken at the cell centres
+    (the library uses cell-constant data), one instance per mu_s."""
+    B = len(mu_s)
+    block = np.zeros((n, n), np.int32)
+    bss = np.asarray(mu_s, np.float64)[:, None]
+    xc = (np.arange(n) + 0.5) / n
+    Gc = np.exp(-100.0 * ((xc[None, :] - 0.5) ** 2 + (xc[:, None] - 0.5) ** 2))
+    G = np.broadcast_to(Gc, (B, n, n)).copy()
+    return Plane(n, n, 1.0, 1.0, _fill(block, bss), _fill(block, bss), G, np.zeros((B, 4)),
+                 block, bss.copy(), bss.copy(), quad, f"homogeneous_{n}x{n}_B{B}")
+
+
+def lattice_medium(params: Sequence[Tuple[float, float]], n: int = 50,
+                   quad=("cl", (40, 6))) -> Plane:
+    """Stand-in for the paper's lattice family (Sec. 4.3.2): [0,5]^2 split into 5 x 5 unit
+    blocks; absorbing blocks (sigma_a, sigma_s) = (mu_a, 0) where bx + by is odd, scattering
+    blocks (0, mu_s) elsewhere; G = 1 on the centre block |x - 2.5|, |y - 2.5| < 0.5; vacuum.
+    (The paper's figure fixes its own absorber pattern; this checkerboard is the reading used.)"""
+    B = len(params)
+    block = _checker_blocks(n, n, 5, 5)
+    absorb = np.array([((b % 5) + (b // 5)) % 2 == 1 for b in range(25)])
+    mu_a = np.array([p[0] for p in params], np.float64)[:, None]
+    mu_s = np.array([p[1] for p in params], np.float64)[:, None]
+    bst = np.where(absorb[None, :], mu_a, mu_s)
+    bss = np.where(absorb[None, :], 0.0, mu_s)
+    Gb = np.zeros((B, 25))
+    Gb[:, 12] = 1.0
+    return Plane(n, n, 5.0, 5.0, _fill(block, bst), _fill(block, bss), _fill(block, Gb),
+                 np.zeros((B, 4)), block, bst, bss, quad, f"lattice_{n}x{n}_B{B}")
 
 
 def c1_checkerboard(n: int = 128, n_phi: int = 64) -> Plane:

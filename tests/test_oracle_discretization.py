@@ -241,3 +241,4 @@ def test_point_symmetry_of_checkerboard():
     r = sisa(d, "si_dsa", eps=1e-12)
     m = r.rho.reshape(32, 32, 4)[..., 0]
     assert np.abs(m - m[::-1, ::-1]).max() < 1e-11 * np.abs(m).max()
+
