@@ -222,6 +222,41 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
                    rte_solve_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream);
 
 /* ------------------------------------------------------------------------------------------
+ * DSA-preconditioned restarted GMRES (the paper's Krylov baseline: Sec. 2.4 and the appendix on
+ * restarted GMRES).  For every instance it solves the left-preconditioned system
+ *   (I + C Sigma_s)(I - L) rho = (I + C Sigma_s) b_bar
+ * with L v the density of one sweep of the source Sigma_s v (no G, vacuum inflow), b_bar the
+ * density of one sweep from rho = 0, and C Sigma_s the diffusion correction of rte_dsa_correct.
+ * GMRES(restart): Arnoldi (classical Gram-Schmidt with one reorthogonalization), Givens
+ * rotations; an instance stops once its estimated preconditioned residual is at most
+ * tol * |(I + C Sigma_s) b_bar| and the residual recomputed from the iterate (one sweep) passes
+ * too; otherwise it restarts from the iterate.  All FP64.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+    double tol;               /* relative residual of the preconditioned system */
+    int restart;              /* Arnoldi steps per cycle, 1..200 */
+    int max_cycles;           /* cycles before RTE_ENOCONV */
+    double cg_rtol;           /* diffusion CG tolerance (preconditioner) */
+    int cg_maxit;
+    int precondition;         /* 0: plain GMRES on (I - L) */
+} rte_krylov_opts;
+
+typedef struct {
+    int *n_sweep;             /* [B] transport sweeps (right-hand side, every (re)start, every step) */
+    int *iterations;          /* [B] Arnoldi steps */
+    int *status;              /* [B] RTE_OK or RTE_ENOCONV */
+    double *residual;         /* [B] estimated relative residual at the last step */
+    int cycles;               /* out: cycles run by the batch */
+} rte_krylov_stats;
+
+int rte_pgmres_workspace_size(const rte_problem *p, int restart, size_t *bytes);
+
+/* rho: device [B][N_DOF], initial guess in (zeros, or e.g. rte_rom_initial_guess), solution out.
+ * stats: host arrays (any may be NULL).  Returns RTE_ENOCONV if an instance did not converge. */
+int rte_pgmres_solve(const rte_problem *p, const rte_krylov_opts *opts, double *rho,
+                     rte_krylov_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream);
+
+/* ------------------------------------------------------------------------------------------
  * Resumable solve for serving (continuous batching).  The problem's B instances are slots; the
  * workspace keeps every slot's Alg. 1 state between calls, so requests can be admitted into free
  * slots while others are mid-iteration.  Each slot counts its own sweeps l (stop test, ROMSAD

@@ -111,7 +111,7 @@ __global__ void dsa1d_kernel(int nc, int B, const double *h, const double *sigma
         double r[4];
         for (int k = 0; k < 2; ++k) {
             const size_t i = ((size_t)b * nc + c) * 2 + k;
-            r[k] = ss * (rho_star[i] - rho_prev[i]);
+            r[k] = ss * (rho_star[i] - (rho_prev ? rho_prev[i] : 0.0));
             r[2 + k] = 0.0;
         }
         for (int i = 0; i < 16; ++i) Dp[i] = Dg[i];
@@ -440,7 +440,8 @@ __global__ void __launch_bounds__(kCgBlock) cg_warm_kernel(MipArgs a, const doub
         const double ss = a.sigma_s[gi];
         double rs[4], rp[4], bv[4], dc[4], y[4];
         load4(rho_star, gi, rs);
-        load4(rho_prev, gi, rp);
+        if (rho_prev) load4(rho_prev, gi, rp);
+        else rp[0] = rp[1] = rp[2] = rp[3] = 0.0;
         for (int k = 0; k < 4; ++k) bv[k] = ss * (rs[k] - rp[k]);
         auto dat = [&](long long c, double v[4]) { load4(d, base + c, v); };
         mip_apply(a, b, (int)(cell % a.nx), (int)(cell / a.nx), dat, y);
@@ -495,7 +496,8 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
             const double ss = a.sigma_s[gi];
             double rs[4], rp[4];
             load4(rho_star, gi, rs);
-            load4(rho_prev, gi, rp);
+            if (rho_prev) load4(rho_prev, gi, rp);
+        else rp[0] = rp[1] = rp[2] = rp[3] = 0.0;
             for (int k = 0; k < 4; ++k) { bv[k] = ss * (rs[k] - rp[k]); xv[k] = 0.0; rv[k] = bv[k]; }
         }
         store4(x, gi, xv);

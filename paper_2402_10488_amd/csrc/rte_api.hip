@@ -47,13 +47,14 @@ struct Layout {
     unsigned long long *cg_total;   // CG iterations summed over instances and calls
     int *flag;
     int *mask;              // [B] instances selected by rte_sisa_admit
+    GmresSpace gm;          // DSA-preconditioned GMRES (rte_pgmres_solve)
     double *sink;           // [8] target of the sweep's stores from idle lanes
 };
 
 int nparts_for(const rte_problem *p) { return sweep_nparts(p); }
 
 Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
-             rte_precision prec, int max_iter) {
+             rte_precision prec, int max_iter, int gm_m = 0) {
     Layout L;
     std::memset(&L, 0, sizeof(L));
     const size_t B = p->B, nd = p->ndof;
@@ -119,6 +120,36 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
         L.rom.ypart = c.take<double>(B * (size_t)L.rom.nsplit * rom->r);
         L.rom.dc = c.take<double>(B * (size_t)rom->r);
         L.rom_status = c.take<int>(B);
+    }
+    if (gm_m > 0) {
+        GmresSpace &g = L.gm;
+        g.m = gm_m;
+        g.nblk = gmres_blocks(p);
+        g.nslot = gm_m + 2;
+        g.normslot = gm_m + 1;
+        g.V = c.take<double>((size_t)(gm_m + 1) * B * nd);
+        g.w = c.take<double>(B * nd);
+        g.t = c.take<double>(B * nd);
+        g.u = c.take<double>(B * nd);
+        g.bbar = c.take<double>(B * nd);
+        g.lv = c.take<double>(B * nd);
+        g.part = c.take<double>(B * (size_t)g.nslot * g.nblk);
+        g.h = c.take<double>(B * (size_t)g.nslot);
+        g.h2 = c.take<double>(B * (size_t)g.nslot);
+        g.H = c.take<double>(B * (size_t)(gm_m + 1) * gm_m);
+        g.cs = c.take<double>(B * (size_t)gm_m);
+        g.sn = c.take<double>(B * (size_t)gm_m);
+        g.y = c.take<double>(B * (size_t)gm_m);
+        g.g = c.take<double>(B * (size_t)(gm_m + 1));
+        g.nb = c.take<double>(B);
+        g.est = c.take<double>(B);
+        g.wn = c.take<double>(B);
+        g.act = c.take<int>(B);
+        g.cyc = c.take<int>(B);
+        g.kused = c.take<int>(B);
+        g.n_sweep = c.take<int>(B);
+        g.n_iter = c.take<int>(B);
+        g.count = c.take<int>(1);
     }
     return L;
 }
@@ -414,6 +445,14 @@ int rte_workspace_size(const rte_problem *p, rte_mode mode, const rte_rom *rom,
     if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
     Carver c(nullptr, 0);
     carve(c, p, mode, rom, prec, max_iter);
+    *bytes = c.off;
+    return RTE_OK;
+}
+
+int rte_pgmres_workspace_size(const rte_problem *p, int restart, size_t *bytes) {
+    if (!p || !bytes || restart < 1 || restart > 200) return RTE_EINVAL;
+    Carver c(nullptr, 0);
+    carve(c, p, RTE_SI_DSA, nullptr, RTE_FP64, 1, restart);
     *bytes = c.off;
     return RTE_OK;
 }
@@ -747,6 +786,114 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     rc = run_iterations(p, L, mode, rom, psi, o, rho, f_out, o->max_iter, s, &iterations, &cg_failed);
     if (rc) return rc;
     return finish_stats(p, L, o->max_iter, iterations, cg_failed, nullptr, stats, s);
+}
+
+int rte_pgmres_solve(const rte_problem *p, const rte_krylov_opts *o, double *rho,
+                     rte_krylov_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream) {
+    if (!p || !o || !rho || !ws) return RTE_EINVAL;
+    if (!(o->tol > 0.0) || o->restart < 1 || o->restart > 200 || o->max_cycles < 1) return RTE_EINVAL;
+    if (o->precondition && p->dim == 2 && (!(o->cg_rtol > 0.0) || o->cg_maxit < 1)) return RTE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, RTE_SI_DSA, nullptr, RTE_FP64, 1, o->restart);
+    if (!c.ok) return RTE_ENOMEM;
+    const GmresSpace &G = L.gm;
+    const int m = o->restart;
+    const size_t vstride = (size_t)p->B * p->ndof;
+    bool cg_failed = false;
+    // M^-1 in = in + C Sigma_s in (DSA correction of the residual in), for the flagged instances
+    auto minv = [&](const double *in, double *out, const int *flag) -> int {
+        if (!o->precondition) {
+            HIPCHK(gm_lincomb(p, in, nullptr, 0.0, nullptr, 0.0, out, flag, s));
+            return RTE_OK;
+        }
+        int failed = 0;
+        int rc = do_dsa(p, L, in, nullptr, L.delta, flag, 1, o->cg_rtol, o->cg_maxit, nullptr,
+                        &failed, nullptr, s);
+        if (rc) return rc;
+        cg_failed = cg_failed || failed;
+        HIPCHK(gm_lincomb(p, in, L.delta, 1.0, nullptr, 0.0, out, flag, s));
+        return RTE_OK;
+    };
+    // density of one sweep: with_G and vacuum/physical inflow per `homogeneous`
+    auto sweep = [&](const double *in, double *out, const int *flag, bool homogeneous) -> int {
+        HIPCHK(launch_source(p, in, L.src, flag, 0, s, !homogeneous));
+        int rc = do_sweep(p, L, L.src, nullptr, out, nullptr, flag, homogeneous ? 1 : 0, 0, s);
+        if (rc) return rc;
+        HIPCHK(gm_count_sweep(p, G, flag, s));
+        return RTE_OK;
+    };
+    auto read_count = [&](int *v) -> int {
+        HIPCHK(hipMemcpyAsync(v, G.count, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return RTE_OK;
+    };
+    int rc;
+    HIPCHK(launch_fill_int(G.act, p->B, 1, s));
+    HIPCHK(launch_fill_int(G.n_sweep, p->B, 0, s));
+    HIPCHK(launch_fill_int(G.n_iter, p->B, 0, s));
+    if (o->precondition && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
+    // b_bar: one sweep from zero with the source and the inflow; |M^-1 b_bar|
+    HIPCHK(launch_zero_rows(G.u, p->B, p->ndof, nullptr, s));
+    if ((rc = sweep(G.u, G.bbar, G.act, false))) return rc;
+    if ((rc = minv(G.bbar, G.w, G.act))) return rc;
+    HIPCHK(gm_norm(p, G, G.w, G.act, s));
+    HIPCHK(gm_sqrt_norm(p, G, G.act, G.nb, s));
+    int cycles = 0;
+    for (int cyc = 0; cyc < o->max_cycles; ++cyc) {
+        // (re)start: r = M^-1 (b_bar - x + L x)
+        if ((rc = sweep(rho, G.lv, G.act, true))) return rc;
+        HIPCHK(gm_lincomb(p, G.bbar, rho, -1.0, G.lv, 1.0, G.t, G.act, s));
+        if ((rc = minv(G.t, G.w, G.act))) return rc;
+        HIPCHK(gm_norm(p, G, G.w, G.act, s));
+        HIPCHK(launch_fill_int(G.count, 1, 0, s));
+        HIPCHK(gm_cycle_start(p, G, o->tol, s));
+        HIPCHK(gm_scale(p, G, G.w, G.g, m + 1, 0, G.V, G.cyc, s));
+        int running = 0;
+        if ((rc = read_count(&running))) return rc;
+        if (running == 0) break;
+        ++cycles;
+        for (int i = 0; i < m; ++i) {
+            double *Vi = G.V + (size_t)i * vstride;
+            // w = M^-1 (V_i - L V_i)
+            if ((rc = sweep(Vi, G.lv, G.cyc, true))) return rc;
+            HIPCHK(gm_lincomb(p, Vi, G.lv, -1.0, nullptr, 0.0, G.u, G.cyc, s));
+            if ((rc = minv(G.u, G.w, G.cyc))) return rc;
+            // classical Gram-Schmidt, twice: h = V^T w, w -= V h (coefficients summed over passes)
+            HIPCHK(gm_dots(p, G, i + 1, G.V, G.w, G.cyc, G.h, 0, s));
+            HIPCHK(gm_axpy(p, G, i + 1, G.V, G.h, G.nslot, -1.0, G.w, G.cyc, false, s));
+            HIPCHK(gm_dots(p, G, i + 1, G.V, G.w, G.cyc, G.h2, 0, s));
+            HIPCHK(gm_resum(p, G, i + 1, G.cyc, G.h, 1, s));
+            HIPCHK(gm_axpy(p, G, i + 1, G.V, G.h2, G.nslot, -1.0, G.w, G.cyc, true, s));
+            HIPCHK(launch_fill_int(G.count, 1, 0, s));
+            HIPCHK(gm_givens(p, G, i, o->tol, s));
+            HIPCHK(gm_scale(p, G, G.w, G.wn, 1, 0, G.V + (size_t)(i + 1) * vstride, G.cyc, s));
+            if ((rc = read_count(&running))) return rc;
+            if (running == 0) break;
+        }
+        // x += V y for every running instance (the minimizer over its cycle's steps)
+        HIPCHK(gm_solve(p, G, s));
+        HIPCHK(gm_axpy(p, G, m, G.V, G.y, m, 1.0, rho, G.act, false, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int> act(p->B);
+    HIPCHK(hipMemcpy(act.data(), G.act, sizeof(int) * p->B, hipMemcpyDeviceToHost));
+    int status = RTE_OK;
+    for (int b = 0; b < p->B; ++b)
+        if (act[b]) status = RTE_ENOCONV;
+    if (stats) {
+        if (stats->n_sweep)
+            HIPCHK(hipMemcpy(stats->n_sweep, G.n_sweep, sizeof(int) * p->B, hipMemcpyDeviceToHost));
+        if (stats->iterations)
+            HIPCHK(hipMemcpy(stats->iterations, G.n_iter, sizeof(int) * p->B, hipMemcpyDeviceToHost));
+        if (stats->residual)
+            HIPCHK(hipMemcpy(stats->residual, G.est, sizeof(double) * p->B, hipMemcpyDeviceToHost));
+        if (stats->status)
+            for (int b = 0; b < p->B; ++b) stats->status[b] = act[b] ? RTE_ENOCONV : RTE_OK;
+        stats->cycles = cycles;
+    }
+    if (cg_failed && status == RTE_OK) status = RTE_ECG;
+    return status;
 }
 
 int rte_sisa_begin(const rte_problem *p, rte_mode mode, const rte_rom *rom, const rte_solve_opts *o,

@@ -163,8 +163,9 @@ hipError_t launch_sweep1d(const rte_problem *p, const void *src, void *f_out, co
                           int zero_inflow, int fp32, hipStream_t s);
 
 // sweep input block from rho: src = sigma_s rho + G * (cell integral of phi_0), plus sigma_t
+// (with_G false: src = sigma_s rho, the source of L rho)
 hipError_t launch_source(const rte_problem *p, const double *rho, void *src, const int *active,
-                         int fp32, hipStream_t s);
+                         int fp32, hipStream_t s, bool with_G = true);
 
 // rho = sum of nparts partial slots (fixed order); optional change/magnitude maxima per instance
 hipError_t launch_reduce_parts(const rte_problem *p, const double *partial, int nparts,
@@ -250,6 +251,49 @@ size_t rom_split(const rte_problem *p, const rte_rom *rom);
 // ROM initial guess: rho = U^rho c, (A0 + sum psi_k A_k) c = (U^iso)^T q_G + sum g_side b_in[side]
 hipError_t launch_rom_initial_guess(const rte_problem *p, const rte_rom *rom, const double *psi,
                                     double *rho, int *status, const RomSpace &w, hipStream_t s);
+
+// DSA-preconditioned restarted GMRES (krylov.hip); per-instance FP64 state
+struct GmresSpace {
+    int m;                 // restart length
+    int nblk;              // reduction blocks per instance
+    int nslot, normslot;   // partial / coefficient slots per instance: m + 2, the last for |w|^2
+    double *V;             // [m+1][B][ndof] Krylov basis
+    double *w, *t, *u, *bbar, *lv;   // [B][ndof]
+    double *part;          // [B][nslot][nblk]
+    double *h, *h2;        // [B][nslot] Gram-Schmidt coefficients of the two passes
+    double *H;             // [B][m+1][m] Hessenberg matrix (rotated)
+    double *cs, *sn, *y;   // [B][m]
+    double *g;             // [B][m+1] rotated residual vector
+    double *nb;            // [B] |M^-1 b_bar|
+    double *est;           // [B] estimated relative residual of the last step
+    double *wn;            // [B] norm of the newest orthogonalized vector
+    int *act;              // [B] 1 while the instance's solve runs
+    int *cyc;              // [B] 1 while it extends its Krylov space in the current cycle
+    int *kused;            // [B] steps of the current cycle
+    int *n_sweep, *n_iter; // [B]
+    int *count;            // [1] instances still extending (host reads it)
+};
+int gmres_blocks(const rte_problem *p);
+hipError_t gm_dots(const rte_problem *p, const GmresSpace &g, int nv, const double *X,
+                   const double *w, const int *flag, double *dst, int accumulate, hipStream_t s);
+hipError_t gm_resum(const rte_problem *p, const GmresSpace &g, int nv, const int *flag,
+                    double *dst, int accumulate, hipStream_t s);
+hipError_t gm_axpy(const rte_problem *p, const GmresSpace &g, int nv, const double *X,
+                   const double *c, int cstride, double sign, double *w, const int *flag,
+                   bool norm, hipStream_t s);
+hipError_t gm_lincomb(const rte_problem *p, const double *a, const double *x, double sa,
+                      const double *y, double sb, double *out, const int *flag, hipStream_t s);
+hipError_t gm_norm(const rte_problem *p, const GmresSpace &g, const double *w, const int *flag,
+                   hipStream_t s);
+hipError_t gm_sqrt_norm(const rte_problem *p, const GmresSpace &g, const int *flag, double *out,
+                        hipStream_t s);
+hipError_t gm_scale(const rte_problem *p, const GmresSpace &g, const double *w, const double *sv,
+                    int sstride, int sslot, double *out, const int *flag, hipStream_t s);
+hipError_t gm_cycle_start(const rte_problem *p, const GmresSpace &g, double tol, hipStream_t s);
+hipError_t gm_givens(const rte_problem *p, const GmresSpace &g, int i, double tol, hipStream_t s);
+hipError_t gm_solve(const rte_problem *p, const GmresSpace &g, hipStream_t s);
+hipError_t gm_count_sweep(const rte_problem *p, const GmresSpace &g, const int *flag,
+                          hipStream_t s);
 
 // Alg. 1 / Alg. 2 bookkeeping
 struct IterState {

@@ -439,7 +439,7 @@ __global__ void source_kernel(int dim, long long ncell, int K, int B, int nx, in
     if (active && active[b] == 0) return;
     const long long cell = t - (long long)b * ncell;
     const double ss = sigma_s[t];
-    const double g0 = G[t] * (cellw ? sqrt(cellw[cell]) : ghost);
+    const double g0 = G ? G[t] * (cellw ? sqrt(cellw[cell]) : ghost) : 0.0;   // G null: no source
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < K; ++k) v[k] = ss * rho[t * K + k] + (k == 0 ? g0 : 0.0);
     write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, v, sigma_t[t], src);
@@ -635,19 +635,19 @@ hipError_t launch_sweep1d(const rte_problem *p, const void *src, void *f_out, co
 }
 
 hipError_t launch_source(const rte_problem *p, const double *rho, void *src, const int *active,
-                         int fp32, hipStream_t s) {
+                         int fp32, hipStream_t s, bool with_G) {
     const long long n = (long long)p->B * p->ncell;
     const double ghost = sqrt(p->hx * p->hy);
     const double *cw = p->dim == 1 ? p->d_widths : nullptr;
+    const double *G = with_G ? p->source : nullptr;
     if (fp32)
         hipLaunchKernelGGL(source_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->dim,
                            p->ncell, p->K, p->B, p->nx, p->ny, rho, p->sigma_t, p->sigma_s,
-                           p->source, cw, ghost, (float *)src, active);
+                           G, cw, ghost, (float *)src, active);
     else
         hipLaunchKernelGGL(source_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            p->dim, p->ncell, p->K, p->B, p->nx, p->ny, rho, p->sigma_t,
-                           p->sigma_s, p->source, cw, ghost,
-                           (double *)src, active);
+                           p->sigma_s, G, cw, ghost, (double *)src, active);
     return hipGetLastError();
 }
 

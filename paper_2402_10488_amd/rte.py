@@ -60,6 +60,19 @@ class SolveStats(ctypes.Structure):
                 ("cg_iterations", ctypes.c_longlong), ("iterations", ctypes.c_int)]
 
 
+class KrylovOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_cycles", ctypes.c_int),
+                ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
+                ("precondition", ctypes.c_int)]
+
+
+class KrylovStats(ctypes.Structure):
+    _fields_ = [("n_sweep", ctypes.POINTER(ctypes.c_int)),
+                ("iterations", ctypes.POINTER(ctypes.c_int)),
+                ("status", ctypes.POINTER(ctypes.c_int)), ("residual", _D),
+                ("cycles", ctypes.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2402_10488_amd/build.py "
@@ -97,6 +110,9 @@ def _load():
                                    ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(SolveStats), _vp, ctypes.c_size_t, _vp]
     L.rte_rom_initial_guess.argtypes = [P, P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.rte_pgmres_workspace_size.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.rte_pgmres_solve.argtypes = [P, ctypes.POINTER(KrylovOpts), _vp, ctypes.POINTER(KrylovStats),
+                                   _vp, ctypes.c_size_t, _vp]
     L.rte_problem_dsa_multigrid.argtypes = [P, ctypes.c_int]
     L.rte_profile_enable.argtypes = [ctypes.c_int]
     L.rte_profile_read.argtypes = [ctypes.c_int, _D, ctypes.POINTER(ctypes.c_longlong)]
@@ -112,7 +128,7 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_profile_read", "rte_problem_dsa_multigrid", "rte_pod_snapshots", "rte_gram",
             "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum",
             "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
-            "rte_inflow_loads"]
+            "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve"]
 
 PROF = {"sweep2d": 0, "reduce": 1, "dsa": 2, "rom": 3, "sweep1d": 4}
 
@@ -209,6 +225,13 @@ class Problem:
         import torch
         nb = self.workspace_bytes(mode, rom, precision, max_iter)
         return torch.empty(max(nb, 256), dtype=torch.uint8, device=self.sigma_t.device)
+
+    def pgmres_workspace(self, restart=25):
+        import torch
+        n = ctypes.c_size_t()
+        _check(lib.rte_pgmres_workspace_size(self.handle, int(restart), ctypes.byref(n)),
+               "rte_pgmres_workspace_size")
+        return torch.empty(max(n.value, 256), dtype=torch.uint8, device=self.sigma_t.device)
 
     def check(self, ws=None):
         ws = ws if ws is not None else self.workspace()
@@ -389,3 +412,31 @@ class Session:
                                         ctypes.byref(stats), _ptr(self.ws), self.ws.numel(),
                                         _stream()), "rte_sisa_iterate")
         return self.active
+
+
+@dataclass
+class PgmresResult:
+    status: int
+    n_sweep: np.ndarray
+    iterations: np.ndarray
+    inst_status: np.ndarray
+    residual: np.ndarray
+    cycles: int
+
+
+def pgmres_solve(p: Problem, rho_inout, tol=1e-10, restart=25, max_cycles=40, cg_rtol=1e-10,
+                 cg_maxit=5000, precondition=True, ws=None, raise_on_error=True):
+    """DSA-preconditioned restarted GMRES for every instance; rho_inout: initial guess / result."""
+    ws = ws if ws is not None else p.pgmres_workspace(restart)
+    B = p.B
+    n_sweep, iters, st = (np.zeros(B, np.int32) for _ in range(3))
+    res = np.zeros(B)
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    stats = KrylovStats(ip(n_sweep), ip(iters), ip(st), res.ctypes.data_as(_D), 0)
+    o = KrylovOpts(float(tol), int(restart), int(max_cycles), float(cg_rtol), int(cg_maxit),
+                   int(bool(precondition)))
+    rc = lib.rte_pgmres_solve(p.handle, ctypes.byref(o), _ptr(rho_inout), ctypes.byref(stats),
+                              _ptr(ws), ws.numel(), _stream())
+    if raise_on_error and rc not in (RTE_OK, RTE_ENOCONV):
+        raise RteError(rc, "rte_pgmres_solve")
+    return PgmresResult(rc, n_sweep, iters, st, res, stats.cycles)
