@@ -133,6 +133,42 @@ def f_form_leg(P, rte, reps=5):
             "cell_dir_updates_per_s": cd / (ms * 1e-3)}
 
 
+def residual_inf(P, rte, rho):
+    """Per-instance R = |rho - (L rho + b_bar)|_inf / |rho|_inf after convergence: one FP64 sweep
+    of the converged density (the residual the paper tabulates next to every method)."""
+    import torch
+    rs = torch.empty_like(rho)
+    rte.sweep(P, rho, rho_star_out=rs, precision="fp64")
+    d = (rs - rho).abs().amax(dim=1) / rho.abs().amax(dim=1)
+    return d.cpu().numpy()
+
+
+def pgmres_leg(args, plane, rte, problems, romsad_solves_per_s):
+    """The paper's Krylov baseline on the first instances of the batch: DSA-preconditioned
+    GMRES(25) to a preconditioned relative residual of eps, FP64 (same diffusion CG)."""
+    import torch
+    k = min(args.pgmres_instances, plane.B)
+    sub = plane.subset(range(k))
+    Pg = problems.plane_problem(sub)
+    ws = Pg.pgmres_workspace(25)
+    rho = torch.zeros((Pg.B, Pg.ndof), dtype=torch.float64, device="cuda")
+    rte.pgmres_solve(Pg, rho, tol=args.eps, restart=25, cg_rtol=args.cg_rtol, ws=ws)   # warm
+    rho.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = rte.pgmres_solve(Pg, rho, tol=args.eps, restart=25, cg_rtol=args.cg_rtol, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sps = Pg.B / dt
+    R = residual_inf(Pg, rte, rho)
+    return {"instances": Pg.B, "solves_per_s": sps, "mean_sweeps": float(r.n_sweep.mean()),
+            "residual_inf_median": float(np.median(R)), "residual_inf_max": float(R.max()),
+            "mean_iterations": float(r.iterations.mean()), "not_converged": int((r.inst_status != 0).sum()),
+            "romsad_batch_vs_pgmres": romsad_solves_per_s / sps, "precision": "fp64",
+            "note": "ratio of the headline batch's solves/s (mixed) to PGMRES solves/s (FP64) on "
+                    "the first instances of the same batch"}
+
+
 SERVE_KEYS = [(n, p) for n in (64, 128, 256) for p in (32, 64, 128)]
 
 
@@ -240,6 +276,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-train", type=int, default=4)
     ap.add_argument("--no-f-form", action="store_true")
+    ap.add_argument("--pgmres-instances", type=int, default=64,
+                    help="instances of the batch solved by DSA-preconditioned GMRES (0: skip)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="copy a buffer of this size before timing (HBM counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=600)
@@ -306,6 +344,7 @@ def main():
     red_ms, red_n = rte.profile_read("reduce")
     rte.profile_enable(False)
     bad = [int(r.status) for r in results if r.status != rte.RTE_OK]
+    R_batch = residual_inf(P, rte, rho)
     dsa_corrections = sum(int((r.kind == 1).sum()) for r in results)
     cg_per_correction = (sum(r.cg_iterations for r in results) / dsa_corrections
                          if dsa_corrections else None)
@@ -364,6 +403,8 @@ def main():
                    "theta": args.theta, "tuning": P.tuning()},
         "solves_per_s": solves / elapsed,
         "mean_sweeps_per_solve": float(sweeps.mean()),
+        "residual_inf_median": float(np.median(R_batch)),
+        "residual_inf_max": float(R_batch.max()),
         "dsa_corrections_per_solve": dsa_corrections / solves,
         "cg_iterations_per_dsa_correction": cg_per_correction,
         "status_not_ok_steps": bad,
@@ -377,6 +418,9 @@ def main():
                           "total": elapsed * 1e3},
     }
     out.update(base)
+    if args.pgmres_instances > 0:
+        out["pgmres"] = pgmres_leg(args, plane, rte, problems, solves / elapsed)
+        log(f"[bench] pgmres: {json.dumps(out['pgmres'])}")
     if not args.no_f_form:
         out["roofline_f_form"] = f_form_leg(P, rte)
         log(f"[bench] f-form sweep: {out['roofline_f_form']['achieved']:.0f} GB/s")
