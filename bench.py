@@ -109,7 +109,7 @@ def measured_traffic(launch_cd):
 def f_form_leg(P, rte, reps=5):
     """rte_sweep writing the FP32 angular flux of the whole batch: HBM roofline of the f-form."""
     import torch
-    f = torch.empty((P.B, P.ncell, P.n_dir, P.K), dtype=torch.float32, device="cuda")
+    f = torch.empty(rte.f_shape(P), dtype=torch.float32, device="cuda")
     rho = torch.rand((P.B, P.ndof), dtype=torch.float64, device="cuda")
     ws = P.workspace("si", None, "mixed")
     rte.sweep(P, rho, f_out=f, precision="mixed", ws=ws)

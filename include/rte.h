@@ -17,8 +17,22 @@
  *      local dof        k = a + 2 b                 (a: x-degree, b: y-degree); K = 4 in 2D,
  *                                                   K = 2 in 1D (k = a)
  *      rho, delta_rho   [B][N_DOF], N_DOF = nx * ny * K
- *      angular flux f   [B][ncell][n_dir][K]        (per cell and direction the K coefficients;
- *                                                   the paper's f_j is f[b][:, j, :])
+ *      angular flux f   2D: [B][n_dir][ncell][4] in sweep order: the cells of direction j
+ *                       are stored in the order its sweep visits them, so that the sweep
+ *                       writes them sequentially.  Reflect to the sweep's frame,
+ *                         x' = x (vx_j >= 0) or nx-1-x (vx_j < 0),  y' likewise with vy_j, ny;
+ *                       cut y' into bands of 64 rows, k = floor(y'/64), r = y' - 64k, band height
+ *                       h = min(64, ny - 64k); within a band order by anti-diagonal d = x' + r,
+ *                       then by r.  Cell (x, y) of direction j is stored at position
+ *                         64 nx k + T(d) + r - max(0, d - nx + 1),
+ *                       where, with m = min(nx, h), M = max(nx, h), T(d) counts the cells of the
+ *                       band's anti-diagonals before d:
+ *                         T(d) = d(d+1)/2                                     d <= m
+ *                              = m(m+1)/2 + (d-m) m                           m < d <= M
+ *                              = m(m+1)/2 + (M-m) m + e(m-1) - e(e-1)/2,      e = d - M > 0.
+ *                       rte_f_natural converts to [B][n_dir][N_DOF] in natural cell order
+ *                       (the paper's f_j is then row j).
+ *                       1D: [B][ncell][n_dir][2] (per cell and direction the 2 coefficients).
  *      materials        [B][ny][nx]  cell-constant sigma_t, sigma_s, G
  *      inflow           [B][4]  isotropic g on the sides x=0, x=Lx, y=0, y=Ly (1D: first two)
  *  - Basis: on a cell of size hx x hy, phi_ab = L_a(xi) L_b(eta) / sqrt(hx hy) with
@@ -93,7 +107,7 @@ int rte_problem_create(const rte_problem_desc *desc, rte_problem **out);
 void rte_problem_destroy(rte_problem *p);
 
 /* rte_problem_create with an explicit 2D sweep schedule (used by the autotuner): dg directions
- * of one quadrant per lane (1, 2, 4, 8, 16; 0 = automatic) and wpb wavefronts per workgroup
+ * of one quadrant per lane (1, 2, 4, 8; 0 = automatic) and wpb wavefronts per workgroup
  * (1..4; 0 = automatic).  Results do not depend on the schedule beyond FP rounding of the
  * partial-density order. */
 int rte_problem_create_tuned(const rte_problem_desc *desc, int dg, int wpb, rte_problem **out);
@@ -157,15 +171,18 @@ int rte_workspace_size(const rte_problem *p, rte_mode mode, const rte_rom *rom,
 /* One transport sweep, eq. (transport_sweep): for every instance and direction solve
  * (D_j + Sigma_t) f_j = Sigma_s rho_in + G + g_j^(bc) in upwind order.
  *   rho_in        device [B][N_DOF]
- *   f_out         device [B][ncell][n_dir][K], double (RTE_FP64) or float (RTE_MIXED); may be
- *                 NULL; 16-byte aligned (32 for double)
+ *   f_out         device angular flux in the layout above (2D sweep order, 1D cell-major),
+ *                 double (RTE_FP64) or float (RTE_MIXED); may be NULL; 16-byte aligned (32 for
+ *                 double).  2D with f_out: fewer than 2^26 cells per instance (RTE_EUNSUPPORTED
+ *                 beyond)
  *   rho_star_out  device [B][N_DOF], rho^* = sum_j w_j f_j; may be NULL
  *   zero_inflow   nonzero: use g = 0 (the kinetic correction equation's boundary condition) */
 int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
               int zero_inflow, rte_precision prec, void *ws, size_t ws_bytes, rte_stream_t stream);
 
 /* Quadrature reduction rho = sum_j w_j f_j (definition under eq. (dg_matrix_vec)).
- *   f     device [B][ncell][n_dir][K], double or float per prec;  rho_out device [B][N_DOF] */
+ *   f     device angular flux in the layout above, double or float per prec;
+ *   rho_out device [B][N_DOF] */
 int rte_scalar_flux(const rte_problem *p, const void *f, double *rho_out, rte_precision prec,
                     rte_stream_t stream);
 
@@ -215,7 +232,7 @@ typedef struct {
  *   mode RTE_SI: no correction; RTE_SI_DSA: DSA every iteration; RTE_ROMSAD: Alg. 2 switch.
  *   rho_inout  device [B][N_DOF]: initial guess in, rho^(l,*) of the stopping iteration out
  *   psi        device [B][m] (ROMSAD only)
- *   f_out      device [B][ncell][n_dir][K] angular flux of the last sweep, or NULL
+ *   f_out      device angular flux of the last sweep (layout above), or NULL
  * Returns RTE_ENOCONV if any instance hit max_iter (per-instance status in stats). */
 int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
                    const rte_solve_opts *opts, double *rho_inout, void *f_out,
@@ -292,11 +309,18 @@ int rte_sisa_iterate(const rte_problem *p, rte_mode mode, const rte_rom *rom, co
  * ------------------------------------------------------------------------------------------ */
 
 /* Snapshot columns delta f = f_final - f_iter per instance (Sec. 3.2.1); f_iter == NULL stands
- * for the zero initial state.  f_final, f_iter: device [B][ncell][n_dir][K] (the sweep's layout);
- * columns are written direction-major, entry j * N_DOF + dof;
+ * for the zero initial state.  f_final, f_iter: device FP64 angular fluxes in the sweep's layout
+ * (see the conventions above); columns are written direction-major in natural cell order, entry
+ * j * N_DOF + dof;
  * column b is written at cols + b * stride (stride >= n_dir * N_DOF). */
 int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double *f_iter,
                       double *cols, long long stride, rte_stream_t stream);
+
+/* The angular flux f (layout of the conventions above, double for RTE_FP64, float for
+ * RTE_MIXED) in natural order: out device [B][n_dir][N_DOF], same type, out[b][j] = f_j of
+ * instance b (the vector of eq. (dg_matrix_vec)).  out must not overlap f. */
+int rte_f_natural(const rte_problem *p, const void *f, void *out, rte_precision prec,
+                  rte_stream_t stream);
 
 /* G = X^T Y for column-major X [nx][len], Y [ny][len] (device), G [nx][ny] device, on the matrix
  * cores.  With cell_class != NULL only rows whose cell ((row / K) mod ncell) has class cls are

@@ -1,7 +1,7 @@
 // Offline construction of the correction ROM on the device (Sec. 3.1 POD, Sec. 3.2.1 snapshot
 // generation, Sec. 3.1.1 reduced affine operators).
 //
-//   snapshot columns   delta f = f^mu - f^(mu,l)                         (pod_snapshot_kernel)
+//   snapshot columns   delta f = f^mu - f^(mu,l)                         (f_gather_kernel)
 //   Gram matrix        G = X^T Y over long columns, optionally restricted to one material class
 //                      (v_mfma_f64_16x16x4f64, split over the rows, fixed-order split sum)
 //   eigenpairs of G    cyclic Jacobi, one workgroup (the method of snapshots: F = U S V^T with
@@ -23,18 +23,30 @@ constexpr double kS3 = 1.7320508075688772935;
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
-// column entry t = j * ndof + dof (direction-major) from the angular flux [B][cell][n_dir][K]
-__global__ void pod_snapshot_kernel(long long ndof, int K, int n_dir, int B, const double *f_final,
-                                    const double *f_l, double *cols, long long stride) {
+// Direction-major, natural-order copy of an angular flux in the sweep's layout (2D:
+// [B][n_dir][cell][K] with each direction's cells in band order of its reflected coordinates; 1D:
+// [B][cell][n_dir][K]), optionally minus a second one: out[b * stride + (j * ncell + cell) * K + k].
+// In 2D a thread owns one stored position, so the reads of a wavefront are contiguous.
+template <typename T>
+__global__ void f_gather_kernel(int dim, int nx, int ny, long long ncell, int K, int n_dir,
+                                const double *vxy, const T *fa, const T *fb, T *out,
+                                long long stride) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
-    const long long len = ndof * n_dir;
-    if (t >= len) return;
-    const long long j = t / ndof, dof = t - j * ndof;
-    const long long c = dof / K, k = dof - c * K;
-    const size_t src = (((size_t)b * (ndof / K) + c) * n_dir + j) * K + k;
-    const double a = f_final[src];
-    cols[(size_t)b * stride + t] = f_l ? a - f_l[src] : a;
+    if (t >= (long long)n_dir * ncell) return;
+    const long long j = t / ncell, e = t - j * ncell;
+    long long cell;
+    size_t src;
+    if (dim == 2) {
+        const int q = (vxy[j] < 0.0 ? 1 : 0) | (vxy[n_dir + j] < 0.0 ? 2 : 0);
+        cell = unreflect(nx, ny, band_cell(nx, ny, (int)e), q);
+        src = (((size_t)b * n_dir + j) * ncell + e) * K;
+    } else {
+        cell = e;
+        src = (((size_t)b * ncell + e) * n_dir + j) * K;
+    }
+    T *o = out + (size_t)b * stride + ((size_t)j * ncell + cell) * K;
+    for (int k = 0; k < K; ++k) o[k] = fb ? fa[src + k] - fb[src + k] : fa[src + k];
 }
 
 // G_part[split][i][j] = sum over rows in the split of X[i][row] Y[j][row] (row in class cls)
@@ -308,9 +320,27 @@ int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double 
     if (!p || !f_final || !cols) return RTE_EINVAL;
     const long long len = (long long)p->n_dir * p->ndof;
     if (stride < len) return RTE_EINVAL;
-    hipLaunchKernelGGL(pod_snapshot_kernel, dim3(cdiv(len, 256), p->B), dim3(256), 0,
-                       (hipStream_t)stream, p->ndof, p->K, p->n_dir, p->B, f_final, f_iter, cols,
-                       stride);
+    hipLaunchKernelGGL(f_gather_kernel<double>, dim3(cdiv((long long)p->n_dir * p->ncell, 256), p->B),
+                       dim3(256), 0, (hipStream_t)stream, p->dim, p->nx, p->ny, p->ncell, p->K,
+                       p->n_dir, p->d_vxy, f_final, f_iter, cols, stride);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_f_natural(const rte_problem *p, const void *f, void *out, rte_precision prec,
+                  rte_stream_t stream) {
+    if (!p || !f || !out) return RTE_EINVAL;
+    if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
+    const dim3 grid(cdiv((long long)p->n_dir * p->ncell, 256), p->B);
+    const long long stride = (long long)p->n_dir * p->ndof;
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == RTE_MIXED)
+        hipLaunchKernelGGL(f_gather_kernel<float>, grid, dim3(256), 0, s, p->dim, p->nx, p->ny,
+                           p->ncell, p->K, p->n_dir, p->d_vxy, (const float *)f, (const float *)nullptr,
+                           (float *)out, stride);
+    else
+        hipLaunchKernelGGL(f_gather_kernel<double>, grid, dim3(256), 0, s, p->dim, p->nx, p->ny,
+                           p->ncell, p->K, p->n_dir, p->d_vxy, (const double *)f,
+                           (const double *)nullptr, (double *)out, stride);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 

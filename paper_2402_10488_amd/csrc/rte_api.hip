@@ -48,7 +48,6 @@ struct Layout {
     int *flag;
     int *mask;              // [B] instances selected by rte_sisa_admit
     GmresSpace gm;          // DSA-preconditioned GMRES (rte_pgmres_solve)
-    double *sink;           // [8] target of the sweep's stores from idle lanes
 };
 
 int nparts_for(const rte_problem *p) { return sweep_nparts(p); }
@@ -65,7 +64,6 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     L.src = c.take<char>(p->dim == 2 ? B * (size_t)p->ncell * 10 * ts : B * nd * ts);
     if (p->dim == 2) L.partial = c.take<double>(B * (size_t)nparts_for(p) * nd);
     else L.fscratch = c.take<char>(B * (size_t)p->n_dir * nd * ts);
-    L.sink = c.take<double>(8);
     L.st.maxd = c.take<unsigned long long>(B);
     L.st.maxr = c.take<unsigned long long>(B);
     L.st.active = c.take<int>(B);
@@ -287,7 +285,7 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
     if (d->dim == 2 && !d->dir_y) return RTE_EINVAL;
     if (d->dim == 1 && !d->widths) return RTE_EINVAL;
     if (!d->sigma_t || !d->sigma_s || !d->source || !d->inflow) return RTE_EINVAL;
-    if (dg != 0 && dg != 1 && dg != 2 && dg != 4 && dg != 8 && dg != 16) return RTE_EINVAL;
+    if (dg != 0 && dg != 1 && dg != 2 && dg != 4 && dg != 8) return RTE_EINVAL;
     if (wpb < 0 || wpb > 4) return RTE_EINVAL;
     if ((long long)d->nx * d->ny > (1ll << 31)) return RTE_EUNSUPPORTED;
     double wsum = 0.0;
@@ -541,12 +539,13 @@ int do_sweep(const rte_problem *p, const Layout &L, const void *src, void *f_out
              double *rho_star, const double *rho_prev, const int *active, int zero_inflow,
              int fp32, hipStream_t s) {
     if (p->dim == 2) {
+        // the f stores address one direction's array with 32-bit byte offsets
+        if (f_out && p->ncell >= (1LL << 26)) return RTE_EUNSUPPORTED;
         SweepLaunch a;
         a.p = p;
         a.src = src;
         a.partial = rho_star ? L.partial : nullptr;
         a.f_out = f_out;
-        a.sink = L.sink;
         a.active = active;
         a.zero_inflow = zero_inflow;
         a.fp32 = fp32;

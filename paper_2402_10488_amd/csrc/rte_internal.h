@@ -73,23 +73,70 @@ namespace rte {
 // min(d + 1, m, nx + ny - 1 - d) cells (m = min(nx, ny), M = max(nx, ny)); the same count for
 // anti-diagonals (x + y = d) and diagonals (x - y + ny - 1 = d).  Arithmetic only, so a sweep
 // step never waits on a memory load for its position.
-__device__ __forceinline__ int diag_off(int nx, int ny, int d) {
+__host__ __device__ __forceinline__ int diag_off(int nx, int ny, int d) {
     const int m = nx < ny ? nx : ny, M = nx < ny ? ny : nx;
     if (d <= m) return d * (d + 1) / 2;
     if (d <= M) return m * (m + 1) / 2 + (d - m) * m;
     const int e = d - M;
     return m * (m + 1) / 2 + (M - m) * m + e * (m - 1) - e * (e - 1) / 2;
 }
-__device__ __forceinline__ int pos_a(int nx, int ny, int x, int y) {
+__host__ __device__ __forceinline__ int pos_a(int nx, int ny, int x, int y) {
     const int d = x + y;
     const int ylo = d - nx + 1 > 0 ? d - nx + 1 : 0;
     return diag_off(nx, ny, d) + y - ylo;
 }
-__device__ __forceinline__ int pos_b(int nx, int ny, int x, int y) {
+__host__ __device__ __forceinline__ int pos_b(int nx, int ny, int x, int y) {
     const int d = x - y + ny - 1;
     const int ylo = ny - 1 - d > 0 ? ny - 1 - d : 0;
     return diag_off(nx, ny, d) + y - ylo;
 }
+// The (anti)diagonal holding position pos: the largest d with diag_off(d) <= pos (bisection).
+__host__ __device__ __forceinline__ int diag_at(int nx, int ny, int pos) {
+    int lo = 0, hi = nx + ny - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (diag_off(nx, ny, mid) <= pos) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+// Inverse of pos_a / pos_b: the natural cell index y * nx + x at position pos.
+__host__ __device__ __forceinline__ int cell_at(int nx, int ny, int pos, bool layout_a) {
+    const int d = diag_at(nx, ny, pos);
+    const int k = pos - diag_off(nx, ny, d);
+    if (layout_a) {
+        const int ylo = d - nx + 1 > 0 ? d - nx + 1 : 0;
+        const int y = ylo + k;
+        return y * nx + (d - y);
+    }
+    const int ylo = ny - 1 - d > 0 ? ny - 1 - d : 0;
+    const int y = ylo + k;
+    return y * nx + (d + y - ny + 1);
+}
+// Storage order of the 2D angular flux, in a direction's reflected coordinates (x', y') (the
+// frame in which its sweep runs +x, +y): the 64-row bands of the sweep one after the other, each
+// band (nx x h cells, h = min(64, ny - 64 k)) in its own anti-diagonal order (pos_a of that
+// band).  A wavefront of the sweep writes one band diagonal per step, right after the one of its
+// previous step, so its writes run through memory sequentially.
+__host__ __device__ __forceinline__ int band_pos(int nx, int ny, int x, int y) {
+    const int k = y >> 6, r = y & 63;
+    const int h = ny - 64 * k < 64 ? ny - 64 * k : 64;
+    return 64 * nx * k + pos_a(nx, h, x, r);
+}
+// Inverse of band_pos: y' * nx + x' of the cell at position pos.
+__host__ __device__ __forceinline__ int band_cell(int nx, int ny, int pos) {
+    const int k = pos / (64 * nx);
+    const int h = ny - 64 * k < 64 ? ny - 64 * k : 64;
+    const int c = cell_at(nx, h, pos - 64 * nx * k, true);
+    return (64 * k + c / nx) * nx + c % nx;
+}
+// Natural cell index of the reflected cell index c' = y' * nx + x' of quadrant q.
+__host__ __device__ __forceinline__ int unreflect(int nx, int ny, int c, int q) {
+    const int yr = c / nx, xr = c - yr * nx;
+    const int x = (q & 1) ? nx - 1 - xr : xr, y = (q & 2) ? ny - 1 - yr : yr;
+    return y * nx + x;
+}
+
 // quadrant q = (vx<0) | 2 (vy<0): q = 0, 3 sweep anti-diagonals (layout A), q = 1, 2 diagonals (B)
 __device__ __forceinline__ bool quad_uses_a(int q) { return q == 0 || q == 3; }
 
@@ -148,7 +195,6 @@ struct SweepLaunch {
     const void *src;          // sweep input block (see above)
     double *partial;          // [B][nparts][ndof] or nullptr
     void *f_out;              // [B][ncell][n_dir][K] T or nullptr
-    void *sink;               // 64 bytes of workspace: target of the stores of idle lanes
     const int *active;        // [B] or nullptr
     int zero_inflow;
     int fp32;

@@ -37,11 +37,7 @@ struct Sweep2DArgs {
     const double *inflow;
     double *partial;
     void *f_out;
-    void *sink;              // stores of lanes without a value to write go here
-    int stage;               // f-form: write the angular flux through an LDS stage (see kernel)
-    int stage_off;           // byte offset of the stage values in LDS
-    int stage_idx_off;       // byte offset of its cell / direction index arrays
-    int lg_nd;               // log2(W * DG)
+    int ring_off;            // LDS offset (in doubles) of the y-trace rings
     const int *active;
 };
 
@@ -150,6 +146,32 @@ __device__ __forceinline__ double recip(double x) {
     return r * (2.0 - x * r);
 }
 
+// Word 3 of a raw buffer resource on gfx9-family devices (32-bit data format; untyped loads and
+// stores ignore the format beyond that), and a byte offset that is out of every range below 2 GiB.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kDropOffset = (int)0x80000000u;
+constexpr int kStoreAux = 2;
+
+// The 4 coefficients of one cell-direction through a raw buffer store (dropped by the hardware
+// when the offset is outside the resource's range).
+__device__ __forceinline__ void store_f4(__amdgpu_buffer_rsrc_t r, int off, const float (&v)[4]) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    v4i x;
+    x.x = __float_as_int(v[0]); x.y = __float_as_int(v[1]);
+    x.z = __float_as_int(v[2]); x.w = __float_as_int(v[3]);
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, kStoreAux);
+}
+__device__ __forceinline__ void store_f4(__amdgpu_buffer_rsrc_t r, int off, const double (&v)[4]) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    v4i x, y;
+    const long long a0 = __double_as_longlong(v[0]), a1 = __double_as_longlong(v[1]);
+    const long long a2 = __double_as_longlong(v[2]), a3 = __double_as_longlong(v[3]);
+    x.x = (int)a0; x.y = (int)(a0 >> 32); x.z = (int)a1; x.w = (int)(a1 >> 32);
+    y.x = (int)a2; y.y = (int)(a2 >> 32); y.z = (int)a3; y.w = (int)(a3 >> 32);
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b128(y, r, off + 16, 0, kStoreAux);
+}
+
 // One workgroup = W wavefronts = W consecutive direction groups of one (instance, quadrant).
 // The wavefronts walk the same pipeline in lockstep (one barrier per step), so at every step
 // lane j of every wavefront is at the same cell; their FP64 partial densities are summed in
@@ -174,7 +196,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
     // LDS: [2][W][64][4] doubles of partial densities (double buffered by step parity), then
     // the W rings of y-traces handed from lane 63 to lane 0 of the next band
     double *red = smem_d;
-    T *ring = reinterpret_cast<T *>(smem_d + 2 * W * 64 * 4) + (size_t)wv * a.nx * DG * 2;
+    T *ring = reinterpret_cast<T *>(smem_d + a.ring_off) + (size_t)wv * a.nx * DG * 2;
 
     DirConst<T> dc[DG];
     T wt[DG];
@@ -201,24 +223,23 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
     const T *src = base + (la ? 0 : nb4) + (size_t)b * a.ncell * 4;
     const T *sig_t = base + 2 * nb4 + (la ? 0 : (size_t)a.B * a.ncell) + (size_t)b * a.ncell;
     double *part_out = a.partial ? a.partial + ((size_t)b * a.nparts + gpart) * a.ncell * 4 : nullptr;
-    // angular flux [B][cell][n_dir][4]: a cell's block holds each direction's 4 coefficients;
-    // the directions of one quadrant are contiguous in the original numbering, so at every step
-    // the workgroup writes whole cache lines of each of its cells
-    T *fout = WF ? reinterpret_cast<T *>(a.f_out) + (size_t)b * a.n_dir * a.ncell * 4 : nullptr;
-    // With a.stage the waves put a step's values in LDS ([64 cells][W*DG directions]) and then
-    // write them back with consecutive lanes on consecutive directions of one cell, so a store
-    // instruction covers whole lines (a few requests) instead of 64 scattered 16-byte pieces.
-    const bool stage_f = WF && a.stage != 0;
-    const int nd_wg = W * DG;
-    Vec4<T> *stage = nullptr;
-    int *st_cell = nullptr, *st_orig = nullptr;
-    if (stage_f) {
-        char *lb = reinterpret_cast<char *>(smem_d);
-        stage = reinterpret_cast<Vec4<T> *>(lb + a.stage_off);
-        st_cell = reinterpret_cast<int *>(lb + a.stage_idx_off);
-        st_orig = st_cell + 64;
-        const int pos = a.qstart[q] + part * nd_wg + (int)threadIdx.x;
-        if ((int)threadIdx.x < nd_wg) st_orig[threadIdx.x] = pos < dend ? a.dirs[pos].orig : -1;
+    // angular flux [B][n_dir][cell][4], each direction's cells in band order (band_pos of the
+    // reflected coordinates): at every step the lanes of a band are on consecutive positions
+    // right after those of the previous step, so each store instruction writes one contiguous
+    // run of 64 x 4 values and a wavefront's stores run through memory sequentially.  The
+    // stores are raw buffer stores through one resource per direction whose range is that
+    // direction's array: a lane without a value (outside the mesh, or a padding direction with
+    // an empty range) gives an offset beyond the range and the hardware drops its store.  Every
+    // lane issues every store, so the number of stores in flight is known at each step.
+    __amdgpu_buffer_rsrc_t frs[WF ? DG : 1];
+    if constexpr (WF) {
+        T *fb = reinterpret_cast<T *>(a.f_out) + (size_t)b * a.n_dir * a.ncell * 4;
+        const int bytes = (int)(a.ncell * 4 * (long long)sizeof(T));
+#pragma unroll
+        for (int d = 0; d < DG; ++d)
+            frs[d] = __builtin_amdgcn_make_buffer_rsrc(
+                fb + (size_t)(orig[d] >= 0 ? orig[d] : 0) * a.ncell * 4, 0,
+                orig[d] >= 0 ? bytes : 0, kBufferWord3);
     }
     T tx0[DG], tx1[DG], ty0[DG], ty1[DG];
 #pragma unroll
@@ -227,18 +248,17 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
     // lane position in the pipeline: band k, column i (k P + i = t - lane), tracked
     // incrementally so the loop carries no division
     const int P = a.P, nx = a.nx, ny = a.ny, nb = a.nbands;
-    // natural cell index (for f) and position in the diagonal layout (inputs, partials)
-    auto cell_of = [&](int kk, int ii, bool &ok, int &pos) -> int {
+    // position of the lane's cell in this quadrant's diagonal layout (inputs, partials)
+    auto locate = [&](int kk, int ii, bool &ok) -> int {
         const int jr = kk * 64 + lane;
         ok = ii >= 0 && kk < nb && ii < nx && jr < ny;
         const int ip = rx ? nx - 1 - ii : ii;
         const int jp = ry ? ny - 1 - jr : jr;
-        pos = ok ? (la ? pos_a(nx, ny, ip, jp) : pos_b(nx, ny, ip, jp)) : 0;
-        return ok ? jp * nx + ip : 0;
+        return ok ? (la ? pos_a(nx, ny, ip, jp) : pos_b(nx, ny, ip, jp)) : 0;
     };
     // cell data of one pipeline step: position (band k, column i) and the prefetched inputs
     struct CellIn {
-        int k, i, cell, pos;
+        int k, i, pos;
         bool ok;
         Vec4<T> sv;
         T sg;
@@ -247,7 +267,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
     // under a branch leaves the compiler unsure whether it was issued, and it then waits for it
     // at once instead of at the step that uses it.
     auto load_cell = [&](CellIn &c) {
-        c.cell = cell_of(c.k, c.i, c.ok, c.pos);
+        c.pos = locate(c.k, c.i, c.ok);
         c.sv = *reinterpret_cast<const Vec4<T> *>(src + (size_t)c.pos * 4);
         c.sg = sig_t[c.pos];
     };
@@ -267,11 +287,15 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
         nxt.i = cur.i + 1;
         if (nxt.i == P) { nxt.i = 0; ++nxt.k; }
         load_cell(nxt);
-        // the lane's DG directions are summed in T, the groups and quadrants in FP64
+        // the lane's DG directions are summed in T, the groups and quadrants in FP64.
+        // With f, every lane runs the arithmetic, also a lane outside the mesh: its values never
+        // reach a lane inside it (at the next step lane j + 1 sits at lane j's column, so both
+        // are outside together, and a lane entering a row resets its traces), its partial sums
+        // are ignored and its f stores are dropped.  With no branch around them the stores are
+        // issued as soon as a direction's values exist, and the compiler counts them exactly.
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        T fo[WF ? DG : 1][4];
-        if (cur.ok) {
-            if (lane == 0) {
+        if (WF || cur.ok) {
+            if (cur.ok && lane == 0) {
 #pragma unroll
                 for (int d = 0; d < DG; ++d) {
                     if (cur.k == 0) { yi0[d] = gy; yi1[d] = T(0); }
@@ -282,6 +306,9 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
 #pragma unroll
                 for (int d = 0; d < DG; ++d) { tx0[d] = gx; tx1[d] = T(0); }
             }
+            const int off = (WF && cur.ok)
+                                ? band_pos(nx, ny, cur.i, cur.k * 64 + lane) * (int)(4 * sizeof(T))
+                                : kDropOffset;
             const T s0 = cur.sv.x, s1 = sx * cur.sv.y, s2 = sy * cur.sv.z, s3 = sx * sy * cur.sv.w;
             const T sig = cur.sg;
             T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
@@ -302,10 +329,11 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
                 a2 += wt[d] * f2;
                 a3 += wt[d] * f3;
                 if constexpr (WF) {
-                    fo[d][0] = f0; fo[d][1] = sx * f1; fo[d][2] = sy * f2; fo[d][3] = sx * sy * f3;
+                    const T fo[4] = {f0, sx * f1, sy * f2, sx * sy * f3};
+                    store_f4(frs[d], off, fo);
                 }
             }
-            if (lane == 63) {
+            if (cur.ok && lane == 63) {
 #pragma unroll
                 for (int d = 0; d < DG; ++d) {
                     ring[(cur.i * DG + d) * 2] = ty0[d];
@@ -317,55 +345,18 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
             acc2 = (double)a2;
             acc3 = (double)a3;
         }
-        // Every lane issues its DG stores, idle lanes and padding directions into the sink: stores
-        // under a branch would leave the compiler unsure how many are in flight, and it would
-        // then wait for all of them before the next step's prefetched data is used.
-        if constexpr (WF) {
-            if (stage_f) {
-#pragma unroll
-                for (int d = 0; d < DG; ++d) {
-                    Vec4<T> o;
-                    o.x = fo[d][0]; o.y = fo[d][1]; o.z = fo[d][2]; o.w = fo[d][3];
-                    stage[lane * nd_wg + wv * DG + d] = o;
-                }
-                if (wv == 0) st_cell[lane] = cur.ok ? cur.cell : -1;
-            } else {
-                T *fc = fout + (size_t)cur.cell * a.n_dir * 4;
-#pragma unroll
-                for (int d = 0; d < DG; ++d) {
-                    T *dst = (cur.ok && orig[d] >= 0) ? fc + (size_t)orig[d] * 4
-                                                      : reinterpret_cast<T *>(a.sink);
-                    Vec4<T> o;
-                    o.x = fo[d][0]; o.y = fo[d][1]; o.z = fo[d][2]; o.w = fo[d][3];
-                    *reinterpret_cast<Vec4<T> *>(dst) = o;
-                }
-            }
-        }
-        if (part_out || stage_f) {
-            // (1) partial densities of this cell from every wavefront into LDS, (2) one barrier,
-            // (3) the staged angular flux back to memory, (4) the fixed-order sum of the W
-            // partials by wavefront 0, (5) a second barrier before the stage is reused
+        if (part_out) {
+            // partial densities of this cell from every wavefront into LDS (double buffered by
+            // step parity, so one barrier per step suffices), then their fixed-order sum by
+            // wavefront 0
             double *slot = red + (size_t)(t & 1) * W * 64 * 4;
-            if (part_out) {
+            {
                 double4 v;
                 v.x = acc0; v.y = acc1; v.z = acc2; v.w = acc3;
                 *reinterpret_cast<double4 *>(slot + ((size_t)wv * 64 + lane) * 4) = v;
             }
             __syncthreads();
-            if constexpr (WF) {
-                if (stage_f) {
-                    const int mask = nd_wg - 1;
-#pragma unroll
-                    for (int r = 0; r < DG; ++r) {
-                        const int e = (r * W + wv) * 64 + lane;
-                        const int ci = st_cell[e >> a.lg_nd], og = st_orig[e & mask];
-                        T *dst = (ci >= 0 && og >= 0) ? fout + ((size_t)ci * a.n_dir + og) * 4
-                                                      : reinterpret_cast<T *>(a.sink);
-                        *reinterpret_cast<Vec4<T> *>(dst) = stage[e];
-                    }
-                }
-            }
-            if (part_out && wv == 0 && cur.ok) {
+            if (wv == 0 && cur.ok) {
                 double4 sum = *reinterpret_cast<const double4 *>(slot + (size_t)lane * 4);
                 for (int w2 = 1; w2 < W; ++w2) {
                     const double4 o = *reinterpret_cast<const double4 *>(slot + ((size_t)w2 * 64 + lane) * 4);
@@ -374,8 +365,14 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
                 sum.y *= dsx; sum.z *= dsy; sum.w *= dsx * dsy;
                 *reinterpret_cast<double4 *>(part_out + (size_t)cur.pos * 4) = sum;
             }
-            if (stage_f) __syncthreads();      // the stage is rewritten at the next step
         }
+        // The ring passes values between lanes of one wavefront (written by lane 63, read by
+        // lane 0 at a later step, the very next one when the pipeline stride P is 64).  Within
+        // one lane's program the write and the read never both run, so the compiler could move a
+        // step's read above the previous step's write.  The barrier of the partial sums keeps
+        // them in order; without partial sums this compiler-only barrier does (no instruction:
+        // the LDS executes one wavefront's accesses in program order).
+        if constexpr (WF) asm volatile("" ::: "memory");
     };
     CellIn A, B;
     A.k = 0;
@@ -498,6 +495,37 @@ __global__ void reduce_parts_kernel(ReduceArgs a, const double *partial, double 
     if (maxr) max_update(maxr + b, m);
 }
 
+// 2D quadrature reduction of an angular flux in the sweep's layout [B][n_dir][cell][4] for the
+// directions of one quadrant q.  A thread owns one stored position (band order of q's reflected
+// coordinates), so for every direction a wavefront reads one contiguous run; the sums go to the
+// natural cell (written by the pass of quadrant 0, added by the others).
+template <typename T>
+__global__ void scalar_flux2d_kernel(int nx, int ny, long long ncell, int n_dir, const double *vxy,
+                                     const double *w, const T *f, double *rho, int q) {
+    const long long pos = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = (int)blockIdx.y;
+    if (pos >= ncell) return;
+    const long long cell = unreflect(nx, ny, band_cell(nx, ny, (int)pos), q);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int j = 0; j < n_dir; ++j) {
+        const int qj = (vxy[j] < 0.0 ? 1 : 0) | (vxy[n_dir + j] < 0.0 ? 2 : 0);
+        if (qj != q) continue;
+        const Vec4<T> v = *reinterpret_cast<const Vec4<T> *>(f + (((size_t)b * n_dir + j) * ncell + pos) * 4);
+        const double wj = w[j];
+        s0 += wj * (double)v.x; s1 += wj * (double)v.y; s2 += wj * (double)v.z; s3 += wj * (double)v.w;
+    }
+    double4 *o = reinterpret_cast<double4 *>(rho + ((size_t)b * ncell + cell) * 4);
+    double4 r;
+    if (q == 0) { r.x = s0; r.y = s1; r.z = s2; r.w = s3; }
+    else {
+        r = *o;
+        r.x += s0; r.y += s1; r.z += s2; r.w += s3;
+    }
+    *o = r;
+}
+
+// 1D quadrature reduction (the slab sweep's f layout [B][cell][n_dir][K]), with the per-instance
+// maxima of |rho| and of the change against rho_prev
 template <typename T>
 __global__ void scalar_flux_kernel(long long ndof, int K, int B, int n_dir, const double *w, const T *f,
                                    double *rho, const double *rho_prev, unsigned long long *maxd,
@@ -555,44 +583,12 @@ hipError_t sweep2d_launch_t(const SweepLaunch &L, hipStream_t s) {
     a.inflow = p->inflow;
     a.partial = L.partial;
     a.f_out = L.f_out;
-    a.sink = L.sink;
     a.active = L.active;
     const unsigned grid = (unsigned)((long long)a.B * a.nparts);
-    const size_t red = (size_t)2 * W * 64 * 4 * sizeof(double);
-    size_t lds = red + (size_t)W * p->nx * DG * 2 * sizeof(T);
-    a.stage = 0;
-    a.stage_off = 0;
-    a.stage_idx_off = 0;
-    a.lg_nd = 0;
-    const int nd = W * DG;
-    if (L.f_out && DG <= 2 && (nd & (nd - 1)) == 0) {
-        // the f stage: [64][W*DG] values, 64 cell indices, W*DG direction indices; it overlays
-        // the partial-sum buffers when no partial densities are formed.  Used with one or two
-        // directions per lane (where a lane's direct stores are 16 or 32 scattered bytes; with
-        // more the direct stores measured faster) and only when the workgroups still fit on the
-        // device in one round (LDS per workgroup within the CU's share).
-        const size_t st = (size_t)64 * nd * sizeof(Vec4<T>);
-        const size_t idx = 64 * sizeof(int) + (size_t)nd * sizeof(int);
-        size_t off, ioff, total;
-        if (!L.partial && st <= red) {
-            off = 0;
-            ioff = (lds + 15) & ~(size_t)15;
-        } else {
-            off = (lds + 15) & ~(size_t)15;
-            ioff = off + st;
-        }
-        total = ioff + idx;
-        const long long per_cu = ((long long)grid + p->n_cu - 1) / p->n_cu;
-        if (per_cu >= 1 && (long long)total * per_cu <= p->lds_per_cu) {
-            a.stage = 1;
-            a.stage_off = (int)off;
-            a.stage_idx_off = (int)ioff;
-            int lg = 0;
-            while ((1 << lg) < nd) ++lg;
-            a.lg_nd = lg;
-            lds = total;
-        }
-    }
+    // partial-sum buffers only when partial densities are formed, then the y-trace rings
+    const size_t red = L.partial ? (size_t)2 * W * 64 * 4 * sizeof(double) : 0;
+    const size_t lds = red + (size_t)W * p->nx * DG * 2 * sizeof(T);
+    a.ring_off = (int)(red / sizeof(double));
     if (L.f_out)
         hipLaunchKernelGGL((sweep2d_kernel<T, DG, true>), dim3(grid), dim3(64 * W), lds, s, a);
     else
@@ -607,7 +603,6 @@ hipError_t sweep2d_dispatch(const SweepLaunch &L, hipStream_t s) {
         case 2: return sweep2d_launch_t<T, 2>(L, s);
         case 4: return sweep2d_launch_t<T, 4>(L, s);
         case 8: return sweep2d_launch_t<T, 8>(L, s);
-        case 16: return sweep2d_launch_t<T, 16>(L, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -671,6 +666,21 @@ hipError_t launch_reduce_parts(const rte_problem *p, const double *partial, int 
 hipError_t launch_scalar_flux(const rte_problem *p, const void *f, double *rho, int fp32,
                               const double *rho_prev, unsigned long long *maxd,
                               unsigned long long *maxr, const int *active, hipStream_t s) {
+    if (p->dim == 2) {
+        // the quadrant-0 pass writes every cell (a quadrant without directions contributes
+        // zero), the others add; no change maxima in 2D (the sweep forms rho* itself)
+        if (rho_prev || maxd || maxr || active) return hipErrorInvalidValue;
+        dim3 g2(blocks_for(p->ncell, 256), p->B);
+        for (int q = 0; q < 4; ++q) {
+            if (fp32)
+                hipLaunchKernelGGL(scalar_flux2d_kernel<float>, g2, dim3(256), 0, s, p->nx, p->ny,
+                                   p->ncell, p->n_dir, p->d_vxy, p->d_w, (const float *)f, rho, q);
+            else
+                hipLaunchKernelGGL(scalar_flux2d_kernel<double>, g2, dim3(256), 0, s, p->nx, p->ny,
+                                   p->ncell, p->n_dir, p->d_vxy, p->d_w, (const double *)f, rho, q);
+        }
+        return hipGetLastError();
+    }
     dim3 grid(blocks_for(p->ndof, 256), p->B);
     if (fp32)
         hipLaunchKernelGGL(scalar_flux_kernel<float>, grid, dim3(256), 0, s, p->ndof, p->K, p->B, p->n_dir,

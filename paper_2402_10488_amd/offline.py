@@ -116,7 +116,7 @@ def training_solves(P, window, eps_train, cg_rtol=1e-12, max_iter=500):
     import torch
     from . import rte
     ws = P.workspace("si_dsa", None, "fp64", max_iter)
-    shape = (P.B, P.ncell, P.n_dir, P.K)    # the sweep's layout
+    shape = rte.f_shape(P)                   # the sweep's layout
     f_final = torch.empty(shape, dtype=torch.float64, device="cuda")
     rho = torch.zeros((P.B, P.ndof), dtype=torch.float64, device="cuda")
     res = rte.sisa_solve(P, rho, mode="si_dsa", eps=eps_train, max_iter=max_iter, cg_rtol=cg_rtol,

@@ -73,11 +73,24 @@ class KrylovStats(ctypes.Structure):
                 ("cycles", ctypes.c_int)]
 
 
+EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destroy",
+            "rte_problem_tuning", "rte_problem_check", "rte_rom_create", "rte_rom_destroy",
+            "rte_workspace_size", "rte_sweep", "rte_scalar_flux", "rte_dsa_correct",
+            "rte_rom_correct", "rte_sisa_solve", "rte_strerror", "rte_profile_enable",
+            "rte_profile_read", "rte_problem_dsa_multigrid", "rte_pod_snapshots", "rte_gram",
+            "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum",
+            "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
+            "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve", "rte_f_natural"]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2402_10488_amd/build.py "
                           "(there is no CPU fallback)")
     L = ctypes.CDLL(LIB_PATH)
+    missing = [n for n in EXPORTED if not hasattr(L, n)]
+    if missing:
+        raise ImportError(f"{LIB_PATH} lacks {missing}: it was built from older sources, rebuild it")
     P = ctypes.c_void_p
     L.rte_strerror.restype = ctypes.c_char_p
     L.rte_strerror.argtypes = [ctypes.c_int]
@@ -95,6 +108,7 @@ def _load():
                                      ctypes.POINTER(ctypes.c_size_t)]
     L.rte_sweep.argtypes = [P, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
     L.rte_scalar_flux.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
+    L.rte_f_natural.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
     L.rte_dsa_correct.argtypes = [P, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
                                   ctypes.c_size_t, _vp]
     L.rte_rom_correct.argtypes = [P, P, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t,
@@ -121,14 +135,6 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destroy",
-            "rte_problem_tuning", "rte_problem_check", "rte_rom_create", "rte_rom_destroy",
-            "rte_workspace_size", "rte_sweep", "rte_scalar_flux", "rte_dsa_correct",
-            "rte_rom_correct", "rte_sisa_solve", "rte_strerror", "rte_profile_enable",
-            "rte_profile_read", "rte_problem_dsa_multigrid", "rte_pod_snapshots", "rte_gram",
-            "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum",
-            "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
-            "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve"]
 
 PROF = {"sweep2d": 0, "reduce": 1, "dsa": 2, "rom": 3, "sweep1d": 4}
 
@@ -288,6 +294,22 @@ def sweep(p: Problem, rho_in, f_out=None, rho_star_out=None, zero_inflow=False, 
     ws = ws if ws is not None else p.workspace("si", None, precision)
     _check(lib.rte_sweep(p.handle, _ptr(rho_in), _ptr(f_out), _ptr(rho_star_out), int(zero_inflow),
                          PRECISIONS[precision], _ptr(ws), ws.numel(), _stream()), "rte_sweep")
+
+
+def f_shape(p: Problem):
+    """Shape of the angular flux the library writes and reads: 2D (B, n_dir, ncell, 4), each
+    direction's cells in its quadrant's diagonal order; 1D (B, ncell, n_dir, 2)."""
+    return (p.B, p.n_dir, p.ncell, p.K) if p.dim == 2 else (p.B, p.ncell, p.n_dir, p.K)
+
+
+def f_natural(p: Problem, f, precision="fp64"):
+    """The angular flux as (B, n_dir, N_DOF) in natural cell order (row j is f_j)."""
+    import torch
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    out = torch.empty((p.B, p.n_dir, p.ndof), dtype=dt, device=f.device)
+    _check(lib.rte_f_natural(p.handle, _ptr(f), _ptr(out), PRECISIONS[precision], _stream()),
+           "rte_f_natural")
+    return out
 
 
 def scalar_flux(p: Problem, f, rho_out, precision="fp64"):

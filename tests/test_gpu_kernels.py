@@ -5,7 +5,7 @@ import pytest
 import rte_workloads as W
 from oracle import dsa as odsa, rom as orom
 from oracle.problem import discretize
-from tests.gpu_common import dev, host, rel_err, say
+from tests.gpu_common import dev, f_library, f_natural, host, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -22,16 +22,6 @@ def R():
     return rte, problems
 
 
-def _dir_major(fb, P):
-    """Library angular flux of one instance [ncell][n_dir][K] -> the oracle's [n_dir][N_DOF]."""
-    return np.ascontiguousarray(np.transpose(np.asarray(fb), (1, 0, 2))).reshape(P.n_dir, P.ndof)
-
-
-def _lib_layout(f_or, P):
-    """The oracle's [n_dir][N_DOF] -> the library's [ncell][n_dir][K]."""
-    return np.ascontiguousarray(np.transpose(f_or.reshape(P.n_dir, P.ncell, P.K), (1, 0, 2)))
-
-
 def _rand_rho(d, seed):
     return np.random.default_rng(seed).uniform(0.0, 1.0, d.ndof) * np.sqrt(d.hx * d.hy)
 
@@ -42,7 +32,7 @@ SWEEP_CASES = [
     (70, 130, 12, 2, 1, 1),       # 3 bands, ragged last band, nx > 64, 3 directions / quadrant
     (70, 130, 12, 2, 2, 4),
     (70, 130, 12, 2, 4, 2),
-    (33, 65, 64, 1, 16, 4),       # 16 directions per lane
+    (33, 65, 64, 1, 8, 4),        # 8 directions per lane, nx < 64 (pipeline stride 64)
     (64, 64, 32, 2, 8, 4),
     (1, 1, 4, 1, 0, 0),           # single cell
     (5, 200, 8, 1, 2, 3),         # nx < 64: padded pipeline stride
@@ -61,16 +51,31 @@ def test_sweep2d_matches_oracle(R, nx, ny, nphi, B, dg, wpb, precision):
     discs = [discretize(plane, b) for b in range(B)]
     rho_in = np.stack([_rand_rho(d, 7 + b) for b, d in enumerate(discs)])
     f_dtype = torch.float64 if precision == "fp64" else torch.float32
-    f = torch.zeros((B, P.ncell, P.n_dir, P.K), dtype=f_dtype, device="cuda")
+    fd = torch.zeros(rte.f_shape(P), dtype=f_dtype, device="cuda")
     rs = torch.zeros((B, P.ndof), dtype=torch.float64, device="cuda")
-    rte.sweep(P, dev(rho_in), f_out=f, rho_star_out=rs, precision=precision)
+    rte.sweep(P, dev(rho_in), f_out=fd, rho_star_out=rs, precision=precision)
     tol = TOL64 if precision == "fp64" else TOL32
-    rs, f = host(rs), host(f)
+    rs, f = host(rs), host(fd)
+    f_or_all = []
     for b, d in enumerate(discs):
         r_or, f_or = d.sweep(rho_in[b], want_f=True)
+        f_or_all.append(f_or)
         assert rel_err(rs[b], r_or) < tol, (b, rel_err(rs[b], r_or))
-        fb = _dir_major(f[b], P)
+        fb = f_natural(f[b], P)
         assert rel_err(fb, f_or) < tol, (b, rel_err(fb, f_or))
+    # the library's own conversion to natural order moves values exactly
+    fn = host(rte.f_natural(P, fd, precision))
+    assert np.array_equal(fn, np.stack([f_natural(f[b], P) for b in range(B)]))
+    # f alone (no partial densities formed): the same values
+    fd2 = torch.zeros_like(fd)
+    rte.sweep(P, dev(rho_in), f_out=fd2, precision=precision)
+    assert np.array_equal(host(fd2), f)
+    # quadrature reduction of the oracle's angular flux in the library layout
+    if precision == "fp64":
+        out = torch.zeros((B, P.ndof), dtype=torch.float64, device="cuda")
+        rte.scalar_flux(P, dev(np.stack([f_library(f_or_all[b], P) for b in range(B)])), out)
+        ref = np.stack([d.w @ f_or_all[b] for b, d in enumerate(discs)])
+        assert rel_err(host(out), ref) < 1e-14
     # zero inflow variant (boundary condition of the kinetic correction equation)
     rte.sweep(P, dev(rho_in), rho_star_out=(rs2 := torch.zeros_like(torch.as_tensor(rs, device="cuda"))),
               zero_inflow=True, precision=precision)
@@ -97,7 +102,7 @@ def test_sweep1d_and_scalar_flux(R, precision):
     discs = [discretize(s) for s in batch]
     rho_in = np.stack([np.random.default_rng(b).uniform(0, 1, d.ndof) for b, d in enumerate(discs)])
     f_dtype = torch.float64 if precision == "fp64" else torch.float32
-    f = torch.zeros((3, P.ncell, P.n_dir, P.K), dtype=f_dtype, device="cuda")
+    f = torch.zeros(rte.f_shape(P), dtype=f_dtype, device="cuda")
     rs = torch.zeros((3, P.ndof), dtype=torch.float64, device="cuda")
     rte.sweep(P, dev(rho_in), f_out=f, rho_star_out=rs, precision=precision)
     tol = TOL64 if precision == "fp64" else TOL32
@@ -105,12 +110,12 @@ def test_sweep1d_and_scalar_flux(R, precision):
     for b, d in enumerate(discs):
         r_or, f_or = d.sweep(rho_in[b], want_f=True)
         assert rel_err(rs_h[b], r_or) < tol
-        assert rel_err(_dir_major(f_h[b], P), f_or) < tol
+        assert rel_err(f_natural(f_h[b], P), f_or) < tol
     # scalar flux of the oracle's angular flux
     f_or = np.stack([d.sweep(rho_in[b], want_f=True)[1] for b, d in enumerate(discs)])
     out = torch.zeros((3, P.ndof), dtype=torch.float64, device="cuda")
     say("scalar_flux fp64")
-    f_lib = np.stack([_lib_layout(f_or[b], P) for b in range(3)])
+    f_lib = np.stack([f_library(f_or[b], P) for b in range(3)])
     rte.scalar_flux(P, dev(f_lib), out)
     ref = np.stack([d.w @ f_or[b] for b, d in enumerate(discs)])
     assert rel_err(host(out), ref) < 1e-14
