@@ -834,14 +834,68 @@ __global__ void mg_zero_kernel(const int *state, long long n, double *x) {
     if (t < n) x[(size_t)b * n + t] = 0.0;
 }
 
-// coarsest grid: nsweep damped Jacobi sweeps from zero, one workgroup per instance, vectors in LDS
+// Inverse of the coarsest operator of the instances with mask[b] == 1 (all if null), one
+// workgroup per instance: the dense matrix from the 9-point stencils, Gauss-Jordan elimination in
+// LDS (the operator is SPD: no pivoting), inverse to cinv [B][nc][nc].
+__global__ void __launch_bounds__(256) mg_coarse_invert_kernel(const int *mask, VG g,
+                                                               const double *S, double *cinv) {
+    extern __shared__ double sh[];
+    const int b = blockIdx.x;
+    if (mask && mask[b] != 1) return;
+    const int n = (int)g.nv, nn = n * n;
+    double *A = sh, *X = sh + nn, *f = sh + 2 * nn;
+    const double *Sb = st_of(S, b, g.nv);
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+        const int v = e / n, w = e - v * n;
+        const int vx = v % g.nvx, vy = v / g.nvx, wx = w % g.nvx, wy = w / g.nvx;
+        const int dx = wx - vx, dy = wy - vy;
+        const bool nb = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
+        A[e] = nb ? Sb[((dy + 1) * 3 + dx + 1) * g.nv + v] : 0.0;
+        X[e] = v == w ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double piv = 1.0 / A[k * n + k];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) f[i] = A[i * n + k];
+        __syncthreads();
+        // row k scaled by 1/pivot, every other row i minus f_i times the scaled row k
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            const int i = e / n, j = e - i * n;
+            const double rk = A[k * n + j] * piv, xk = X[k * n + j] * piv;
+            if (i == k) continue;
+            A[e] -= f[i] * rk;
+            X[e] -= f[i] * xk;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            A[k * n + j] *= piv;
+            X[k * n + j] *= piv;
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) cinv[(size_t)b * nn + e] = X[e];
+}
+
+// coarsest grid from zero: x = cinv b when the inverse exists, else nsweep damped Jacobi sweeps;
+// one workgroup per instance, vectors in LDS
 __global__ void __launch_bounds__(256) mg_coarse_kernel(const int *state, VG g, const double *S,
-                                                        const double *bv, double *x, int nsweep) {
+                                                        const double *bv, double *x, int nsweep,
+                                                        const double *cinv) {
     extern __shared__ double sh[];
     const int b = blockIdx.x;
     if (state[b] != 1) return;
     double *xa = sh, *xb = sh + g.nv;
     const size_t o = (size_t)b * g.nv;
+    if (cinv) {
+        const int n = (int)g.nv;
+        const double *Ci = cinv + (size_t)b * n * n;
+        for (int v = threadIdx.x; v < n; v += blockDim.x) {
+            double acc = 0.0;
+            for (int w = 0; w < n; ++w) acc += Ci[v * n + w] * bv[o + w];
+            x[o + v] = acc;
+        }
+        return;
+    }
     const double *Sb = st_of(S, b, g.nv);
     const double *wd = Sb + 9 * g.nv;
     for (long long v = threadIdx.x; v < g.nv; v += blockDim.x) xa[v] = wd[v] * bv[o + v];
@@ -967,7 +1021,7 @@ struct SmallLevels {
 
 __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state, SmallLevels sl,
                                                                const double *b_top, double *x_top,
-                                                               int nsweep) {
+                                                               int nsweep, const double *cinv) {
     extern __shared__ double sh[];
     const int b = blockIdx.x;
     if (state[b] != 1) return;
@@ -1018,8 +1072,19 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
         }
         __syncthreads();
     }
-    // coarsest: damped Jacobi sweeps from zero; the result ends in xb
-    {
+    // coarsest from zero: the exact solve when the inverse exists, else damped Jacobi sweeps;
+    // the result ends in xb
+    if (cinv) {
+        const int l = sl.n - 1;
+        const int n = (int)sl.nv[l];
+        const double *Ci = cinv + (size_t)b * n * n;
+        for (int v = t; v < n; v += nt) {
+            double acc = 0.0;
+            for (int w = 0; w < n; ++w) acc += Ci[v * n + w] * bv[l][w];
+            xb[l][v] = acc;
+        }
+        __syncthreads();
+    } else {
         const int l = sl.n - 1;
         const VG g = grid_of(l);
         const double *S = S_of(l);
@@ -1159,13 +1224,13 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
             lds += 4 * M.nv * (long long)sizeof(double);
         }
         hipLaunchKernelGGL(mg_small_vcycle_kernel, dim3(p->B), dim3(1024), (size_t)lds, s, c.state,
-                           sl, L.bv, L.xb, kCoarseSweeps);
+                           sl, L.bv, L.xb, kCoarseSweeps, c.mg.cinv);
         return L.xb;
     }
     if (l == c.mg.L - 1) {
         if (L.nv <= 4096) {
             hipLaunchKernelGGL(mg_coarse_kernel, dim3(p->B), dim3(256), 2 * L.nv * sizeof(double), s,
-                               c.state, g, L.S, L.bv, L.xa, kCoarseSweeps);
+                               c.state, g, L.S, L.bv, L.xa, kCoarseSweeps, c.mg.cinv);
             return L.xa;
         }
         hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xa, L.bv, L.xa, 0);
@@ -1225,6 +1290,12 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
                 hipLaunchKernelGGL(mg_scatter_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.rv, L.S);
             }
         hipLaunchKernelGGL(mg_wdiag_kernel, gv, dim3(256), 0, s, all, g, L.S);
+    }
+    if (c.mg.cinv) {
+        const MGLevel &C = c.mg.lv[c.mg.L - 1];
+        const size_t lds = (2 * (size_t)C.nv * C.nv + C.nv) * sizeof(double);
+        hipLaunchKernelGGL(mg_coarse_invert_kernel, dim3(p->B), dim3(256), lds, s, all, vg_of(C),
+                           C.S, c.mg.cinv);
     }
     return hipGetLastError();
 }

@@ -104,9 +104,12 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
                 g.bv = c.take<double>(B * (size_t)g.nv);
                 g.rv = c.take<double>(B * (size_t)g.nv);
             }
+            L.cg.mg.cinv = nullptr;
             if (L.cg.mg.L > 0) {
                 L.cg.mg.t = c.take<double>(B * nd);
                 L.cg.mg.e = c.take<double>(B * (size_t)L.cg.mg.lv[0].nv);
+                const long long nc = L.cg.mg.lv[L.cg.mg.L - 1].nv;
+                if (nc <= kDirectCoarse) L.cg.mg.cinv = c.take<double>(B * (size_t)(nc * nc));
             }
         } else {
             L.dsa1d = c.take<double>(B * (size_t)p->nx * 20);

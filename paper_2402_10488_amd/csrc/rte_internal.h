@@ -244,7 +244,11 @@ struct MGSpace {
     MGLevel lv[kMaxLevels];
     double *t;             // [B][ndof] DG scratch
     double *e;             // [B][nv0] probe vector
+    double *cinv;          // [B][nc][nc] inverse of the coarsest operator (nc = its vertices),
+                           // when nc <= kDirectCoarse; null otherwise (damped Jacobi sweeps)
 };
+// coarsest vertex grids up to this many vertices are solved exactly (dense inverse per instance)
+constexpr int kDirectCoarse = 60;     // its inversion holds 2 nc^2 + nc doubles in LDS (< 64 KiB)
 // levels for an nx x ny mesh (0 when the mesh is too small for a coarse space)
 int mg_levels(int nx, int ny, int *nvx, int *nvy);
 
