@@ -305,16 +305,19 @@ int rte_sisa_iterate(const rte_problem *p, rte_mode mode, const rte_rom *rom, co
 
 /* ------------------------------------------------------------------------------------------
  * Offline construction of the correction ROM (Sec. 3.1 POD, Sec. 3.2.1 snapshots, Sec. 3.1.1
- * reduced affine operators).  Building blocks driven by the Python offline builder; all FP64.
+ * reduced affine operators).  Building blocks driven by the Python offline builder.  Results
+ * and accumulations are FP64; the long snapshot columns may be stored in FP32 (RTE_MIXED), which
+ * halves the memory of bases whose FP64 columns would not fit in HBM.
  * ------------------------------------------------------------------------------------------ */
 
 /* Snapshot columns delta f = f_final - f_iter per instance (Sec. 3.2.1); f_iter == NULL stands
  * for the zero initial state.  f_final, f_iter: device FP64 angular fluxes in the sweep's layout
- * (see the conventions above); columns are written direction-major in natural cell order, entry
- * j * N_DOF + dof;
- * column b is written at cols + b * stride (stride >= n_dir * N_DOF). */
+ * (see the conventions above); the difference is formed in FP64 and written as double
+ * (cols_prec RTE_FP64) or rounded to float (RTE_MIXED), direction-major in natural cell order,
+ * entry j * N_DOF + dof; column b is written at cols + b * stride elements
+ * (stride >= n_dir * N_DOF). */
 int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double *f_iter,
-                      double *cols, long long stride, rte_stream_t stream);
+                      void *cols, long long stride, rte_precision cols_prec, rte_stream_t stream);
 
 /* The angular flux f (layout of the conventions above, double for RTE_FP64, float for
  * RTE_MIXED) in natural order: out device [B][n_dir][N_DOF], same type, out[b][j] = f_j of
@@ -322,39 +325,41 @@ int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double 
 int rte_f_natural(const rte_problem *p, const void *f, void *out, rte_precision prec,
                   rte_stream_t stream);
 
-/* G = X^T Y for column-major X [nx][len], Y [ny][len] (device), G [nx][ny] device, on the matrix
- * cores.  With cell_class != NULL only rows whose cell ((row / K) mod ncell) has class cls are
- * summed (the material-class restriction of the reduced affine operators).  ws: device
- * scratch for the split partial sums (ENOMEM if too small for one split). */
-int rte_gram(const double *X, int nx, const double *Y, int ny, long long len,
-             const int *cell_class, int K, long long ncell, int cls, double *G, void *ws,
-             size_t ws_bytes, rte_stream_t stream);
+/* G = X^T Y for column-major X [nx][len], Y [ny][len] (device; double for RTE_FP64, float for
+ * RTE_MIXED, widened to double), G [nx][ny] FP64 device, on the FP64 matrix cores.  With
+ * cell_class != NULL only rows whose cell ((row / K) mod ncell) has class cls are summed (the
+ * material-class restriction of the reduced affine operators).  ws: device scratch for the
+ * split partial sums (ENOMEM if too small for one split). */
+int rte_gram(const void *X, rte_precision xprec, int nx, const void *Y, rte_precision yprec,
+             int ny, long long len, const int *cell_class, int K, long long ncell, int cls,
+             double *G, void *ws, size_t ws_bytes, rte_stream_t stream);
 
 /* Eigen-decomposition of a symmetric n x n device matrix A (n <= 256, overwritten) by cyclic
  * Jacobi: evals [n] (unsorted), evecs [n][n] with eigenvectors as columns (method of snapshots,
  * Sec. 3.1: F^T F = V Lambda^2 V^T). */
 int rte_sym_eig(double *A, int n, double *evals, double *evecs, rte_stream_t stream);
 
-/* out[c] = sum_col W[col][c] X[col] for X [ncol][len], W [ncol][r], out [r][len] (device), on
- * the matrix cores (the basis U = F V Lambda^-1 of the method of snapshots). */
+/* out[c] = sum_col W[col][c] X[col] for X [ncol][len], W [ncol][r], out [r][len] (device FP64),
+ * on the matrix cores (the basis U = F V Lambda^-1 of the method of snapshots). */
 int rte_combine(const double *X, int ncol, long long len, const double *W, int r, double *out,
                 rte_stream_t stream);
 
 /* y_j = D_j x_j of eq. (dg_matrix_vec) (streaming + upwind flux, no boundary load) for nvec
- * vectors x, y [nvec][n_dir][N_DOF] (2D). */
-int rte_apply_streaming(const rte_problem *p, const double *x, int nvec, double *y,
-                        rte_stream_t stream);
+ * vectors x [nvec][n_dir][N_DOF] (double or float per xprec), y FP64 of the same shape (2D). */
+int rte_apply_streaming(const rte_problem *p, const void *x, rte_precision xprec, int nvec,
+                        double *y, rte_stream_t stream);
+
+/* out[side][k] = sum_j U_k,j^T b_side,j: projections of the load of a unit isotropic inflow on each
+ * side (x=0, x=Lx, y=0, y=Ly; eq. (dg_matrix_vec)) on the vectors U [nvec][n_dir][N_DOF]
+ * (device, direction-major, double or float per uprec).  out: device FP64 [4][nvec].  2D only. */
+int rte_inflow_loads(const rte_problem *p, const void *U, rte_precision uprec, int nvec,
+                     double *out, rte_stream_t stream);
 
 /* out[v] = sum_j w_j x[v][j] (weighted != 0) or sum_j x[v][j] (weighted == 0) for
- * x [nvec][n_dir][N_DOF], out [nvec][N_DOF]: U^rho and U^iso of eq. (rho_basis). */
-/* out[side][k] = sum_j U_k,j^T b_side,j: projections of the load of a unit isotropic inflow on each
- * side (x=0, x=Lx, y=0, y=Ly; eq. (dg_matrix_vec)) on the basis vectors U [nvec][n_dir][N_DOF]
- * (device, direction-major).  out: device [4][nvec].  2D only. */
-int rte_inflow_loads(const rte_problem *p, const double *U, int nvec, double *out,
-                     rte_stream_t stream);
-
-int rte_direction_sum(const rte_problem *p, const double *x, int nvec, int weighted, double *out,
-                      rte_stream_t stream);
+ * x [nvec][n_dir][N_DOF] (double or float per xprec), out FP64 [nvec][N_DOF]: U^rho and U^iso of
+ * eq. (rho_basis). */
+int rte_direction_sum(const rte_problem *p, const void *x, rte_precision xprec, int nvec,
+                      int weighted, double *out, rte_stream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around every launch of the
  * named kernel group (process-wide; not for concurrent use from several threads).

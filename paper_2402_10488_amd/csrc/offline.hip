@@ -27,9 +27,9 @@ inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) /
 // [B][n_dir][cell][K] with each direction's cells in band order of its reflected coordinates; 1D:
 // [B][cell][n_dir][K]), optionally minus a second one: out[b * stride + (j * ncell + cell) * K + k].
 // In 2D a thread owns one stored position, so the reads of a wavefront are contiguous.
-template <typename T>
+template <typename T, typename TO>
 __global__ void f_gather_kernel(int dim, int nx, int ny, long long ncell, int K, int n_dir,
-                                const double *vxy, const T *fa, const T *fb, T *out,
+                                const double *vxy, const T *fa, const T *fb, TO *out,
                                 long long stride) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
@@ -45,12 +45,14 @@ __global__ void f_gather_kernel(int dim, int nx, int ny, long long ncell, int K,
         cell = e;
         src = (((size_t)b * ncell + e) * n_dir + j) * K;
     }
-    T *o = out + (size_t)b * stride + ((size_t)j * ncell + cell) * K;
-    for (int k = 0; k < K; ++k) o[k] = fb ? fa[src + k] - fb[src + k] : fa[src + k];
+    TO *o = out + (size_t)b * stride + ((size_t)j * ncell + cell) * K;
+    for (int k = 0; k < K; ++k) o[k] = (TO)(fb ? fa[src + k] - fb[src + k] : fa[src + k]);
 }
 
-// G_part[split][i][j] = sum over rows in the split of X[i][row] Y[j][row] (row in class cls)
-__global__ void __launch_bounds__(64) gram_kernel(const double *X, int nxc, const double *Y,
+// G_part[split][i][j] = sum over rows in the split of X[i][row] Y[j][row] (row in class cls);
+// FP32 inputs are widened to FP64 before the FP64 matrix-core product
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(64) gram_kernel(const TX *X, int nxc, const TY *Y,
                                                   int nyc, long long len, long long per_split,
                                                   const int *cell_class, int K, long long ncell,
                                                   int cls, double *part) {
@@ -70,8 +72,8 @@ __global__ void __launch_bounds__(64) gram_kernel(const double *X, int nxc, cons
             const long long k = k0 + 4 * kq + s;
             bool in = k < k_end;
             if (in && cell_class) in = cell_class[(k / K) % ncell] == cls;
-            av[s] = (in && li) ? X[(size_t)ci * len + k] : 0.0;
-            bv[s] = (in && lj) ? Y[(size_t)cj * len + k] : 0.0;
+            av[s] = (in && li) ? (double)X[(size_t)ci * len + k] : 0.0;
+            bv[s] = (in && lj) ? (double)Y[(size_t)cj * len + k] : 0.0;
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
@@ -213,8 +215,9 @@ __global__ void __launch_bounds__(64) combine_kernel(const double *X, int ncol, 
 // y_j = D_j x_j for every vector and direction (upwind DG streaming operator, no boundary load),
 // in the reflected coordinates of the direction's quadrant: D = a (A (x) I) + b (I (x) A) minus
 // the inflow coupling to the upwind neighbours' outgoing traces.
+template <typename TX>
 __global__ void apply_streaming_kernel(int nx, int ny, int n_dir, int nvec, const double *vx,
-                                       const double *vy, double hx, double hy, const double *x,
+                                       const double *vy, double hx, double hy, const TX *x,
                                        double *y) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long ncell = (long long)nx * ny;
@@ -226,10 +229,11 @@ __global__ void apply_streaming_kernel(int nx, int ny, int n_dir, int nvec, cons
     const int ix = (int)(cell % nx), iy = (int)(cell / nx);
     const double sx = vx[j] < 0 ? -1.0 : 1.0, sy = vy[j] < 0 ? -1.0 : 1.0;
     const double a = fabs(vx[j]) / hx, b = fabs(vy[j]) / hy, c = kS3;
-    const double *xv = x + (size_t)vj * ncell * 4;
+    const TX *xv = x + (size_t)vj * ncell * 4;
     auto load = [&](long long cc, double f[4]) {
-        const double4 v = *reinterpret_cast<const double4 *>(xv + cc * 4);
-        f[0] = v.x; f[1] = sx * v.y; f[2] = sy * v.z; f[3] = sx * sy * v.w;   // reflected
+        const TX *e = xv + cc * 4;
+        f[0] = (double)e[0]; f[1] = sx * (double)e[1]; f[2] = sy * (double)e[2];
+        f[3] = sx * sy * (double)e[3];                                          // reflected
     };
     double f[4];
     load(cell, f);
@@ -258,14 +262,15 @@ __global__ void apply_streaming_kernel(int nx, int ny, int n_dir, int nvec, cons
     *reinterpret_cast<double4 *>(y + (size_t)vj * ncell * 4 + cell * 4) = r;
 }
 
+template <typename TX>
 __global__ void direction_sum_kernel(long long ndof, int n_dir, int nvec, const double *w,
-                                     const double *x, double *out) {
+                                     const TX *x, double *out) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
     if (t >= ndof) return;
-    const double *xv = x + (size_t)v * n_dir * ndof + t;
+    const TX *xv = x + (size_t)v * n_dir * ndof + t;
     double s = 0.0;
-    for (int j = 0; j < n_dir; ++j) s += (w ? w[j] : 1.0) * xv[(size_t)j * ndof];
+    for (int j = 0; j < n_dir; ++j) s += (w ? w[j] : 1.0) * (double)xv[(size_t)j * ndof];
     out[(size_t)v * ndof + t] = s;
 }
 
@@ -273,9 +278,10 @@ __global__ void direction_sum_kernel(long long ndof, int n_dir, int nvec, const 
 // isotropic inflow on a side (eq. (dg_matrix_vec)) enters the cells next to it for the
 // directions entering there, |v.n| g (h_t / sqrt(hx hy)) L_a(-+1) on the face-normal index a
 // (tangential index 0), h_t the face length.  One workgroup per (vector, side), fixed-order sum.
+template <typename TU>
 __global__ void __launch_bounds__(256) inflow_load_kernel(int nx, int ny, long long ndof, int n_dir,
                                                          const double *vxy, double hx, double hy,
-                                                         const double *U, int nvec, double *out) {
+                                                         const TU *U, int nvec, double *out) {
     const int v = blockIdx.x, side = blockIdx.y;
     const bool xs = side < 2;                      // x = 0 / x = Lx faces
     const int nface = xs ? ny : nx;                // cells along the side
@@ -295,8 +301,8 @@ __global__ void __launch_bounds__(256) inflow_load_kernel(int nx, int ny, long l
         // trace of the face-normal Legendre index on the face: -sqrt(3) at the low, +sqrt(3) at
         // the high face of the cell (dof 1 for x faces, dof 2 for y faces)
         const double tr = (side == 0 || side == 2) ? -s3 : s3;
-        const double *u = U + ((size_t)v * n_dir + j) * ndof + (size_t)cell * 4;
-        acc += fabs(vn) * scale * (u[0] + tr * (xs ? u[1] : u[2]));
+        const TU *u = U + ((size_t)v * n_dir + j) * ndof + (size_t)cell * 4;
+        acc += fabs(vn) * scale * ((double)u[0] + tr * (double)(xs ? u[1] : u[2]));
     }
     __shared__ double sh[256];
     sh[threadIdx.x] = acc;
@@ -316,13 +322,21 @@ using namespace rte;
 extern "C" {
 
 int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double *f_iter,
-                      double *cols, long long stride, rte_stream_t stream) {
+                      void *cols, long long stride, rte_precision cols_prec, rte_stream_t stream) {
     if (!p || !f_final || !cols) return RTE_EINVAL;
+    if (cols_prec != RTE_FP64 && cols_prec != RTE_MIXED) return RTE_EINVAL;
     const long long len = (long long)p->n_dir * p->ndof;
     if (stride < len) return RTE_EINVAL;
-    hipLaunchKernelGGL(f_gather_kernel<double>, dim3(cdiv((long long)p->n_dir * p->ncell, 256), p->B),
-                       dim3(256), 0, (hipStream_t)stream, p->dim, p->nx, p->ny, p->ncell, p->K,
-                       p->n_dir, p->d_vxy, f_final, f_iter, cols, stride);
+    const dim3 grid(cdiv((long long)p->n_dir * p->ncell, 256), p->B);
+    hipStream_t s = (hipStream_t)stream;
+    if (cols_prec == RTE_MIXED)
+        hipLaunchKernelGGL((f_gather_kernel<double, float>), grid, dim3(256), 0, s, p->dim, p->nx,
+                           p->ny, p->ncell, p->K, p->n_dir, p->d_vxy, f_final, f_iter, (float *)cols,
+                           stride);
+    else
+        hipLaunchKernelGGL((f_gather_kernel<double, double>), grid, dim3(256), 0, s, p->dim, p->nx,
+                           p->ny, p->ncell, p->K, p->n_dir, p->d_vxy, f_final, f_iter,
+                           (double *)cols, stride);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 
@@ -334,20 +348,22 @@ int rte_f_natural(const rte_problem *p, const void *f, void *out, rte_precision 
     const long long stride = (long long)p->n_dir * p->ndof;
     hipStream_t s = (hipStream_t)stream;
     if (prec == RTE_MIXED)
-        hipLaunchKernelGGL(f_gather_kernel<float>, grid, dim3(256), 0, s, p->dim, p->nx, p->ny,
-                           p->ncell, p->K, p->n_dir, p->d_vxy, (const float *)f, (const float *)nullptr,
-                           (float *)out, stride);
+        hipLaunchKernelGGL((f_gather_kernel<float, float>), grid, dim3(256), 0, s, p->dim, p->nx,
+                           p->ny, p->ncell, p->K, p->n_dir, p->d_vxy, (const float *)f,
+                           (const float *)nullptr, (float *)out, stride);
     else
-        hipLaunchKernelGGL(f_gather_kernel<double>, grid, dim3(256), 0, s, p->dim, p->nx, p->ny,
-                           p->ncell, p->K, p->n_dir, p->d_vxy, (const double *)f,
+        hipLaunchKernelGGL((f_gather_kernel<double, double>), grid, dim3(256), 0, s, p->dim, p->nx,
+                           p->ny, p->ncell, p->K, p->n_dir, p->d_vxy, (const double *)f,
                            (const double *)nullptr, (double *)out, stride);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 
-int rte_gram(const double *X, int nxc, const double *Y, int nyc, long long len,
-             const int *cell_class, int K, long long ncell, int cls, double *G, void *ws,
-             size_t ws_bytes, rte_stream_t stream) {
+int rte_gram(const void *X, rte_precision xprec, int nxc, const void *Y, rte_precision yprec,
+             int nyc, long long len, const int *cell_class, int K, long long ncell, int cls,
+             double *G, void *ws, size_t ws_bytes, rte_stream_t stream) {
     if (!X || !Y || !G || nxc < 1 || nyc < 1 || len < 1 || !ws) return RTE_EINVAL;
+    if ((xprec != RTE_FP64 && xprec != RTE_MIXED) || (yprec != RTE_FP64 && yprec != RTE_MIXED))
+        return RTE_EINVAL;
     if (cell_class && (K < 1 || ncell < 1)) return RTE_EINVAL;
     const long long tiles = (long long)cdiv(nxc, 16) * cdiv(nyc, 16);
     long long nsplit = (4096 + tiles - 1) / tiles;
@@ -359,8 +375,21 @@ int rte_gram(const double *X, int nxc, const double *Y, int nyc, long long len,
     long long per = (len + nsplit - 1) / nsplit;
     per = (per + 15) / 16 * 16;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(gram_kernel, dim3((unsigned)nsplit, cdiv(nxc, 16), cdiv(nyc, 16)), dim3(64),
-                       0, s, X, nxc, Y, nyc, len, per, cell_class, K, ncell, cls, (double *)ws);
+    const dim3 grid((unsigned)nsplit, cdiv(nxc, 16), cdiv(nyc, 16));
+    double *part = (double *)ws;
+    const bool xf = xprec == RTE_MIXED, yf = yprec == RTE_MIXED;
+    if (xf && yf)
+        hipLaunchKernelGGL((gram_kernel<float, float>), grid, dim3(64), 0, s, (const float *)X, nxc,
+                           (const float *)Y, nyc, len, per, cell_class, K, ncell, cls, part);
+    else if (xf)
+        hipLaunchKernelGGL((gram_kernel<float, double>), grid, dim3(64), 0, s, (const float *)X, nxc,
+                           (const double *)Y, nyc, len, per, cell_class, K, ncell, cls, part);
+    else if (yf)
+        hipLaunchKernelGGL((gram_kernel<double, float>), grid, dim3(64), 0, s, (const double *)X,
+                           nxc, (const float *)Y, nyc, len, per, cell_class, K, ncell, cls, part);
+    else
+        hipLaunchKernelGGL((gram_kernel<double, double>), grid, dim3(64), 0, s, (const double *)X,
+                           nxc, (const double *)Y, nyc, len, per, cell_class, K, ncell, cls, part);
     const long long n = (long long)nxc * nyc;
     hipLaunchKernelGGL(sum_splits_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, (const double *)ws,
                        (int)nsplit, n, G);
@@ -382,31 +411,51 @@ int rte_combine(const double *X, int ncol, long long len, const double *W, int r
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 
-int rte_apply_streaming(const rte_problem *p, const double *x, int nvec, double *y,
-                        rte_stream_t stream) {
+int rte_apply_streaming(const rte_problem *p, const void *x, rte_precision xprec, int nvec,
+                        double *y, rte_stream_t stream) {
     if (!p || !x || !y || nvec < 1 || p->dim != 2) return RTE_EINVAL;
+    if (xprec != RTE_FP64 && xprec != RTE_MIXED) return RTE_EINVAL;
     const long long tot = (long long)nvec * p->n_dir * p->ncell;
-    hipLaunchKernelGGL(apply_streaming_kernel, dim3(cdiv(tot, 256)), dim3(256), 0,
-                       (hipStream_t)stream, p->nx, p->ny, p->n_dir, nvec, p->d_vxy,
-                       p->d_vxy + p->n_dir, p->hx, p->hy, x, y);
+    hipStream_t s = (hipStream_t)stream;
+    if (xprec == RTE_MIXED)
+        hipLaunchKernelGGL(apply_streaming_kernel<float>, dim3(cdiv(tot, 256)), dim3(256), 0, s,
+                           p->nx, p->ny, p->n_dir, nvec, p->d_vxy, p->d_vxy + p->n_dir, p->hx,
+                           p->hy, (const float *)x, y);
+    else
+        hipLaunchKernelGGL(apply_streaming_kernel<double>, dim3(cdiv(tot, 256)), dim3(256), 0, s,
+                           p->nx, p->ny, p->n_dir, nvec, p->d_vxy, p->d_vxy + p->n_dir, p->hx,
+                           p->hy, (const double *)x, y);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 
-int rte_inflow_loads(const rte_problem *p, const double *U, int nvec, double *out,
-                     rte_stream_t stream) {
+int rte_inflow_loads(const rte_problem *p, const void *U, rte_precision uprec, int nvec,
+                     double *out, rte_stream_t stream) {
     if (!p || !U || !out || nvec < 1) return RTE_EINVAL;
+    if (uprec != RTE_FP64 && uprec != RTE_MIXED) return RTE_EINVAL;
     if (p->dim != 2) return RTE_EUNSUPPORTED;
-    hipLaunchKernelGGL(inflow_load_kernel, dim3(nvec, 4), dim3(256), 0, (hipStream_t)stream,
-                       p->nx, p->ny, p->ndof, p->n_dir, p->d_vxy, p->hx, p->hy, U, nvec, out);
+    hipStream_t s = (hipStream_t)stream;
+    if (uprec == RTE_MIXED)
+        hipLaunchKernelGGL(inflow_load_kernel<float>, dim3(nvec, 4), dim3(256), 0, s, p->nx, p->ny,
+                           p->ndof, p->n_dir, p->d_vxy, p->hx, p->hy, (const float *)U, nvec, out);
+    else
+        hipLaunchKernelGGL(inflow_load_kernel<double>, dim3(nvec, 4), dim3(256), 0, s, p->nx, p->ny,
+                           p->ndof, p->n_dir, p->d_vxy, p->hx, p->hy, (const double *)U, nvec, out);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 
-int rte_direction_sum(const rte_problem *p, const double *x, int nvec, int weighted, double *out,
-                      rte_stream_t stream) {
+int rte_direction_sum(const rte_problem *p, const void *x, rte_precision xprec, int nvec,
+                      int weighted, double *out, rte_stream_t stream) {
     if (!p || !x || !out || nvec < 1) return RTE_EINVAL;
-    hipLaunchKernelGGL(direction_sum_kernel, dim3(cdiv(p->ndof, 256), nvec), dim3(256), 0,
-                       (hipStream_t)stream, p->ndof, p->n_dir, nvec, weighted ? p->d_w : nullptr,
-                       x, out);
+    if (xprec != RTE_FP64 && xprec != RTE_MIXED) return RTE_EINVAL;
+    const dim3 grid(cdiv(p->ndof, 256), nvec);
+    const double *w = weighted ? p->d_w : nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (xprec == RTE_MIXED)
+        hipLaunchKernelGGL(direction_sum_kernel<float>, grid, dim3(256), 0, s, p->ndof, p->n_dir,
+                           nvec, w, (const float *)x, out);
+    else
+        hipLaunchKernelGGL(direction_sum_kernel<double>, grid, dim3(256), 0, s, p->ndof, p->n_dir,
+                           nvec, w, (const double *)x, out);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 

@@ -1,14 +1,19 @@
 """Offline construction of the correction ROM on the GPU (Sec. 3.1, 3.2.1, 3.1.1).
 
 Orchestrates library entry points (argument marshalling only):
-  1. FP64 f-form SI-DSA training solves (Alg. 1) that keep f^(1), f^(2), ... and the converged f;
+  1. FP64 f-form SI-DSA training solves (Alg. 1) that keep f^(1), f^(2), ... and the converged f,
+     a chunk of training instances at a time;
   2. snapshot columns delta f = f - f^(l) for the window of iterates that starts at the zero
-     initial state (so f itself is the first column), Sec. 3.2.1;
-  3. method of snapshots: G = dF^T dF on the matrix cores, Jacobi eigenpairs, basis
-     dU = dF V_r Lambda_r^{-1/2} (the r largest singular values);
-  4. dU^rho = sum_j w_j dU_j, dU^iso = sum_j dU_j (eq. (rho_basis)) and the reduced affine
-     operators A0 = sum_j dU_j^T D_j dU_j, A_t,k = sum_j dU_j^T M_k dU_j,
-     A_s,k = -(dU^iso)^T M_k dU^rho for the material classes k (Sec. 3.1.1).
+     initial state (so f itself is the first column), Sec. 3.2.1, stored in FP64 or FP32;
+  3. method of snapshots: G = dF^T dF on the matrix cores, Jacobi eigenpairs; the basis is
+     dU = dF W with W = V_r Lambda_r^{-1/2} (the r largest singular values);
+  4. everything the reduced model needs, formed from the snapshot columns and W without the
+     basis itself: dU^rho = (sum_j w_j dF_j) W, dU^iso = (sum_j dF_j) W (eq. (rho_basis)),
+     A0 = sum_j dU_j^T D_j dU_j = W^T (dF^T D dF) W, A_t,k = sum_j dU_j^T M_k dU_j =
+     W^T (dF^T M_k dF) W, A_s,k = -(dU^iso)^T M_k dU^rho for the material classes k (Sec. 3.1.1)
+     and the reduced unit-inflow loads (W^T applied to those of the columns).
+FP32 columns halve the memory of the snapshot matrix (all products accumulate in FP64), which
+lets the 512^2 x 256-direction training set (192 columns of 2.7e8 values) fit on one device.
 """
 import ctypes
 from dataclasses import dataclass
@@ -16,17 +21,28 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import problems
-from .rte import _check, _ptr, _stream, lib
+from .rte import PRECISIONS, _check, _ptr, _stream, lib
 
 _vp = ctypes.c_void_p
-lib.rte_pod_snapshots.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_longlong, _vp]
-lib.rte_gram.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_longlong, _vp, ctypes.c_int,
-                         ctypes.c_longlong, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp]
-lib.rte_sym_eig.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
-lib.rte_combine.argtypes = [_vp, ctypes.c_int, ctypes.c_longlong, _vp, ctypes.c_int, _vp, _vp]
-lib.rte_apply_streaming.argtypes = [_vp, _vp, ctypes.c_int, _vp, _vp]
-lib.rte_direction_sum.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
-lib.rte_inflow_loads.argtypes = [_vp, _vp, ctypes.c_int, _vp, _vp]
+_i, _ll = ctypes.c_int, ctypes.c_longlong
+lib.rte_pod_snapshots.argtypes = [_vp, _vp, _vp, _vp, _ll, _i, _vp]
+lib.rte_gram.argtypes = [_vp, _i, _i, _vp, _i, _i, _ll, _vp, _i, _ll, _i, _vp, _vp, ctypes.c_size_t,
+                         _vp]
+lib.rte_sym_eig.argtypes = [_vp, _i, _vp, _vp, _vp]
+lib.rte_combine.argtypes = [_vp, _i, _ll, _vp, _i, _vp, _vp]
+lib.rte_apply_streaming.argtypes = [_vp, _vp, _i, _i, _vp, _vp]
+lib.rte_direction_sum.argtypes = [_vp, _vp, _i, _i, _i, _vp, _vp]
+lib.rte_inflow_loads.argtypes = [_vp, _vp, _i, _i, _vp, _vp]
+
+
+def _prec(t):
+    """Library precision code of a tensor's element type (float64 or float32)."""
+    import torch
+    if t.dtype == torch.float64:
+        return PRECISIONS["fp64"]
+    if t.dtype == torch.float32:
+        return PRECISIONS["mixed"]
+    raise TypeError(f"unsupported element type {t.dtype}")
 
 
 @dataclass
@@ -43,15 +59,15 @@ class RomArrays:
 
 
 def gram(X, Y, cell_class=None, K=4, ncell=1, cls=0, scratch=None):
-    """G = X^T Y for column-major X [nx, len], Y [ny, len] (CUDA float64)."""
+    """G = X^T Y (FP64) for column-major X [nx, len], Y [ny, len] (CUDA float64 or float32)."""
     import torch
     nx, L = X.shape
     ny = Y.shape[0]
     G = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
     if scratch is None:
         scratch = torch.empty(4096 * nx * ny + 256, dtype=torch.float64, device=X.device)
-    _check(lib.rte_gram(_ptr(X), nx, _ptr(Y), ny, L, _ptr(cell_class), K, ncell, cls, _ptr(G),
-                        _ptr(scratch), scratch.numel() * 8, _stream()), "rte_gram")
+    _check(lib.rte_gram(_ptr(X), _prec(X), nx, _ptr(Y), _prec(Y), ny, L, _ptr(cell_class), K, ncell,
+                        cls, _ptr(G), _ptr(scratch), scratch.numel() * 8, _stream()), "rte_gram")
     return G
 
 
@@ -75,9 +91,10 @@ def combine(X, W):
 
 
 def apply_streaming(P, x):
+    """D_j x_j (FP64) for x [nvec, n_dir, N_DOF] (float64 or float32)."""
     import torch
-    y = torch.empty_like(x)
-    _check(lib.rte_apply_streaming(P.handle, _ptr(x), x.shape[0], _ptr(y), _stream()),
+    y = torch.empty(x.shape, dtype=torch.float64, device=x.device)
+    _check(lib.rte_apply_streaming(P.handle, _ptr(x), _prec(x), x.shape[0], _ptr(y), _stream()),
            "rte_apply_streaming")
     return y
 
@@ -85,8 +102,9 @@ def apply_streaming(P, x):
 def inflow_loads(P, U3):
     """[4, nvec] projections of unit side-inflow loads on U3 [nvec][n_dir][N_DOF]."""
     import torch
+    U3 = U3.contiguous()
     out = torch.empty((4, U3.shape[0]), dtype=torch.float64, device=U3.device)
-    _check(lib.rte_inflow_loads(P.handle, _ptr(U3.contiguous()), U3.shape[0], _ptr(out), _stream()),
+    _check(lib.rte_inflow_loads(P.handle, _ptr(U3), _prec(U3), U3.shape[0], _ptr(out), _stream()),
            "rte_inflow_loads")
     return out
 
@@ -94,21 +112,24 @@ def inflow_loads(P, U3):
 def direction_sum(P, x, weighted):
     import torch
     out = torch.empty((x.shape[0], P.ndof), dtype=torch.float64, device=x.device)
-    _check(lib.rte_direction_sum(P.handle, _ptr(x), x.shape[0], int(bool(weighted)), _ptr(out),
-                                 _stream()), "rte_direction_sum")
+    _check(lib.rte_direction_sum(P.handle, _ptr(x), _prec(x), x.shape[0], int(bool(weighted)),
+                                 _ptr(out), _stream()), "rte_direction_sum")
     return out
 
 
-def snapshot_columns(P, f_final, f_iters, window):
-    """[B * window, n_dir * N_DOF] columns f_b - f_b^(l), l = 0..window-1 (f^(0) = 0)."""
+def snapshot_columns(P, f_final, f_iters, window, out=None, dtype=None):
+    """[B * window, n_dir * N_DOF] columns f_b - f_b^(l), l = 0..window-1 (f^(0) = 0), written
+    into ``out`` (rows b * window + l) or a new FP64 array."""
     import torch
     L = P.n_dir * P.ndof
-    cols = torch.empty((P.B, window, L), dtype=torch.float64, device=f_final.device)
+    if out is None:
+        out = torch.empty((P.B * window, L), dtype=dtype or torch.float64, device=f_final.device)
+    assert out.shape == (P.B * window, L) and out.is_contiguous()
     for l in range(window):
         src = None if l == 0 else f_iters[l - 1]
-        _check(lib.rte_pod_snapshots(P.handle, _ptr(f_final), _ptr(src), _ptr(cols[:, l]),
-                                     window * L, _stream()), "rte_pod_snapshots")
-    return cols.view(P.B * window, L)
+        _check(lib.rte_pod_snapshots(P.handle, _ptr(f_final), _ptr(src), _ptr(out[l]), window * L,
+                                     _prec(out), _stream()), "rte_pod_snapshots")
+    return out
 
 
 def training_solves(P, window, eps_train, cg_rtol=1e-12, max_iter=500):
@@ -134,18 +155,40 @@ def training_solves(P, window, eps_train, cg_rtol=1e-12, max_iter=500):
 
 
 def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=None,
-                         cg_rtol=1e-12, classes=None) -> RomArrays:
+                         cg_rtol=1e-12, classes=None, snapshot_dtype="fp64", chunk=None,
+                         slice_cols=8, train_max_iter=500, log=None) -> RomArrays:
     """Correction ROM of rank r (or by eps_pod) from the training instances of ``train_plane``.
 
-    ``classes``: material class of every cell (default: the block map of the lattice); the
-    affine parameters are then (sigma_t per class, sigma_s per class).
+    ``classes``: material class of every cell (default: the material map of the description);
+    the affine parameters are then (sigma_t per class, sigma_s per class).
+    ``snapshot_dtype``: "fp64" or "fp32" storage of the snapshot columns.  ``chunk``: training
+    instances solved together (default: all).  ``slice_cols``: columns per D dF slice.
+    ``train_max_iter``: iteration limit of each training solve.
     """
     import torch
-    P = problems.plane_problem(train_plane)
-    f_final, f_iters, n_sweep = training_solves(P, window, eps_train, cg_rtol)
-    cols = snapshot_columns(P, f_final, f_iters, window)
-    del f_iters
-    G = gram(cols, cols)
+    say = log or (lambda *a: None)
+    n_inst = train_plane.B
+    chunk = chunk or n_inst
+    L = None
+    X = None
+    n_sweep = []
+    for c0 in range(0, n_inst, chunk):
+        sub = train_plane.subset(range(c0, min(n_inst, c0 + chunk)))
+        P = problems.plane_problem(sub)
+        if X is None:
+            L = P.n_dir * P.ndof
+            dt = torch.float32 if snapshot_dtype == "fp32" else torch.float64
+            X = torch.empty((n_inst * window, L), dtype=dt, device="cuda")
+        f_final, f_iters, ns = training_solves(P, window, eps_train, cg_rtol, train_max_iter)
+        snapshot_columns(P, f_final, f_iters, window, out=X[c0 * window:(c0 + sub.B) * window])
+        n_sweep.extend(int(v) for v in ns)
+        del f_final, f_iters, P
+        say(f"training instances {c0}..{c0 + sub.B - 1}: sweeps {[int(v) for v in ns]}")
+    torch.cuda.empty_cache()
+    ncol = X.shape[0]
+    Pm = problems.plane_problem(train_plane.instance(0))      # mesh and directions
+    scratch = torch.empty(4096 * ncol * ncol + 256, dtype=torch.float64, device="cuda")
+    G = gram(X, X, scratch=scratch)
     ev, V = sym_eig(G)
     ev_h = ev.cpu().numpy()
     order = np.argsort(-ev_h, kind="stable")
@@ -155,35 +198,39 @@ def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=N
         r = int(np.argmax(ratio >= 1.0 - eps_pod) + 1)
     r = min(r, int(np.sum(sv > sv[0] * 1e-13)))
     eps_eff = float(max(0.0, 1.0 - np.sum(sv[:r]) / np.sum(sv)))
-    Vh = V.cpu().numpy()[:, order[:r]] / sv[:r]
-    W = torch.as_tensor(np.ascontiguousarray(Vh), device="cuda")
-    dU = combine(cols, W)                         # [r, n_dir * N_DOF]
-    del cols
-    dU3 = dU.view(r, P.n_dir, P.ndof)
-    U_rho = direction_sum(P, dU3, True)           # [r, N_DOF]
-    U_iso = direction_sum(P, dU3, False)
-    DdU = apply_streaming(P, dU3)
-    A0 = gram(dU, DdU.view(r, -1))
+    Wh = V.cpu().numpy()[:, order[:r]] / sv[:r]                   # [ncol, r]
+    W = torch.as_tensor(np.ascontiguousarray(Wh), device="cuda")
+    X3 = X.view(ncol, Pm.n_dir, Pm.ndof)
+    U_rho = combine(direction_sum(Pm, X3, True), W)               # [r, N_DOF]
+    U_iso = combine(direction_sum(Pm, X3, False), W)
+    # dF^T D dF, a slice of columns of D dF at a time
+    GD = torch.empty((ncol, ncol), dtype=torch.float64, device="cuda")
+    for s0 in range(0, ncol, slice_cols):
+        s1 = min(ncol, s0 + slice_cols)
+        DX = apply_streaming(Pm, X3[s0:s1])
+        GD[:, s0:s1] = gram(X, DX.view(s1 - s0, L), scratch=scratch)
+        del DX
+    A0 = W.T @ GD @ W
     if classes is None:
         classes = train_plane.block.reshape(-1)
     classes = np.asarray(classes, dtype=np.int32).reshape(-1)
     ncls = int(classes.max()) + 1
     cls_d = torch.as_tensor(classes, device="cuda")
-    scratch = torch.empty(4096 * r * r + 256, dtype=torch.float64, device="cuda")
-    At = [gram(dU, dU, cls_d, 4, P.ncell, k, scratch) for k in range(ncls)]
-    As = [-gram(U_iso, U_rho, cls_d, 4, P.ncell, k, scratch) for k in range(ncls)]
+    At = [W.T @ gram(X, X, cls_d, 4, Pm.ncell, k, scratch) @ W for k in range(ncls)]
+    sc_r = torch.empty(4096 * r * r + 256, dtype=torch.float64, device="cuda")
+    As = [-gram(U_iso, U_rho, cls_d, 4, Pm.ncell, k, sc_r) for k in range(ncls)]
     A = torch.stack(At + As).cpu().numpy()
-    b_in = inflow_loads(P, dU3).cpu().numpy()
+    b_in = (inflow_loads(Pm, X3) @ W).cpu().numpy()
     torch.cuda.synchronize()
     return RomArrays(U_rho.T.contiguous().cpu().numpy(), U_iso.T.contiguous().cpu().numpy(),
                      A0.cpu().numpy(), A, sv, eps_eff, eps_train, np.asarray(n_sweep), b_in)
 
 
 def build_parametric_rom(train_plane, r=20, eps_train=1e-10, eps_pod=None, cg_rtol=1e-12,
-                         classes=None) -> RomArrays:
+                         classes=None, **kw) -> RomArrays:
     """Parametric ROM of Sec. 3.1 for the ROM initial guess (eq. (rom_parametric)): POD of the
     converged angular fluxes of the training parameters.  Those are the snapshot columns of the
     correction ROM with a one-iterate window (f - f^(0) = f), so the same construction applies;
     the reduced unit-inflow loads come with it."""
     return build_correction_rom(train_plane, r=r, window=1, eps_train=eps_train, eps_pod=eps_pod,
-                                cg_rtol=cg_rtol, classes=classes)
+                                cg_rtol=cg_rtol, classes=classes, **kw)

@@ -340,28 +340,43 @@ def c4_multiscale(n: int = 512, n_phi: int = 256, eps: float = 1e-3,
                   ss_thin: float = 1.0, sa_thin: float = 0.1, nb: int = 16) -> Plane:
     """16x16 checkerboard of (n/16)^2-cell blocks on [0,1]^2: thick blocks
     (bx+by even) sigma_s=1/eps, sigma_a=eps; thin blocks sigma_s=ss_thin,
-    sigma_a=sa_thin and G=1; vacuum inflow."""
-    block = _checker_blocks(n, n, nb, nb)
-    thick = np.array([((b % nb) + (b // nb)) % 2 == 0 for b in range(nb * nb)])
-    ss = np.where(thick, 1.0 / eps, ss_thin)
-    sa = np.where(thick, eps, sa_thin)
+    sigma_a=sa_thin and G=1; vacuum inflow.  The material map has two materials
+    (0 thick, 1 thin), so the affine parameters are the two materials' values."""
+    lattice = _checker_blocks(n, n, nb, nb)
+    material = (((lattice % nb) + (lattice // nb)) % 2).astype(np.int32)
+    ss = np.array([1.0 / eps, ss_thin])
+    sa = np.array([eps, sa_thin])
     bst = (ss + sa)[None, :]
     bss = ss[None, :]
-    Gb = np.where(thick, 0.0, 1.0)[None, :]
-    return Plane(n, n, 1.0, 1.0, _fill(block, bst), _fill(block, bss), _fill(block, Gb),
-                 np.zeros((1, 4)), block, bst, bss, ("cheb", n_phi),
+    Gb = np.array([[0.0, 1.0]])
+    return Plane(n, n, 1.0, 1.0, _fill(material, bst), _fill(material, bss), _fill(material, Gb),
+                 np.zeros((1, 4)), material, bst, bss, ("cheb", n_phi),
                  f"c4_multiscale_{n}x{n}_cheb{n_phi}")
 
 
-def c4_training(N: int = 64, n: int = 512, n_phi: int = 256) -> List[Plane]:
-    """Training draws: eps ~ logU[5e-4, 2e-3], thin sigma_s ~ U[0.8,1.2], thin sigma_a ~ U[0.08,0.12]."""
+def stack(planes: Sequence[Plane], name: str = None) -> Plane:
+    """One batch from instances that share mesh, directions and material map."""
+    p0 = planes[0]
+    for p in planes:
+        assert (p.nx, p.ny, p.Lx, p.Ly, p.quad) == (p0.nx, p0.ny, p0.Lx, p0.Ly, p0.quad)
+        assert np.array_equal(p.block, p0.block)
+    cat = lambda a: np.concatenate([getattr(p, a) for p in planes], axis=0)
+    seeds = tuple(s for p in planes for s in p.seeds)
+    return Plane(p0.nx, p0.ny, p0.Lx, p0.Ly, cat("sigma_t"), cat("sigma_s"), cat("G"), cat("g"),
+                 p0.block, cat("block_sigma_t"), cat("block_sigma_s"), p0.quad,
+                 name or p0.name, seeds)
+
+
+def c4_training(N: int = 64, n: int = 512, n_phi: int = 256) -> Plane:
+    """Training draws, one batch: eps ~ logU[5e-4, 2e-3], thin sigma_s ~ U[0.8,1.2],
+    thin sigma_a ~ U[0.08,0.12]."""
     out = []
     for i in range(N):
         rng = np.random.default_rng(50000 + i)
         eps = float(np.exp(rng.uniform(np.log(5e-4), np.log(2e-3))))
         out.append(c4_multiscale(n, n_phi, eps, float(rng.uniform(0.8, 1.2)),
                                  float(rng.uniform(0.08, 0.12))))
-    return out
+    return stack(out, name=f"c4_train_{n}x{n}_cheb{n_phi}")
 
 
 def random_plane(seed: int, nx: int = 13, ny: int = 9, n_phi: int = 8, B: int = 1,

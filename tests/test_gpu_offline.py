@@ -92,3 +92,31 @@ def test_offline_rom_matches_oracle_rom(R):
         d = discretize(test, b)
         ref = ro.correct(d, d.apply_Ss(rs[b] - rp[b]))
         assert rel_err(delta[b], ref) < 1e-7, rel_err(delta[b], ref)
+
+
+def test_offline_rom_fp32_snapshots_and_chunks(R):
+    """FP32 snapshot storage, training solved in chunks: the singular values and the ROMSA
+    correction stay within FP32 storage rounding of the oracle's."""
+    import torch
+    rte, problems, offline = R
+    train = W.c2_lattice([30000 + i for i in range(5)], n=12, n_phi=8)
+    say("offline rom build, fp32 snapshots, chunks of 2")
+    ra = offline.build_correction_rom(train, r=9, window=3, eps_train=1e-12, cg_rtol=1e-13,
+                                      snapshot_dtype="fp32", chunk=2, slice_cols=4)
+    discs = [discretize(train, b) for b in range(train.B)]
+    ro = orom.build_correction_rom(discs, orom.plane_affine(discs[0]), orom.plane_psi, window=3,
+                                   r=9, eps_train=1e-12)
+    assert rel_err(ra.sv[:6], ro.sv[:6]) < 1e-6
+    test = W.c2_lattice([20000 + i for i in range(3)], n=12, n_phi=8)
+    P = problems.plane_problem(test)
+    Rm = rte.Rom(P, ra.U_rho, ra.U_iso, ra.A0, ra.A, ra.eps_pod, ra.eps_train)
+    rng = np.random.default_rng(11)
+    rs = rng.uniform(0, 1, (test.B, P.ndof))
+    rp = rs + 1e-3 * rng.normal(size=rs.shape)
+    delta = torch.zeros((test.B, P.ndof), dtype=torch.float64, device="cuda")
+    rte.rom_correct(P, Rm, problems.plane_psi(test), dev(rs), dev(rp), delta)
+    delta = host(delta)
+    for b in range(test.B):
+        d = discretize(test, b)
+        ref = ro.correct(d, d.apply_Ss(rs[b] - rp[b]))
+        assert rel_err(delta[b], ref) < 1e-4, rel_err(delta[b], ref)
