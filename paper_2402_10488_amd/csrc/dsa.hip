@@ -167,8 +167,11 @@ struct MipArgs {
     const double *sigma_t, *sigma_s;
     // per-cell data of the operator, computed once per solve by mip_prepare_kernel:
     //   cf   [B][5][ncell]  sigma_a, Dx, Dy, kappa of the right face, kappa of the top face
-    //   binv [B][10][ncell] inverse of the diagonal 4x4 block (upper triangle, row-major)
-    const double *cf, *binv;
+    //   binv [B][10][ncell] inverse of the diagonal 4x4 block (upper triangle, row-major), FP32:
+    //        it is the block-Jacobi smoother of the preconditioner; one stored entry serves both
+    //        halves, so the rounded smoother stays exactly symmetric
+    const double *cf;
+    const float *binv;
 };
 constexpr int kCf = 5;
 constexpr int kBinv = 10;
@@ -305,7 +308,7 @@ __device__ __forceinline__ double cfv(const MipArgs &a, int b, int k, long long 
 // z = B^-1 r with the stored inverse of the diagonal block (symmetric by construction)
 __device__ __forceinline__ void binv_apply(const MipArgs &a, int b, long long cell, const double r[4],
                                            double z[4]) {
-    const double *q = a.binv + (size_t)b * kBinv * a.ncell + cell;
+    const float *q = a.binv + (size_t)b * kBinv * a.ncell + cell;
     const long long n = a.ncell;
     const double m00 = q[0], m01 = q[n], m02 = q[2 * n], m03 = q[3 * n], m11 = q[4 * n],
                  m12 = q[5 * n], m13 = q[6 * n], m22 = q[7 * n], m23 = q[8 * n], m33 = q[9 * n];
@@ -368,7 +371,7 @@ __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y
 }
 
 // per-cell operator data and the inverse of the diagonal block, once per solve
-__global__ void mip_prepare_kernel(MipArgs a, const int *mask, double *cf, double *binv) {
+__global__ void mip_prepare_kernel(MipArgs a, const int *mask, double *cf, float *binv) {
     const int b = blockIdx.y;
     if (mask && mask[b] != 1) return;
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -390,10 +393,10 @@ __global__ void mip_prepare_kernel(MipArgs a, const int *mask, double *cf, doubl
         e[k] = 1.0;
         spd4_solve(A, e, col[k]);        // column k of A^-1
     }
-    double *q = binv + (size_t)b * kBinv * a.ncell + cell;
+    float *q = binv + (size_t)b * kBinv * a.ncell + cell;
     int idx = 0;
     for (int r = 0; r < 4; ++r)
-        for (int k = r; k < 4; ++k) q[(idx++) * a.ncell] = col[k][r];
+        for (int k = r; k < 4; ++k) q[(idx++) * a.ncell] = (float)col[k][r];
 }
 
 // fixed-order block sum of two values; thread 0 returns the totals
@@ -699,15 +702,18 @@ __global__ void mg_restrict_dg_kernel(MipArgs a, const int *state, const double 
 
 // ---- vertex grids: 9-point stencils in planes, S[b][(dy+1)*3 + dx+1][v], and a tenth plane
 // S[b][9][v] = omega / diagonal (kStencilPlanes planes of nv values per instance)
-__device__ __forceinline__ const double *st_of(const double *S, int b, long long nv) {
+template <typename TS>
+__device__ __forceinline__ const TS *st_of(const TS *S, int b, long long nv) {
     return S + (size_t)b * kStencilPlanes * nv;
 }
-__device__ __forceinline__ double *st_of(double *S, int b, long long nv) {
+template <typename TS>
+__device__ __forceinline__ TS *st_of(TS *S, int b, long long nv) {
     return S + (size_t)b * kStencilPlanes * nv;
 }
-__device__ __forceinline__ double stencil_apply(const double *Sb, const double *x, VG g, int vx,
+template <typename TS>
+__device__ __forceinline__ double stencil_apply(const TS *Sb, const double *x, VG g, int vx,
                                                 int vy) {
-    const double *st = Sb + (long long)vy * g.nvx + vx;
+    const TS *st = Sb + (long long)vy * g.nvx + vx;
     double s = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int yy = vy + dy;
@@ -715,7 +721,7 @@ __device__ __forceinline__ double stencil_apply(const double *Sb, const double *
         for (int dx = -1; dx <= 1; ++dx) {
             const int xx = vx + dx;
             if (xx < 0 || xx >= g.nvx) continue;
-            s += st[((dy + 1) * 3 + dx + 1) * g.nv] * x[(long long)yy * g.nvx + xx];
+            s += (double)st[((dy + 1) * 3 + dx + 1) * g.nv] * x[(long long)yy * g.nvx + xx];
         }
     }
     return s;
@@ -723,14 +729,15 @@ __device__ __forceinline__ double stencil_apply(const double *Sb, const double *
 
 // mode 0: x_out = omega b / diag; 1: x_out = x_in + omega (b - S x_in)/diag; 2: out = b - S x_in;
 // 3: out = S x_in
-__global__ void mg_vertex_kernel(const int *state, VG g, const double *S, const double *x_in,
+template <typename TS>
+__global__ void mg_vertex_kernel(const int *state, VG g, const TS *S, const double *x_in,
                                  const double *bv, double *out, int mode) {
     const int b = blockIdx.y;
     if (state && state[b] != 1) return;
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
-    const double *Sb = st_of(S, b, g.nv);
+    const TS *Sb = st_of(S, b, g.nv);
     const double wd = Sb[9 * g.nv + v];
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
     double res;
@@ -827,6 +834,14 @@ __global__ void mg_wdiag_kernel(const int *state, VG g, double *S) {
     Sb[9 * g.nv + v] = kOmegaV / Sb[4 * g.nv + v];
 }
 
+// FP32 copy of an instance's stencil planes (the V-cycle's copy)
+__global__ void mg_round_kernel(const int *state, long long n, const double *x, float *y) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[(size_t)b * n + t] = (float)x[(size_t)b * n + t];
+}
+
 __global__ void mg_zero_kernel(const int *state, long long n, double *x) {
     const int b = blockIdx.y;
     if (state && state[b] != 1) return;
@@ -878,7 +893,7 @@ __global__ void __launch_bounds__(256) mg_coarse_invert_kernel(const int *mask, 
 
 // coarsest grid from zero: x = cinv b when the inverse exists, else nsweep damped Jacobi sweeps;
 // one workgroup per instance, vectors in LDS
-__global__ void __launch_bounds__(256) mg_coarse_kernel(const int *state, VG g, const double *S,
+__global__ void __launch_bounds__(256) mg_coarse_kernel(const int *state, VG g, const float *S,
                                                         const double *bv, double *x, int nsweep,
                                                         const double *cinv) {
     extern __shared__ double sh[];
@@ -896,8 +911,8 @@ __global__ void __launch_bounds__(256) mg_coarse_kernel(const int *state, VG g, 
         }
         return;
     }
-    const double *Sb = st_of(S, b, g.nv);
-    const double *wd = Sb + 9 * g.nv;
+    const float *Sb = st_of(S, b, g.nv);
+    const float *wd = Sb + 9 * g.nv;
     for (long long v = threadIdx.x; v < g.nv; v += blockDim.x) xa[v] = wd[v] * bv[o + v];
     __syncthreads();
     for (int k = 1; k < nsweep; ++k) {
@@ -949,17 +964,17 @@ __global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const i
 }
 
 // two damped Jacobi sweeps from zero: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - S x1)
-__global__ void mg_vpre_kernel(const int *state, VG g, const double *S, const double *bv, double *x2) {
+__global__ void mg_vpre_kernel(const int *state, VG g, const float *S, const double *bv, double *x2) {
     const int b = blockIdx.y;
     if (state[b] != 1) return;
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
-    const double *Sb = st_of(S, b, g.nv);
-    const double *wd = Sb + 9 * g.nv;
+    const float *Sb = st_of(S, b, g.nv);
+    const float *wd = Sb + 9 * g.nv;
     const double *bb = bv + o;
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-    const double *st = Sb + v;
+    const float *st = Sb + v;
     double sx1 = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int yy = vy + dy;
@@ -983,17 +998,17 @@ __device__ __forceinline__ double prolong_at(const double *c, VG gc, int x, int 
 }
 
 // x3 = x2 + P x_c, x4 = x3 + w D^-1 (b - S x3)
-__global__ void mg_vpost1_kernel(const int *state, VG g, const double *S, const double *bv,
+__global__ void mg_vpost1_kernel(const int *state, VG g, const float *S, const double *bv,
                                  const double *x2, VG gc, const double *xc, double *x4) {
     const int b = blockIdx.y;
     if (state[b] != 1) return;
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
-    const double *Sb = st_of(S, b, g.nv);
+    const float *Sb = st_of(S, b, g.nv);
     const double *cb = xc + (size_t)b * gc.nv;
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-    const double *st = Sb + v;
+    const float *st = Sb + v;
     double sx3 = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int yy = vy + dy;
@@ -1016,7 +1031,7 @@ struct SmallLevels {
     int n;
     int nvx[kMaxLevels], nvy[kMaxLevels];
     long long nv[kMaxLevels];
-    const double *S[kMaxLevels];
+    const float *S[kMaxLevels];
 };
 
 __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state, SmallLevels sl,
@@ -1041,8 +1056,8 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
     // down: two pre-smoothing sweeps, residual, restriction
     for (int l = 0; l < sl.n - 1; ++l) {
         const VG g = grid_of(l);
-        const double *S = S_of(l);
-        const double *wd = S + 9 * g.nv;
+        const float *S = S_of(l);
+        const float *wd = S + 9 * g.nv;
         for (long long v = t; v < g.nv; v += nt) xa[l][v] = wd[v] * bv[l][v];
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
@@ -1087,8 +1102,8 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
     } else {
         const int l = sl.n - 1;
         const VG g = grid_of(l);
-        const double *S = S_of(l);
-        const double *wd = S + 9 * g.nv;
+        const float *S = S_of(l);
+        const float *wd = S + 9 * g.nv;
         for (long long v = t; v < g.nv; v += nt) xb[l][v] = wd[v] * bv[l][v];
         __syncthreads();
         for (int k = 1; k < nsweep; ++k) {
@@ -1104,8 +1119,8 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
     // up: prolongation-correction, two post-smoothing sweeps (result in xb)
     for (int l = sl.n - 2; l >= 0; --l) {
         const VG g = grid_of(l), gc = grid_of(l + 1);
-        const double *S = S_of(l);
-        const double *wd = S + 9 * g.nv;
+        const float *S = S_of(l);
+        const float *wd = S + 9 * g.nv;
         for (long long v = t; v < g.nv; v += nt) {
             const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
             const int X0 = x / 2, Y0 = y / 2;
@@ -1220,7 +1235,7 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
             sl.nvx[k] = M.nvx;
             sl.nvy[k] = M.nvy;
             sl.nv[k] = M.nv;
-            sl.S[k] = M.S;
+            sl.S[k] = M.S32;
             lds += 4 * M.nv * (long long)sizeof(double);
         }
         hipLaunchKernelGGL(mg_small_vcycle_kernel, dim3(p->B), dim3(1024), (size_t)lds, s, c.state,
@@ -1230,13 +1245,13 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
     if (l == c.mg.L - 1) {
         if (L.nv <= 4096) {
             hipLaunchKernelGGL(mg_coarse_kernel, dim3(p->B), dim3(256), 2 * L.nv * sizeof(double), s,
-                               c.state, g, L.S, L.bv, L.xa, kCoarseSweeps, c.mg.cinv);
+                               c.state, g, L.S32, L.bv, L.xa, kCoarseSweeps, c.mg.cinv);
             return L.xa;
         }
-        hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xa, L.bv, L.xa, 0);
+        hipLaunchKernelGGL(mg_vertex_kernel<float>, grid, dim3(256), 0, s, c.state, g, L.S32, L.xa, L.bv, L.xa, 0);
         double *cur = L.xa, *nxt = L.xb;
         for (int k = 1; k < kCoarseSweeps; ++k) {
-            hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, cur, L.bv, nxt, 1);
+            hipLaunchKernelGGL(mg_vertex_kernel<float>, grid, dim3(256), 0, s, c.state, g, L.S32, cur, L.bv, nxt, 1);
             double *t = cur; cur = nxt; nxt = t;
         }
         return cur;
@@ -1245,17 +1260,17 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
     const VG gcv = vg_of(C);
     // two pre-smoothing sweeps from zero, residual, restriction
     if (kVertexSweeps == 2)
-        hipLaunchKernelGGL(mg_vpre_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.bv, L.xb);
+        hipLaunchKernelGGL(mg_vpre_kernel, grid, dim3(256), 0, s, c.state, g, L.S32, L.bv, L.xb);
     else
-        hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xb, L.bv, L.xb, 0);
-    hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xb, L.bv, L.rv, 2);
+        hipLaunchKernelGGL(mg_vertex_kernel<float>, grid, dim3(256), 0, s, c.state, g, L.S32, L.xb, L.bv, L.xb, 0);
+    hipLaunchKernelGGL(mg_vertex_kernel<float>, grid, dim3(256), 0, s, c.state, g, L.S32, L.xb, L.bv, L.rv, 2);
     hipLaunchKernelGGL(mg_vrestrict_kernel, dim3(blocks_for(C.nv, 256), p->B), dim3(256), 0, s,
                        c.state, g, L.rv, gcv, C.bv);
     double *xc = vcycle(p, c, l + 1, s);
     // coarse correction with the first post-smoothing sweep, then the second sweep
-    hipLaunchKernelGGL(mg_vpost1_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.bv, L.xb, gcv, xc, L.xa);
+    hipLaunchKernelGGL(mg_vpost1_kernel, grid, dim3(256), 0, s, c.state, g, L.S32, L.bv, L.xb, gcv, xc, L.xa);
     if (kVertexSweeps == 1) return L.xa;
-    hipLaunchKernelGGL(mg_vertex_kernel, grid, dim3(256), 0, s, c.state, g, L.S, L.xa, L.bv, L.xb, 1);
+    hipLaunchKernelGGL(mg_vertex_kernel<float>, grid, dim3(256), 0, s, c.state, g, L.S32, L.xa, L.bv, L.xb, 1);
     return L.xb;
 }
 }  // namespace
@@ -1284,12 +1299,14 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
                     const dim3 gfv(blocks_for(F.nv, 256), p->B);
                     hipLaunchKernelGGL(mg_colour_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.xa);
                     hipLaunchKernelGGL(mg_vprolong_kernel, gfv, dim3(256), 0, s, all, g, L.xa, gf, F.xa, 0);
-                    hipLaunchKernelGGL(mg_vertex_kernel, gfv, dim3(256), 0, s, all, gf, F.S, F.xa, F.bv, F.rv, 3);
+                    hipLaunchKernelGGL(mg_vertex_kernel<double>, gfv, dim3(256), 0, s, all, gf, F.S, F.xa, F.bv, F.rv, 3);
                     hipLaunchKernelGGL(mg_vrestrict_kernel, gv, dim3(256), 0, s, all, gf, F.rv, g, L.rv);
                 }
                 hipLaunchKernelGGL(mg_scatter_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.rv, L.S);
             }
         hipLaunchKernelGGL(mg_wdiag_kernel, gv, dim3(256), 0, s, all, g, L.S);
+        hipLaunchKernelGGL(mg_round_kernel, dim3(blocks_for(L.nv * kStencilPlanes, 256), p->B),
+                           dim3(256), 0, s, all, L.nv * kStencilPlanes, L.S, L.S32);
     }
     if (c.mg.cinv) {
         const MGLevel &C = c.mg.lv[c.mg.L - 1];

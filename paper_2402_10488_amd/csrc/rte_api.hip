@@ -90,7 +90,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
             L.cg.state = c.take<int>(B);
             L.cg.n_running = c.take<int>(1);
             L.cg.cf = c.take<double>(B * (size_t)p->ncell * 5);
-            L.cg.binv = c.take<double>(B * (size_t)p->ncell * 10);
+            L.cg.binv = c.take<float>(B * (size_t)p->ncell * 10);
             int nvx[kMaxLevels], nvy[kMaxLevels];
             L.cg.mg.L = p->dsa_mg ? mg_levels(p->nx, p->ny, nvx, nvy) : 0;
             for (int l = 0; l < L.cg.mg.L; ++l) {
@@ -99,6 +99,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
                 g.nvy = nvy[l];
                 g.nv = (long long)nvx[l] * nvy[l];
                 g.S = c.take<double>(B * (size_t)g.nv * kStencilPlanes);
+                g.S32 = c.take<float>(B * (size_t)g.nv * kStencilPlanes);
                 g.xa = c.take<double>(B * (size_t)g.nv);
                 g.xb = c.take<double>(B * (size_t)g.nv);
                 g.bv = c.take<double>(B * (size_t)g.nv);

@@ -236,7 +236,8 @@ constexpr int kMaxLevels = 12;
 struct MGLevel {
     int nvx, nvy;          // vertices per axis
     long long nv;
-    double *S;             // [B][nv][9] Galerkin stencils
+    double *S;             // [B][kStencilPlanes][nv] Galerkin stencils (built in FP64)
+    float *S32;            // the same rounded to FP32, read by the V-cycle of the CG
     double *xa, *xb, *bv, *rv;   // [B][nv]
 };
 struct MGSpace {
@@ -258,7 +259,8 @@ constexpr int kStencilPlanes = 10;
 struct CGSpace {
     MGSpace mg;
     double *cf;                        // [B][5][ncell] per-cell operator data (2D)
-    double *binv;                      // [B][10][ncell] inverse diagonal blocks (2D)
+    float *binv;                       // [B][10][ncell] inverse diagonal blocks (2D), FP32: the
+                                       // smoother's data (the operator stays FP64)
     double *x, *r, *z, *p0, *p1, *q;   // [B][ndof]
     double *part;                      // [B][5][nblk] partial sums
     double *scal;                      // [B][8] per-instance scalars
