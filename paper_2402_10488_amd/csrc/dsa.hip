@@ -22,6 +22,8 @@
 //     and the volume term 12 D/h^2 on the dofs of degree 1 in that direction, plus sigma_a.
 //     Per-instance scalars are re-derived by every block from fixed-order partial sums, so no
 //     grid-wide synchronization is needed and the result does not depend on block scheduling.
+#include <algorithm>
+
 #include "rte_internal.h"
 
 namespace rte {
@@ -1025,8 +1027,9 @@ __global__ void mg_vpost1_kernel(const int *state, VG g, const float *S, const d
 }
 
 
-// V-cycle over the small coarse levels ls..L-1 of one instance in one workgroup, all vectors in
-// LDS: same smoothing, restriction, prolongation and coarsest sweeps as the per-level kernels.
+// V-cycle over the small coarse levels ls..L-1 of one instance in one workgroup, all vectors and
+// the FP32 stencils in LDS (the stencils are copied in once, so no sweep waits on global
+// memory): same smoothing, restriction, prolongation and coarsest sweeps as the per-level kernels.
 struct SmallLevels {
     int n;
     int nvx[kMaxLevels], nvy[kMaxLevels];
@@ -1041,6 +1044,7 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
     const int b = blockIdx.x;
     if (state[b] != 1) return;
     double *xa[kMaxLevels], *xb[kMaxLevels], *bv[kMaxLevels], *rv[kMaxLevels];
+    float *Sl[kMaxLevels];
     double *q = sh;
     for (int l = 0; l < sl.n; ++l) {
         xa[l] = q; q += sl.nv[l];
@@ -1048,11 +1052,17 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
         bv[l] = q; q += sl.nv[l];
         rv[l] = q; q += sl.nv[l];
     }
+    float *fq = reinterpret_cast<float *>(q);
+    for (int l = 0; l < sl.n; ++l) { Sl[l] = fq; fq += kStencilPlanes * sl.nv[l]; }
     const int t = threadIdx.x, nt = blockDim.x;
+    for (int l = 0; l < sl.n; ++l) {
+        const float *src = st_of(sl.S[l], b, sl.nv[l]);
+        for (long long v = t; v < kStencilPlanes * sl.nv[l]; v += nt) Sl[l][v] = src[v];
+    }
     for (long long v = t; v < sl.nv[0]; v += nt) bv[0][v] = b_top[(size_t)b * sl.nv[0] + v];
     __syncthreads();
     auto grid_of = [&](int l) { VG g; g.nvx = sl.nvx[l]; g.nvy = sl.nvy[l]; g.nv = sl.nv[l]; return g; };
-    auto S_of = [&](int l) { return st_of(sl.S[l], b, sl.nv[l]); };
+    auto S_of = [&](int l) { return static_cast<const float *>(Sl[l]); };
     // down: two pre-smoothing sweeps, residual, restriction
     for (int l = 0; l < sl.n - 1; ++l) {
         const VG g = grid_of(l);
@@ -1206,15 +1216,19 @@ constexpr int kCoarseSweeps = 30;
 // separate launches (the LDS-resident small levels always use two)
 constexpr int kVertexSweeps = 1;
 
-constexpr long long kSmallLds = 64 * 1024;
+// LDS bytes per vertex of a level held by the small-level kernel: 4 FP64 vectors and the
+// FP32 stencil planes
+constexpr long long kSmallBytesPerVertex = 4 * 8 + kStencilPlanes * 4;
+constexpr long long kSmallLdsMax = 128 * 1024;
 
-// first level whose V-cycle tail (it and all coarser levels, 4 vectors each) fits in LDS
-int small_start(const CGSpace &c) {
+// first level whose V-cycle tail (it and all coarser levels) fits in the workgroup's LDS
+int small_start(const rte_problem *p, const CGSpace &c) {
+    const long long budget = std::min<long long>(kSmallLdsMax, p->lds_per_cu);
     long long tail = 0;
     int ls = c.mg.L;
     for (int l = c.mg.L - 1; l >= 0; --l) {
-        tail += 4 * c.mg.lv[l].nv * (long long)sizeof(double);
-        if (tail > kSmallLds) break;
+        tail += kSmallBytesPerVertex * c.mg.lv[l].nv;
+        if (tail > budget) break;
         ls = l;
     }
     return ls;
@@ -1225,7 +1239,7 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
     const MGLevel &L = c.mg.lv[l];
     const VG g = vg_of(L);
     const dim3 grid(blocks_for(L.nv, 256), p->B);
-    const int ls = small_start(c);
+    const int ls = small_start(p, c);
     if (l == ls && ls < c.mg.L) {
         SmallLevels sl;
         sl.n = c.mg.L - ls;
@@ -1236,8 +1250,11 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
             sl.nvy[k] = M.nvy;
             sl.nv[k] = M.nv;
             sl.S[k] = M.S32;
-            lds += 4 * M.nv * (long long)sizeof(double);
+            lds += kSmallBytesPerVertex * M.nv;
         }
+        if (lds > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(mg_small_vcycle_kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(mg_small_vcycle_kernel, dim3(p->B), dim3(1024), (size_t)lds, s, c.state,
                            sl, L.bv, L.xb, kCoarseSweeps, c.mg.cinv);
         return L.xb;
