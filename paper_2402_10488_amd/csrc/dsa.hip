@@ -1252,9 +1252,7 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
             sl.S[k] = M.S32;
             lds += kSmallBytesPerVertex * M.nv;
         }
-        if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(mg_small_vcycle_kernel),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+
         hipLaunchKernelGGL(mg_small_vcycle_kernel, dim3(p->B), dim3(1024), (size_t)lds, s, c.state,
                            sl, L.bv, L.xb, kCoarseSweeps, c.mg.cinv);
         return L.xb;
@@ -1325,6 +1323,11 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
         hipLaunchKernelGGL(mg_round_kernel, dim3(blocks_for(L.nv * kStencilPlanes, 256), p->B),
                            dim3(256), 0, s, all, L.nv * kStencilPlanes, L.S, L.S32);
     }
+    // LDS beyond 64 KiB for the small-level V-cycle (set here, outside any stream capture)
+    if (c.mg.L > 0)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(mg_small_vcycle_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)std::min<long long>(kSmallLdsMax, p->lds_per_cu));
     if (c.mg.cinv) {
         const MGLevel &C = c.mg.lv[c.mg.L - 1];
         const size_t lds = (2 * (size_t)C.nv * C.nv + C.nv) * sizeof(double);
@@ -1377,7 +1380,10 @@ hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double 
     hipLaunchKernelGGL(cg_setup_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, rho_star,
                        rho_prev, kind, want_kind, guess, c.q, c.x, c.r, c.z, c.part, c.state,
                        c.iters, c.n_running, bj);
-    if (bj == 2) return launch_mg_precond(p, c, 0, s);    // hierarchy built by launch_dsa_build
+    if (bj == 2) {                                        // hierarchy built by launch_dsa_build
+        if (c.precond[0]) return hipGraphLaunch(c.precond[0], s);
+        return launch_mg_precond(p, c, 0, s);
+    }
     return hipGetLastError();
 }
 
@@ -1393,8 +1399,38 @@ hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, d
     const int bj = c.mg.L == 0 ? 1 : 2;
     hipLaunchKernelGGL(cg_update_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, it, p_new,
                        c.q, c.x, c.r, c.z, c.part, c.state, bj);
-    if (bj == 2) return launch_mg_precond(p, c, it & 1, s);
+    if (bj == 2) {
+        if (c.precond[it & 1]) return hipGraphLaunch(c.precond[it & 1], s);
+        return launch_mg_precond(p, c, it & 1, s);
+    }
     return hipGetLastError();
+}
+
+void mg_precond_release(CGSpace &c) {
+    for (int k = 0; k < 2; ++k) {
+        if (c.precond[k]) (void)hipGraphExecDestroy(c.precond[k]);
+        c.precond[k] = nullptr;
+    }
+}
+
+void mg_precond_capture(const rte_problem *p, CGSpace &c) {
+    mg_precond_release(c);
+    if (c.mg.L == 0) return;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return;
+    bool ok = true;
+    for (int k = 0; k < 2 && ok; ++k) {
+        hipGraph_t g = nullptr;
+        ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        const hipError_t le = ok ? launch_mg_precond(p, c, k, cs) : hipSuccess;
+        const hipError_t ce = ok ? hipStreamEndCapture(cs, &g) : hipErrorUnknown;
+        ok = ok && le == hipSuccess && ce == hipSuccess && g;
+        if (ok) ok = hipGraphInstantiate(&c.precond[k], g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+    }
+    (void)hipStreamDestroy(cs);
+    if (!ok) mg_precond_release(c);
+    (void)hipGetLastError();
 }
 
 hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delta, int *iters_out,

@@ -79,6 +79,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     if (mode != RTE_SI) {
         if (p->dim == 2) {
             L.cg.nblk = (int)cg_blocks_per_instance(p);
+            L.cg.precond[0] = L.cg.precond[1] = nullptr;
             L.cg.x = c.take<double>(B * nd);
             L.cg.r = c.take<double>(B * nd);
             L.cg.z = c.take<double>(B * nd);
@@ -606,6 +607,16 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
 }
 
 
+// The multigrid preconditioner captured as graphs for the duration of one long call (released on
+// every return path); the kernels run one by one when capture is off or fails.
+struct PrecondGraphs {
+    CGSpace &c;
+    PrecondGraphs(const rte_problem *p, CGSpace &cg, bool on) : c(cg) {
+        if (on) mg_precond_capture(p, c);
+    }
+    ~PrecondGraphs() { mg_precond_release(c); }
+};
+
 // psi is checked only where the ROM correction runs (need_psi)
 int check_solve_args(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
                      bool need_psi, const rte_solve_opts *o) {
@@ -783,6 +794,7 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     HIPCHK(launch_zero_rows(L.delta, p->B, p->ndof, nullptr, s));
     HIPCHK(launch_zero_u64(L.cg_total, 1, s));
     if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
+    PrecondGraphs graphs(p, L.cg, mode != RTE_SI && p->dim == 2);
     HIPCHK(launch_source(p, rho, L.src, nullptr, o->precision == RTE_MIXED, s));
     int iterations = 0;
     bool cg_failed = false;
@@ -836,6 +848,7 @@ int rte_pgmres_solve(const rte_problem *p, const rte_krylov_opts *o, double *rho
     HIPCHK(launch_fill_int(G.n_sweep, p->B, 0, s));
     HIPCHK(launch_fill_int(G.n_iter, p->B, 0, s));
     if (o->precondition && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
+    PrecondGraphs graphs(p, L.cg, o->precondition && p->dim == 2);
     // b_bar: one sweep from zero with the source and the inflow; |M^-1 b_bar|
     HIPCHK(launch_zero_rows(G.u, p->B, p->ndof, nullptr, s));
     if ((rc = sweep(G.u, G.bbar, G.act, false))) return rc;

@@ -268,6 +268,9 @@ struct CGSpace {
     int *state;                        // [B] 0 idle, 1 running, 2 converged, 3 failed
     int *n_running;                    // [1]
     int nblk;                          // blocks per instance
+    // the multigrid preconditioner's launches captured as HIP graphs, one per parity slot of
+    // its (r, z) partial sums (null: launched one by one); valid for this carve-up only
+    hipGraphExec_t precond[2] = {nullptr, nullptr};
 };
 // CG start for the instances with kind == want_kind (all if kind is null); guess (nullable)
 // is the previous correction, used as a search direction for the initial iterate
@@ -282,6 +285,10 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
 hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot, hipStream_t s);
 hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, double rtol,
                                int maxit, hipStream_t s);
+// Captures the multigrid preconditioner (after launch_dsa_build) into c.precond; on any failure
+// c.precond stays null and the kernels are launched one by one.  mg_precond_release frees them.
+void mg_precond_capture(const rte_problem *p, CGSpace &c);
+void mg_precond_release(CGSpace &c);
 // delta = x for the instances of the call; iters_out[b] (nullable) and *total (nullable, summed)
 // receive the iteration counts
 hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delta, int *iters_out,
