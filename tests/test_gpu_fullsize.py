@@ -142,3 +142,50 @@ def test_c4_full_size_romsad(R, c4, c4_ref):
     assert (kinds == 2).any()
     assert err_romsad < 1e-5
     assert err_romsad <= err_dsa
+
+
+def test_c3_full_stream(R):
+    """The serving stream at full size: 10,000 seeded requests over the nine (mesh, directions)
+    keys, each key with its rank-20 correction ROM from 32 training solves, ROMSAD at 1e-6 in
+    mixed precision, all queued at once.  Every request converges; sampled requests equal
+    themselves served alone (bitwise: same pool capacity, hence the same schedule) and leave a
+    small residual ||rho - (L rho + b)|| / ||rho|| (one FP64 sweep)."""
+    import torch
+    rte, problems, offline = R
+    from paper_2402_10488_amd import quadrature, serving
+    keys = [(n, p) for n in (64, 128, 256) for p in (32, 64, 128)]
+    say("c3: nine key ROMs")
+    roms = {k: offline.build_correction_rom(W.c3_training(k[0], k[1], 32), r=20, window=3,
+                                            eps_train=1e-10) for k in keys}
+    torch.cuda.empty_cache()
+
+    def capacity(n, p):
+        return int(np.clip((256 << 20) // (n * n * p), 16, 64))
+
+    pools = {k: serving.KeyPool(k[0], k[1], capacity(*k), "romsad", roms[k], precision="mixed",
+                                eps=1e-6, theta=5, cg_rtol=1e-10, keep_rho=True) for k in keys}
+    say("c3: 10,000 requests")
+    reqs = [serving.lattice_request(i, 0.0, r.n, r.n_phi, r.seed)
+            for i, r in enumerate(W.c3_requests(10000))]
+    out = serving.Server(pools, 64 << 30).run(reqs)
+    summary = serving.latency_summary(out, max(r.finished for r in out))
+    say(f"  {summary}")
+    assert [r.rid for r in out] == list(range(10000))
+    assert all(r.status == 0 for r in out)
+    for rid in (0, 4321, 9999):
+        q = reqs[rid]
+        say(f"c3: request {rid} ({q.n}^2, {q.n_phi} directions) alone")
+        alone = serving.Server(pools, 64 << 30).run(
+            [serving.Request(0, 0.0, q.n, q.n_phi, q.sigma_t, q.sigma_s, q.G, q.g, q.psi)])[0]
+        assert alone.n_sweep == out[rid].n_sweep
+        assert np.array_equal(alone.rho, out[rid].rho)
+        vx, vy, w = quadrature.chebyshev_circle(q.n_phi)
+        dev = lambda a: torch.as_tensor(np.ascontiguousarray(a[None]), device="cuda")
+        Pi = rte.Problem(2, q.n, q.n, vx, w, dev(q.sigma_t), dev(q.sigma_s), dev(q.G), dev(q.g),
+                         dirs_y=vy)
+        rho = torch.as_tensor(out[rid].rho.reshape(1, -1), device="cuda")
+        rs = torch.empty_like(rho)
+        rte.sweep(Pi, rho, rho_star_out=rs, precision="fp64")
+        resid = float((rs - rho).abs().max() / rho.abs().max())
+        say(f"  residual {resid:.2e}")
+        assert resid < 1e-5
