@@ -48,6 +48,9 @@ struct Layout {
     int *flag;
     int *mask;              // [B] instances selected by rte_sisa_admit
     GmresSpace gm;          // DSA-preconditioned GMRES (rte_pgmres_solve)
+    // host-side: the CG iteration after which the previous diffusion solve of this call was
+    // first seen finished (0: none yet); where do_dsa first looks at the running count
+    mutable int cg_look;
 };
 
 int nparts_for(const rte_problem *p) { return sweep_nparts(p); }
@@ -589,16 +592,23 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
     }
     // the multigrid hierarchy depends only on the materials: built by the caller once
     HIPCHK(launch_cg_setup(p, L.cg, rho_star, rho_prev, kind, want, guess, rtol, s));
-    // the host looks at the number of running instances every few iterations only: a look
-    // drains the queue, and iterations launched after every instance stopped return at once
-    const int poll = 4;
+    // A look at the number of running instances drains the queue, and an iteration launched
+    // after every instance stopped still costs its launches (its kernels return at once).  So
+    // the host first looks after the iteration at which the previous solve of this call was seen
+    // finished (after iteration 8 for the first), then after every iteration.  When the first look
+    // already finds every instance stopped, the next solve looks one iteration earlier, so the
+    // look follows iteration counts that shrink as well as grow.
+    const int first = L.cg_look > 0 ? L.cg_look : 8;
     int running = 1;
     for (int it = 1; it <= maxit + 1; ++it) {
         HIPCHK(launch_cg_iteration(p, L.cg, it, rtol, maxit, s));
-        if ((it >= 8 && it % poll == 0) || it == maxit + 1) {
+        if (it >= first || it == maxit + 1) {
             HIPCHK(hipMemcpyAsync(&running, L.cg.n_running, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            if (running == 0) break;
+            if (running == 0) {
+                L.cg_look = it == first ? std::max(2, it - 1) : it;
+                break;
+            }
         }
     }
     if (failed) *failed = running != 0;

@@ -13,6 +13,10 @@ from tests.gpu_common import host, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
+# The diffusion CG's relative residual in the benchmark's launch configuration: each correction is
+# computed to 0.1% of its own size, far below what the SI stop test at 1e-6 can see.
+BENCH_CG_RTOL = 1e-3
+
 
 @pytest.fixture(scope="module")
 def R():
@@ -32,7 +36,8 @@ def c2(R):
     P = problems.plane_problem(plane)
     say(f"c2 full batch si_dsa mixed, tuning {P.tuning()}")
     rho = torch.zeros((P.B, P.ndof), dtype=torch.float64, device="cuda")
-    res = rte.sisa_solve(P, rho, mode="si_dsa", eps=1e-6, precision="mixed", cg_rtol=1e-10)
+    res = rte.sisa_solve(P, rho, mode="si_dsa", eps=1e-6, precision="mixed",
+                         cg_rtol=BENCH_CG_RTOL)
     return plane, P, host(rho), res
 
 
@@ -58,7 +63,7 @@ def test_c2_full_batch_romsad_reaches_the_same_solutions(R, c2):
     say("c2 full batch romsad mixed")
     rho = torch.zeros((P.B, P.ndof), dtype=torch.float64, device="cuda")
     res = rte.sisa_solve(P, rho, mode="romsad", rom=Rm, psi=problems.plane_psi(plane), eps=1e-6,
-                         theta=5, precision="mixed", cg_rtol=1e-10)
+                         theta=5, precision="mixed", cg_rtol=BENCH_CG_RTOL)
     assert res.status == 0
     rho = host(rho)
     err = np.abs(rho - rho_dsa).max(axis=1) / np.abs(rho_dsa).max(axis=1)
@@ -163,7 +168,8 @@ def test_c3_full_stream(R):
         return int(np.clip((256 << 20) // (n * n * p), 16, 64))
 
     pools = {k: serving.KeyPool(k[0], k[1], capacity(*k), "romsad", roms[k], precision="mixed",
-                                eps=1e-6, theta=5, cg_rtol=1e-10, keep_rho=True) for k in keys}
+                                eps=1e-6, theta=5, cg_rtol=BENCH_CG_RTOL, keep_rho=True)
+             for k in keys}
     say("c3: 10,000 requests")
     reqs = [serving.lattice_request(i, 0.0, r.n, r.n_phi, r.seed)
             for i, r in enumerate(W.c3_requests(10000))]
