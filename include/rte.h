@@ -377,6 +377,9 @@ int rte_profile_enable(int on);
 int rte_profile_read(int kernel, double *total_ms, long long *count);
 
 const char *rte_strerror(int status);
+/* The HIP runtime's description of the last HIP error for which a call made on this thread
+ * returned RTE_EDEVICE ("" if none).  The string is static; the library owns it. */
+const char *rte_last_device_error(void);
 
 #ifdef __cplusplus
 }

@@ -430,7 +430,7 @@ __device__ __forceinline__ double *slot(double *part, int b, int s, int nblk) {
 }
 
 // Warm start, first pass: with d the instance's previous correction, b = Sigma_s (rho* - rho_prev)
-// is stored in r and A d in q, and the partials of (d, b) and (d, A d) go to slots 2 and 3.
+// is stored in r and A d in q, and the partials of (d, b) and (d, A d) go to slots 2 and 1.
 __global__ void __launch_bounds__(kCgBlock) cg_warm_kernel(MipArgs a, const double *rho_star,
                                                            const double *rho_prev, const int *kind,
                                                            int want, const double *d, double *r,
@@ -458,14 +458,15 @@ __global__ void __launch_bounds__(kCgBlock) cg_warm_kernel(MipArgs a, const doub
     block_sum2(db, dad);
     if (threadIdx.x == 0) {
         slot(part, b, 2, a.nblk)[blockIdx.x] = db;
-        slot(part, b, 3, a.nblk)[blockIdx.x] = dad;
+        slot(part, b, 1, a.nblk)[blockIdx.x] = dad;
     }
 }
 
 // CG start.  Cold (d == nullptr): x = 0, r = b.  Warm: x = alpha d, r = b - alpha A d with
 // alpha = (d, b) / (d, A d), the multiple of d closest to the solution in the energy norm
 // (alpha = 0 when d = 0 or the quotient is not a positive finite number); r and A d come from
-// cg_warm_kernel.  The stopping test stays relative to ||b||.
+// cg_warm_kernel.  The stopping test stays relative to ||b||: slot 3 starts as the partials of
+// (b, b), so the test before the first iteration stops only a zero (or NaN) right-hand side.
 __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const double *rho_star,
                                                             const double *rho_prev, const int *kind,
                                                             int want, const double *d,
@@ -481,11 +482,11 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
     double alpha = 0.0;
     if (d) {
         const double db = sum_parts(slot(part, b, 2, a.nblk), a.nblk);
-        const double dad = sum_parts(slot(part, b, 3, a.nblk), a.nblk);
+        const double dad = sum_parts(slot(part, b, 1, a.nblk), a.nblk);
         alpha = dad > 0.0 ? db / dad : 0.0;
         if (!(fabs(alpha) < INFINITY)) alpha = 0.0;
     }
-    // slots 2 and 3 are only read here and slots 0 and 4 only written, so blocks need no order
+    // slots 1 and 2 are only read here and slots 0, 3 and 4 only written, so blocks need no order
     const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
     double rz = 0.0, bb = 0.0;
     if (cell < a.ncell) {
@@ -519,6 +520,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
     block_sum2(rz, bb);
     if (threadIdx.x == 0) {
         slot(part, b, 0, a.nblk)[blockIdx.x] = rz;
+        slot(part, b, 3, a.nblk)[blockIdx.x] = bb;
         slot(part, b, 4, a.nblk)[blockIdx.x] = bb;
         if (blockIdx.x == 0) {
             state[b] = 1;
@@ -584,7 +586,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, 
 __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, const double *p,
                                                              const double *q, double *x, double *r,
                                                              double *z, double *part,
-                                                             const int *state, int bj) {
+                                                             const int *state, int *iters, int bj) {
     const int b = blockIdx.y;
     if (state[b] != 1) return;
     const int nb = a.nblk;
@@ -616,6 +618,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, 
     if (threadIdx.x == 0) {
         if (bj == 1) slot(part, b, it & 1, nb)[blockIdx.x] = rz_new;
         slot(part, b, 3, nb)[blockIdx.x] = rr;
+        if (blockIdx.x == 0) iters[b] = it;   // updates done; final once the instance stops
     }
 }
 
@@ -629,8 +632,12 @@ __global__ void cg_finish_kernel(long long ndof, const double *x, double *delta,
     if (t == 0 && total) atomicAdd(total, (unsigned long long)iters[b]);
 }
 
-__global__ void zero_int_kernel(int *x) {
-    if (threadIdx.x == 0) *x = 0;
+// a CG call's start: no instance running yet, and the call's squared relative tolerance
+__global__ void cg_begin_kernel(int *n_running, double *tol2, double rtol2) {
+    if (threadIdx.x == 0) {
+        *n_running = 0;
+        *tol2 = rtol2;
+    }
 }
 
 // ------------------------------------------------------------------------- multigrid
@@ -675,11 +682,26 @@ __device__ __forceinline__ double pt_vertex(const double *rdg, int nx, int ny, i
     return s;
 }
 
-// t = r - A z
-__global__ void mg_resid_dg_kernel(MipArgs a, const int *state, const double *r, const double *z,
-                                   double *t) {
+// t = r - A z.  First the CG's convergence test on the (r, r) partials of the update just done
+// (the matvec kernel's test, on the same fixed-order sums): an instance that passes it stops
+// here, so it skips the rest of the preconditioner and the next iteration.  Every block reaches
+// the same decision; block 0 records it.
+__global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const double *z,
+                                   double *t, const double *part, const double *tol2,
+                                   int *n_running) {
     const int b = blockIdx.y;
     if (state[b] != 1) return;
+    {
+        const double bb = sum_parts(part + ((size_t)b * 5 + 4) * a.nblk, a.nblk);
+        const double rr = sum_parts(part + ((size_t)b * 5 + 3) * a.nblk, a.nblk);
+        if (!(rr > tol2[0] * bb)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                state[b] = rr == rr ? 2 : 3;
+                atomicSub(n_running, 1);
+            }
+            return;
+        }
+    }
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     const size_t base = (size_t)b * a.ncell;
@@ -1344,7 +1366,8 @@ hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot_id
     const VG g0 = vg_of(L0);
     // c.z holds the pre-smoothed z = omega D^-1 r (written with r by the CG kernels);
     // residual t = r - A z and the coarse right-hand side P^T t
-    hipLaunchKernelGGL(mg_resid_dg_kernel, gc, dim3(256), 0, s, a, c.state, c.r, c.z, c.mg.t);
+    hipLaunchKernelGGL(mg_resid_dg_kernel, gc, dim3(256), 0, s, a, c.state, c.r, c.z, c.mg.t,
+                       c.part, c.tol2, c.n_running);
     hipLaunchKernelGGL(mg_restrict_dg_kernel, dim3(blocks_for(L0.nv, 256), p->B), dim3(256), 0, s,
                        a, c.state, c.mg.t, g0, L0.bv);
     const double *x0 = vcycle(p, c, 0, s);
@@ -1371,7 +1394,8 @@ hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double 
                            const double *rho_prev, const int *kind, int want_kind,
                            const double *guess, double rtol, hipStream_t s) {
     const MipArgs a = mip_args(p, c);
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, c.n_running);
+    hipLaunchKernelGGL(cg_begin_kernel, dim3(1), dim3(64), 0, s, c.n_running, c.tol2,
+                       rtol * rtol);
     if (guess)
         hipLaunchKernelGGL(cg_warm_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, rho_star,
                            rho_prev, kind, want_kind, guess, c.r, c.q, c.part);
@@ -1398,7 +1422,7 @@ hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, d
                        c.n_running);
     const int bj = c.mg.L == 0 ? 1 : 2;
     hipLaunchKernelGGL(cg_update_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, it, p_new,
-                       c.q, c.x, c.r, c.z, c.part, c.state, bj);
+                       c.q, c.x, c.r, c.z, c.part, c.state, c.iters, bj);
     if (bj == 2) {
         if (c.precond[it & 1]) return hipGraphLaunch(c.precond[it & 1], s);
         return launch_mg_precond(p, c, it & 1, s);

@@ -37,7 +37,8 @@ __global__ void decide_kernel(int B, int max_iter, double eps, int relative, int
     else k = (l >= 1 && l <= theta && e >= eps_romsad) ? 2 : 1;    // Alg. 2
     kind[b] = k;
     kinds[(size_t)b * max_iter + (l - 1)] = k < 0 ? 0 : k;
-    if (k >= 0) atomicAdd(n_active, 1);
+    if (k >= 0) atomicAdd(&n_active[0], 1);
+    if (k > 0) atomicAdd(&n_active[k], 1);            // [1]: DSA this iteration, [2]: ROMSA
 }
 
 template <typename T>
@@ -114,7 +115,7 @@ __global__ void fill_int_kernel(int *x, long long n, int v) {
 
 hipError_t launch_decide(const rte_problem *p, const IterState &st, int max_iter, double eps,
                          int relative, int mode, int theta, double eps_romsad, hipStream_t s) {
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, st.n_active, 1ll, 0);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, st.n_active, 3ll, 0);
     hipLaunchKernelGGL(decide_kernel, dim3(blocks_for(p->B, 256)), dim3(256), 0, s, p->B,
                        max_iter, eps, relative, mode, theta, eps_romsad, st.maxd, st.maxr,
                        st.active, st.kind, st.n_sweep, st.status, st.change, st.kinds,

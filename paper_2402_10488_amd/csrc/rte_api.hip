@@ -75,7 +75,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     L.st.status = c.take<int>(B);
     L.st.change = c.take<double>(B * (size_t)std::max(max_iter, 1));
     L.st.kinds = c.take<int>(B * (size_t)std::max(max_iter, 1));
-    L.st.n_active = c.take<int>(1);
+    L.st.n_active = c.take<int>(3);
     L.cg_total = c.take<unsigned long long>(1);
     L.flag = c.take<int>(1);
     L.mask = c.take<int>(B);
@@ -93,6 +93,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
             L.cg.iters = c.take<int>(B);
             L.cg.state = c.take<int>(B);
             L.cg.n_running = c.take<int>(1);
+            L.cg.tol2 = c.take<double>(1);
             L.cg.cf = c.take<double>(B * (size_t)p->ncell * 5);
             L.cg.binv = c.take<float>(B * (size_t)p->ncell * 10);
             int nvx[kMaxLevels], nvy[kMaxLevels];
@@ -160,10 +161,18 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     return L;
 }
 
+// the last HIP error a call of this thread returned RTE_EDEVICE for (rte_last_device_error)
+thread_local hipError_t g_last_hip = hipSuccess;
+
+int device_error(hipError_t e) {
+    g_last_hip = e;
+    return RTE_EDEVICE;
+}
+
 #define HIPCHK(x)                                        \
     do {                                                 \
         hipError_t e_ = (x);                             \
-        if (e_ != hipSuccess) return RTE_EDEVICE;        \
+        if (e_ != hipSuccess) return device_error(e_);   \
     } while (0)
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -279,6 +288,10 @@ const char *rte_strerror(int s) {
     }
 }
 
+const char *rte_last_device_error(void) {
+    return g_last_hip == hipSuccess ? "" : hipGetErrorString(g_last_hip);
+}
+
 int rte_problem_create(const rte_problem_desc *d, rte_problem **out) {
     return rte_problem_create_tuned(d, 0, 0, out);
 }
@@ -349,11 +362,12 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
     p->dsa_mg = 1;
     {
         int dev = 0, ncu = 0, lds = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) {
             delete p;
-            return RTE_EDEVICE;
+            return device_error(e);
         }
         p->n_cu = ncu > 0 ? ncu : 1;
         p->lds_per_cu = lds > 0 ? lds : 64 * 1024;
@@ -392,29 +406,25 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
     }
     p->n_sorted = (int)table.size();
     choose_tuning(p, dg, wpb);
-    bool ok = true;
-    if (!table.empty()) {
-        ok = ok && hipMalloc(&p->d_dirs, table.size() * sizeof(DirEntry)) == hipSuccess;
-        ok = ok && hipMemcpy(p->d_dirs, table.data(), table.size() * sizeof(DirEntry),
-                             hipMemcpyHostToDevice) == hipSuccess;
-    }
-    ok = ok && hipMalloc(&p->d_w, sizeof(double) * p->n_dir) == hipSuccess;
-    ok = ok && hipMemcpy(p->d_w, p->w.data(), sizeof(double) * p->n_dir, hipMemcpyHostToDevice) == hipSuccess;
+    hipError_t e = hipSuccess;
+    auto upload = [&](auto **dst, const void *src, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc((void **)dst, bytes);
+        if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    if (!table.empty()) upload(&p->d_dirs, table.data(), table.size() * sizeof(DirEntry));
+    upload(&p->d_w, p->w.data(), sizeof(double) * p->n_dir);
     if (d->dim == 1) {
-        ok = ok && hipMalloc(&p->d_mu, sizeof(double) * p->n_dir) == hipSuccess;
-        ok = ok && hipMemcpy(p->d_mu, p->vx.data(), sizeof(double) * p->n_dir, hipMemcpyHostToDevice) == hipSuccess;
-        ok = ok && hipMalloc(&p->d_widths, sizeof(double) * p->nx) == hipSuccess;
-        ok = ok && hipMemcpy(p->d_widths, p->widths.data(), sizeof(double) * p->nx, hipMemcpyHostToDevice) == hipSuccess;
+        upload(&p->d_mu, p->vx.data(), sizeof(double) * p->n_dir);
+        upload(&p->d_widths, p->widths.data(), sizeof(double) * p->nx);
     }
     if (d->dim == 2) {
         std::vector<double> vxy(2 * (size_t)p->n_dir);
         for (int j = 0; j < p->n_dir; ++j) { vxy[j] = p->vx[j]; vxy[p->n_dir + j] = p->vy[j]; }
-        ok = ok && hipMalloc(&p->d_vxy, sizeof(double) * vxy.size()) == hipSuccess;
-        ok = ok && hipMemcpy(p->d_vxy, vxy.data(), sizeof(double) * vxy.size(), hipMemcpyHostToDevice) == hipSuccess;
+        upload(&p->d_vxy, vxy.data(), sizeof(double) * vxy.size());
     }
-    if (!ok) {
+    if (e != hipSuccess) {
         rte_problem_destroy(p);
-        return RTE_EDEVICE;
+        return device_error(e);
     }
     *out = p;
     return RTE_OK;
@@ -641,7 +651,10 @@ int check_solve_args(const rte_problem *p, rte_mode mode, const rte_rom *rom, co
 }
 
 // Up to n_max outer iterations (Alg. 1; Alg. 2 for ROMSAD) of every active instance; returns
-// early once no instance is active (looked at every poll_every iterations).
+// early once no instance is active.  SI looks at the active count every poll_every iterations.
+// The modes with a diffusion solve wait on the device inside every iteration anyway, so they
+// read the decision's counts at once: a correction no instance takes is not launched, and the
+// loop ends with the iteration in which the last instance stopped.
 int run_iterations(const rte_problem *p, const Layout &L, rte_mode mode, const rte_rom *rom,
                    const double *psi, const rte_solve_opts *o, double *rho, void *f_out, int n_max,
                    hipStream_t s, int *iterations, bool *cg_failed) {
@@ -650,30 +663,39 @@ int run_iterations(const rte_problem *p, const Layout &L, rte_mode mode, const r
     if (mode == RTE_ROMSAD && eps_romsad < 0.0)
         eps_romsad = 0.1 * std::max(rom->eps_train, rom->eps_pod);   // eq. (romsad_parameters)
     const int poll = o->poll_every > 0 ? o->poll_every : 1;
+    const bool corrected = mode != RTE_SI;
+    int counts[3] = {1, 1, 1};                // active, taking DSA, taking ROMSA
     for (int l = 1; l <= n_max; ++l) {
         int rc = do_sweep(p, L, L.src, f_out, L.rho_star, rho, L.st.active, 0, fp32, s);
         if (rc) return rc;
         HIPCHK(launch_decide(p, L.st, o->max_iter, o->eps, o->relative, (int)mode, o->theta,
                              eps_romsad, s));
-        const double *delta = nullptr;
-        if (mode == RTE_ROMSAD) {
+        if (corrected) {
+            HIPCHK(hipMemcpyAsync(counts, L.st.n_active, sizeof(counts), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        // L.delta holds every instance's previous correction (zero before its first)
+        const double *delta = corrected ? L.delta : nullptr;
+        // a singular reduced system sends its instance to DSA (kind 1) on the device, so after a
+        // ROM correction the diffusion solve runs whatever the count said
+        const bool rom_ran = mode == RTE_ROMSAD && counts[2] > 0;
+        if (rom_ran) {
             ProfScope ps(RTE_PROF_ROM, s);
             HIPCHK(launch_rom_correct(p, rom, psi, L.rho_star, rho, L.delta, L.rom_status,
                                       L.st.kind, 2, L.rom, fp32, s));
-            delta = L.delta;
         }
-        if (mode != RTE_SI) {
+        if (corrected && (counts[1] > 0 || rom_ran)) {
             int failed = 0;
-            // L.delta holds every instance's previous correction (zero before its first)
             rc = do_dsa(p, L, L.rho_star, rho, L.delta, L.st.kind, 1, o->cg_rtol, o->cg_maxit,
                         L.cg.iters, &failed, L.delta, s);
             if (rc) return rc;
             *cg_failed = *cg_failed || failed;
-            delta = L.delta;
         }
         HIPCHK(launch_update(p, L.st, L.rho_star, delta, rho, L.src, fp32, s));
         *iterations = l;
-        if (l % poll == 0 || l == n_max) {
+        if (corrected) {
+            if (counts[0] == 0) break;
+        } else if (l % poll == 0 || l == n_max) {
             int n_active = 0;
             HIPCHK(hipMemcpyAsync(&n_active, L.st.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));

@@ -267,6 +267,7 @@ struct CGSpace {
     int *iters;                        // [B]
     int *state;                        // [B] 0 idle, 1 running, 2 converged, 3 failed
     int *n_running;                    // [1]
+    double *tol2;                      // [1] the call's squared relative tolerance
     int nblk;                          // blocks per instance
     // the multigrid preconditioner's launches captured as HIP graphs, one per parity slot of
     // its (r, z) partial sums (null: launched one by one); valid for this carve-up only
@@ -363,7 +364,8 @@ struct IterState {
     int *status;                       // [B]
     double *change;                    // [B][max_iter]
     int *kinds;                        // [B][max_iter]
-    int *n_active;                     // [1]
+    int *n_active;                     // [3] after a decision: instances still iterating,
+                                       // taking DSA, taking ROMSA
 };
 // stop test and choice of correction after every active instance's latest sweep
 hipError_t launch_decide(const rte_problem *p, const IterState &st, int max_iter, double eps,

@@ -25,7 +25,10 @@ PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 
 class RteError(RuntimeError):
     def __init__(self, status, what):
-        super().__init__(f"{what}: {strerror(status)} ({status})")
+        detail = ""
+        if status == RTE_EDEVICE:
+            detail = lib.rte_last_device_error().decode()
+        super().__init__(f"{what}: {strerror(status)} ({status})" + (f": {detail}" if detail else ""))
         self.status = status
 
 
@@ -80,10 +83,16 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_profile_read", "rte_problem_dsa_multigrid", "rte_pod_snapshots", "rte_gram",
             "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum",
             "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
-            "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve", "rte_f_natural"]
+            "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve", "rte_f_natural",
+            "rte_last_device_error"]
 
 
 def _load():
+    # The library takes torch's device pointers and streams, so it must bind to the HIP runtime
+    # torch carries.  torch's copy of libamdhip64 has the same soname as the system one the
+    # library was linked against: loading torch first makes the library's dependency resolve to
+    # torch's copy.  Loaded the other way round, the process would hold two HIP runtimes.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2402_10488_amd/build.py "
                           "(there is no CPU fallback)")
@@ -94,6 +103,8 @@ def _load():
     P = ctypes.c_void_p
     L.rte_strerror.restype = ctypes.c_char_p
     L.rte_strerror.argtypes = [ctypes.c_int]
+    L.rte_last_device_error.restype = ctypes.c_char_p
+    L.rte_last_device_error.argtypes = []
     L.rte_problem_create_tuned.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(P)]
     L.rte_problem_destroy.argtypes = [P]

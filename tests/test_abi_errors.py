@@ -99,3 +99,12 @@ def test_status_strings_and_profile_ids():
         assert lib.rte_strerror(code)
     t, c = ctypes.c_double(), ctypes.c_longlong()
     assert lib.rte_profile_read(99, ctypes.byref(t), ctypes.byref(c)) == rte.RTE_EINVAL
+
+
+def test_last_device_error_is_empty_when_no_hip_call_failed():
+    """Argument errors are not device errors: after any number of rejected calls the HIP error
+    detail stays empty (the binding appends it to RTE_EDEVICE messages only)."""
+    rc, _ = _create(nx=0)
+    assert rc == rte.RTE_EINVAL
+    assert lib.rte_last_device_error() == b""
+    assert "HIP" not in str(rte.RteError(rte.RTE_EINVAL, "x"))

@@ -29,6 +29,9 @@ def lib():
     if not os.path.exists(LIB):
         from paper_2402_10488_amd import build
         build.build()
+    # torch first, as the binding does: the library then binds to torch's HIP runtime, and a
+    # later GPU test in this process does not find a second runtime loaded
+    import torch  # noqa: F401
     return ctypes.CDLL(LIB)
 
 
@@ -62,3 +65,19 @@ def test_binding_mirrors_the_abi():
     from paper_2402_10488_amd import rte
     names = declared_functions()
     assert set(rte.EXPORTED) <= set(names)
+
+
+def test_binding_binds_the_library_to_one_hip_runtime():
+    """torch carries its own libamdhip64 with the same soname as the system one the library links
+    against.  Importing the binding (in a fresh process) must leave exactly one HIP runtime and one
+    HSA runtime mapped: two would not share devices, memory or streams."""
+    code = ("import re\n"
+            "from paper_2402_10488_amd import rte\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "libs = sorted(set(l.split()[-1] for l in maps.splitlines()\n"
+            "                  if re.search(r'lib(amdhip64|hsa-runtime64)', l)))\n"
+            "print('\\n'.join(libs))\n")
+    out = subprocess.run(["python3", "-c", code], capture_output=True, text=True, check=True,
+                         cwd=ROOT).stdout.split()
+    assert sum("amdhip64" in l for l in out) == 1, out
+    assert sum("hsa-runtime64" in l for l in out) == 1, out
