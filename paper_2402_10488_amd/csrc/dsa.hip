@@ -793,23 +793,6 @@ __global__ void mg_vrestrict_kernel(const int *state, VG gf, const double *rf, V
     bc[(size_t)b * gc.nv + v] = s;
 }
 
-// fine x_f (+)= P x_c (bilinear); add = 0 overwrites
-__global__ void mg_vprolong_kernel(const int *state, VG gc, const double *xc, VG gf, double *xf,
-                                   int add) {
-    const int b = blockIdx.y;
-    if (state && state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= gf.nv) return;
-    const int x = (int)(v % gf.nvx), y = (int)(v / gf.nvx);
-    const double *c = xc + (size_t)b * gc.nv;
-    const int X0 = x / 2, Y0 = y / 2;
-    const int X1 = (x & 1) ? X0 + 1 : X0, Y1 = (y & 1) ? Y0 + 1 : Y0;
-    const double val = 0.25 * (c[(long long)Y0 * gc.nvx + X0] + c[(long long)Y0 * gc.nvx + X1] +
-                               c[(long long)Y1 * gc.nvx + X0] + c[(long long)Y1 * gc.nvx + X1]);
-    const size_t o = (size_t)b * gf.nv + v;
-    xf[o] = add ? xf[o] + val : val;
-}
-
 // probing: e = indicator of the vertices of colour (cx, cy) (coordinates mod 3)
 __global__ void mg_colour_kernel(const int *state, VG g, int cx, int cy, double *e) {
     const int b = blockIdx.y;
@@ -846,6 +829,55 @@ __global__ void mg_scatter_kernel(const int *state, VG g, int cx, int cy, const 
     const int dx = mx == 2 ? -1 : mx, dy = my == 2 ? -1 : my;
     if (x + dx < 0 || x + dx >= g.nvx || y + dy < 0 || y + dy >= g.nvy) return;
     st_of(S, b, g.nv)[((dy + 1) * 3 + dx + 1) * g.nv + v] = z[(size_t)b * g.nv + v];
+}
+
+// Galerkin operator of a coarse vertex level, S_c = R S_f P with the bilinear prolongation P
+// (weight 1 at the coincident fine vertex, 1/2 per axis at odd fine coordinates) and R = P^T.
+// One thread per coarse vertex I: the fine vertices i of R's row, their stencil entries
+// S_f[i][j], and the coarse parents J of every j, all within one coarse neighbour of I.
+__device__ __forceinline__ double p_weight(int fine, int coarse) {
+    const int d = fine - 2 * coarse;
+    return d == 0 ? 1.0 : ((d == 1 || d == -1) ? 0.5 : 0.0);
+}
+
+__global__ void mg_galerkin_kernel(const int *state, VG gf, const double *Sf, VG gc, double *Sc) {
+    const int b = blockIdx.y;
+    if (state && state[b] != 1) return;
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= gc.nv) return;
+    const int X = (int)(v % gc.nvx), Y = (int)(v / gc.nvx);
+    const double *Sb = st_of(Sf, b, gf.nv);
+    double acc[9];
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int iy = 2 * Y + dy;
+        if (iy < 0 || iy >= gf.nvy) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int ix = 2 * X + dx;
+            if (ix < 0 || ix >= gf.nvx) continue;
+            const double r = p_weight(ix, X) * p_weight(iy, Y);
+            const long long i = (long long)iy * gf.nvx + ix;
+            for (int ey = -1; ey <= 1; ++ey) {
+                const int jy = iy + ey;
+                if (jy < 0 || jy >= gf.nvy) continue;
+                for (int ex = -1; ex <= 1; ++ex) {
+                    const int jx = ix + ex;
+                    if (jx < 0 || jx >= gf.nvx) continue;
+                    const double rs = r * Sb[((ey + 1) * 3 + ex + 1) * gf.nv + i];
+                    // coarse parents of j: jx / 2 (and jx / 2 + 1 when jx is odd), the same in y
+                    const int jx0 = jx >> 1, jy0 = jy >> 1;
+                    for (int py = 0; py <= (jy & 1); ++py)
+                        for (int px = 0; px <= (jx & 1); ++px) {
+                            const int JX = jx0 + px, JY = jy0 + py;
+                            acc[(JY - Y + 1) * 3 + (JX - X + 1)] +=
+                                rs * p_weight(jx, JX) * p_weight(jy, JY);
+                        }
+                }
+            }
+        }
+    }
+    double *Cb = st_of(Sc, b, gc.nv);
+    for (int k = 0; k < 9; ++k) Cb[(long long)k * gc.nv + v] = acc[k];
 }
 
 // omega / diagonal plane of the smoother
@@ -1322,25 +1354,22 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
         const MGLevel &L = c.mg.lv[l];
         const VG g = vg_of(L);
         const dim3 gv(blocks_for(L.nv, 256), p->B);
-        hipLaunchKernelGGL(mg_zero_kernel, dim3(blocks_for(L.nv * kStencilPlanes, 256), p->B),
-                           dim3(256), 0, s, all, L.nv * kStencilPlanes, L.S);
-        for (int cy = 0; cy < 3; ++cy)
-            for (int cx = 0; cx < 3; ++cx) {
-                if (l == 0) {
+        if (l == 0) {
+            // the DG operator seen through P: probed with the 9 vertex colours (coordinates
+            // mod 3), whose 3 x 3 neighbourhoods hold one vertex of each colour
+            hipLaunchKernelGGL(mg_zero_kernel, dim3(blocks_for(L.nv * kStencilPlanes, 256), p->B),
+                               dim3(256), 0, s, all, L.nv * kStencilPlanes, L.S);
+            for (int cy = 0; cy < 3; ++cy)
+                for (int cx = 0; cx < 3; ++cx) {
                     hipLaunchKernelGGL(mg_colour_kernel, gv, dim3(256), 0, s, all, g, cx, cy, c.mg.e);
                     hipLaunchKernelGGL(mg_probe_dg_kernel, gc, dim3(256), 0, s, a, all, c.mg.e, g, c.mg.t);
                     hipLaunchKernelGGL(mg_restrict_dg_kernel, gv, dim3(256), 0, s, a, all, c.mg.t, g, L.rv);
-                } else {
-                    const MGLevel &F = c.mg.lv[l - 1];
-                    const VG gf = vg_of(F);
-                    const dim3 gfv(blocks_for(F.nv, 256), p->B);
-                    hipLaunchKernelGGL(mg_colour_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.xa);
-                    hipLaunchKernelGGL(mg_vprolong_kernel, gfv, dim3(256), 0, s, all, g, L.xa, gf, F.xa, 0);
-                    hipLaunchKernelGGL(mg_vertex_kernel<double>, gfv, dim3(256), 0, s, all, gf, F.S, F.xa, F.bv, F.rv, 3);
-                    hipLaunchKernelGGL(mg_vrestrict_kernel, gv, dim3(256), 0, s, all, gf, F.rv, g, L.rv);
+                    hipLaunchKernelGGL(mg_scatter_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.rv, L.S);
                 }
-                hipLaunchKernelGGL(mg_scatter_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.rv, L.S);
-            }
+        } else {
+            const MGLevel &F = c.mg.lv[l - 1];
+            hipLaunchKernelGGL(mg_galerkin_kernel, gv, dim3(256), 0, s, all, vg_of(F), F.S, g, L.S);
+        }
         hipLaunchKernelGGL(mg_wdiag_kernel, gv, dim3(256), 0, s, all, g, L.S);
         hipLaunchKernelGGL(mg_round_kernel, dim3(blocks_for(L.nv * kStencilPlanes, 256), p->B),
                            dim3(256), 0, s, all, L.nv * kStencilPlanes, L.S, L.S32);

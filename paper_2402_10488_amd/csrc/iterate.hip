@@ -70,6 +70,51 @@ __global__ void update_kernel(int dim, long long ncell, int K, int B, int nx, in
     write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, v, sigma_t[t], src);
 }
 
+// 2D update on 16 x 16 cell tiles (grid: tiles x instances): rho = rho* + delta and the source
+// part of the sweep input.  sigma_t in the sweep input does not change between iterations (the
+// solve's start writes it), so it is not rewritten.  A tile's cells on one diagonal sit on
+// consecutive positions of either diagonal layout, so a workgroup's source stores fill whole
+// cache lines.
+template <typename T>
+__global__ void __launch_bounds__(256) update2d_kernel(long long ncell, int B, int nx, int ny,
+                                                       int tiles_x, const int *kind, int *active,
+                                                       const double *rho_star, const double *delta,
+                                                       double *rho, const double *sigma_s,
+                                                       const double *G, double ghost, T *src) {
+    const int b = blockIdx.y;
+    const int k = kind[b];
+    if (k == -3) return;                              // finished earlier
+    const int x = (int)(blockIdx.x % tiles_x) * 16 + (int)(threadIdx.x & 15);
+    const int y = (int)(blockIdx.x / tiles_x) * 16 + (int)(threadIdx.x >> 4);
+    if (x >= nx || y >= ny) return;
+    const long long cell = (long long)y * nx + x;
+    const long long t = (long long)b * ncell + cell;
+    const double4 rs = *reinterpret_cast<const double4 *>(rho_star + t * 4);
+    double4 r = rs;
+    if (k < 0) {                                      // converged / stopped: keep rho^(l,*)
+        *reinterpret_cast<double4 *>(rho + t * 4) = r;
+        if (cell == 0) active[b] = 0;
+        return;
+    }
+    if (k > 0 && delta) {
+        const double4 dv = *reinterpret_cast<const double4 *>(delta + t * 4);
+        r.x += dv.x; r.y += dv.y; r.z += dv.z; r.w += dv.w;
+    }
+    *reinterpret_cast<double4 *>(rho + t * 4) = r;
+    const double ss = sigma_s[t];
+    const double g0 = G[t] * ghost;
+    Vec4<T> o;
+    o.x = (T)(ss * r.x + g0);
+    o.y = (T)(ss * r.y + 0.0);
+    o.z = (T)(ss * r.z + 0.0);
+    o.w = (T)(ss * r.w + 0.0);
+    const size_t nb4 = (size_t)B * ncell * 4;
+    const size_t pa = (size_t)b * ncell + pos_a(nx, ny, x, y);
+    const size_t pb = (size_t)b * ncell + pos_b(nx, ny, x, y);
+    *reinterpret_cast<Vec4<T> *>(src + pa * 4) = o;
+    *reinterpret_cast<Vec4<T> *>(src + nb4 + pb * 4) = o;
+}
+
 // start (run = 1) or idle (run = 0) the instances selected by mask (all when mask is null)
 __global__ void init_state_kernel(int B, int max_iter, const int *mask, int run,
                                   unsigned long long *maxd, unsigned long long *maxr, int *active,
@@ -128,6 +173,19 @@ hipError_t launch_update(const rte_problem *p, const IterState &st, const double
     const long long n = (long long)p->B * p->ncell;
     const double ghost = sqrt(p->hx * p->hy);
     const double *cw = p->dim == 1 ? p->d_widths : nullptr;
+    if (p->dim == 2) {
+        const int tx = (p->nx + 15) / 16, ty = (p->ny + 15) / 16;
+        const dim3 grid((unsigned)(tx * ty), p->B);
+        if (fp32)
+            hipLaunchKernelGGL(update2d_kernel<float>, grid, dim3(256), 0, s, p->ncell, p->B,
+                               p->nx, p->ny, tx, st.kind, st.active, rho_star, delta, rho,
+                               p->sigma_s, p->source, ghost, (float *)src);
+        else
+            hipLaunchKernelGGL(update2d_kernel<double>, grid, dim3(256), 0, s, p->ncell, p->B,
+                               p->nx, p->ny, tx, st.kind, st.active, rho_star, delta, rho,
+                               p->sigma_s, p->source, ghost, (double *)src);
+        return hipGetLastError();
+    }
     if (fp32)
         hipLaunchKernelGGL(update_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            p->dim, p->ncell, p->K, p->B, p->nx, p->ny, st.kind, st.active,

@@ -454,22 +454,29 @@ __device__ __forceinline__ void max_update(unsigned long long *dst, double v) {
 }
 
 // rho* of one cell (4 dofs) = sum of the partial densities of every quadrant block, each read
-// from its quadrant's diagonal layout, in fixed order
+// from its quadrant's diagonal layout, in fixed order.  Workgroups cover 16 x 16 cell tiles: a
+// tile's cells on one diagonal sit on consecutive positions of either layout, so the reads of a
+// workgroup fill whole cache lines.
 struct ReduceArgs {
     long long ncell;
     int B, nx, ny, nparts;
     int gq[4];
 };
 
-__global__ void reduce_parts_kernel(ReduceArgs a, const double *partial, double *rho_star,
-                                    const double *rho_prev, unsigned long long *maxd,
-                                    unsigned long long *maxr, const int *active) {
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) reduce_parts_kernel(ReduceArgs a, int tiles_x,
+                                                           const double *partial,
+                                                           double *rho_star,
+                                                           const double *rho_prev,
+                                                           unsigned long long *maxd,
+                                                           unsigned long long *maxr,
+                                                           const int *active) {
     const int b = (int)(blockIdx.y);
+    const int x = (int)(blockIdx.x % tiles_x) * 16 + (int)(threadIdx.x & 15);
+    const int y = (int)(blockIdx.x / tiles_x) * 16 + (int)(threadIdx.x >> 4);
+    const long long cell = (long long)y * a.nx + x;
     double d = 0.0, m = 0.0;
-    const bool live = cell < a.ncell && (!active || active[b] != 0);
+    const bool live = x < a.nx && y < a.ny && (!active || active[b] != 0);
     if (live) {
-        const int x = (int)(cell % a.nx), y = (int)(cell / a.nx);
         const size_t pa = (size_t)pos_a(a.nx, a.ny, x, y);
         const size_t pb = (size_t)pos_b(a.nx, a.ny, x, y);
         const double *base = partial + (size_t)b * a.nparts * a.ncell * 4;
@@ -657,9 +664,10 @@ hipError_t launch_reduce_parts(const rte_problem *p, const double *partial, int 
     a.nparts = nparts;
     const int W = p->tune.wpb, DG = p->tune.dg;
     for (int q = 0; q < 4; ++q) a.gq[q] = ((p->quad.count[q] + DG - 1) / DG + W - 1) / W;
-    dim3 grid(blocks_for(p->ncell, 256), p->B);
-    hipLaunchKernelGGL(reduce_parts_kernel, grid, dim3(256), 0, s, a, partial, rho_star, rho_prev,
-                       maxd, maxr, active);
+    const int tx = (p->nx + 15) / 16, ty = (p->ny + 15) / 16;
+    dim3 grid((unsigned)(tx * ty), p->B);
+    hipLaunchKernelGGL(reduce_parts_kernel, grid, dim3(256), 0, s, a, tx, partial, rho_star,
+                       rho_prev, maxd, maxr, active);
     return hipGetLastError();
 }
 
