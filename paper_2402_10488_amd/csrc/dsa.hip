@@ -374,9 +374,10 @@ __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y
 
 // per-cell operator data and the inverse of the diagonal block, once per solve
 __global__ void mip_prepare_kernel(MipArgs a, const int *mask, double *cf, float *binv) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (mask && mask[b] != 1) return;
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long cell = (long long)blk.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
     const CellCoef cc = coef_at(a, b, cell);
@@ -435,9 +436,10 @@ __global__ void __launch_bounds__(kCgBlock) cg_warm_kernel(MipArgs a, const doub
                                                            const double *rho_prev, const int *kind,
                                                            int want, const double *d, double *r,
                                                            double *q, double *part) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (kind && kind[b] != want) return;
-    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    const long long cell = (long long)blk.x * kCgBlock + threadIdx.x;
     double db = 0.0, dad = 0.0;
     if (cell < a.ncell) {
         const size_t base = (size_t)b * a.ncell;
@@ -457,8 +459,8 @@ __global__ void __launch_bounds__(kCgBlock) cg_warm_kernel(MipArgs a, const doub
     }
     block_sum2(db, dad);
     if (threadIdx.x == 0) {
-        slot(part, b, 2, a.nblk)[blockIdx.x] = db;
-        slot(part, b, 1, a.nblk)[blockIdx.x] = dad;
+        slot(part, b, 2, a.nblk)[blk.x] = db;
+        slot(part, b, 1, a.nblk)[blk.x] = dad;
     }
 }
 
@@ -473,10 +475,11 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
                                                             const double *q, double *x, double *r,
                                                             double *z, double *part, int *state,
                                                             int *iters, int *n_running, int bj) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     const bool mine = !kind || kind[b] == want;
     if (!mine) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) state[b] = 0;
+        if (blk.x == 0 && threadIdx.x == 0) state[b] = 0;
         return;
     }
     double alpha = 0.0;
@@ -487,7 +490,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
         if (!(fabs(alpha) < INFINITY)) alpha = 0.0;
     }
     // slots 1 and 2 are only read here and slots 0, 3 and 4 only written, so blocks need no order
-    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    const long long cell = (long long)blk.x * kCgBlock + threadIdx.x;
     double rz = 0.0, bb = 0.0;
     if (cell < a.ncell) {
         const long long gi = (long long)b * a.ncell + cell;
@@ -519,10 +522,10 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
     }
     block_sum2(rz, bb);
     if (threadIdx.x == 0) {
-        slot(part, b, 0, a.nblk)[blockIdx.x] = rz;
-        slot(part, b, 3, a.nblk)[blockIdx.x] = bb;
-        slot(part, b, 4, a.nblk)[blockIdx.x] = bb;
-        if (blockIdx.x == 0) {
+        slot(part, b, 0, a.nblk)[blk.x] = rz;
+        slot(part, b, 3, a.nblk)[blk.x] = bb;
+        slot(part, b, 4, a.nblk)[blk.x] = bb;
+        if (blk.x == 0) {
             state[b] = 1;
             iters[b] = 0;
             atomicAdd(n_running, 1);
@@ -536,14 +539,15 @@ __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, 
                                                              const double *p_old, double *p_new,
                                                              double *q, double *part, int *state,
                                                              int *iters, int *n_running) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state[b] != 1) return;
     const int nb = a.nblk;
     const double bb = sum_parts(slot(part, b, 4, nb), nb);
     const double rr = it == 1 ? bb : sum_parts(slot(part, b, 3, nb), nb);
     const bool done = !(rr > rtol2 * bb);     // also stops on NaN
     if (done || it > maxit) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (blk.x == 0 && threadIdx.x == 0) {
             state[b] = done && rr == rr ? 2 : 3;
             iters[b] = it - 1;
             atomicSub(n_running, 1);
@@ -556,7 +560,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, 
         const double rz_prev = sum_parts(slot(part, b, it & 1, nb), nb);
         beta = rz_cur / rz_prev;
     }
-    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    const long long cell = (long long)blk.x * kCgBlock + threadIdx.x;
     double pq = 0.0, dummy = 0.0;
     if (cell < a.ncell) {
         const size_t base = (size_t)b * a.ncell;
@@ -580,20 +584,21 @@ __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, 
         for (int k = 0; k < 4; ++k) pq += pc[k] * y[k];
     }
     block_sum2(pq, dummy);
-    if (threadIdx.x == 0) slot(part, b, 2, nb)[blockIdx.x] = pq;
+    if (threadIdx.x == 0) slot(part, b, 2, nb)[blk.x] = pq;
 }
 
 __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, const double *p,
                                                              const double *q, double *x, double *r,
                                                              double *z, double *part,
                                                              const int *state, int *iters, int bj) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state[b] != 1) return;
     const int nb = a.nblk;
     const double pq = sum_parts(slot(part, b, 2, nb), nb);
     const double rz = sum_parts(slot(part, b, (it - 1) & 1, nb), nb);
     const double alpha = rz / pq;
-    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    const long long cell = (long long)blk.x * kCgBlock + threadIdx.x;
     double rz_new = 0.0, rr = 0.0;
     if (cell < a.ncell) {
         const long long gi = (long long)b * a.ncell + cell;
@@ -616,16 +621,17 @@ __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, 
     }
     block_sum2(rz_new, rr);
     if (threadIdx.x == 0) {
-        if (bj == 1) slot(part, b, it & 1, nb)[blockIdx.x] = rz_new;
-        slot(part, b, 3, nb)[blockIdx.x] = rr;
-        if (blockIdx.x == 0) iters[b] = it;   // updates done; final once the instance stops
+        if (bj == 1) slot(part, b, it & 1, nb)[blk.x] = rz_new;
+        slot(part, b, 3, nb)[blk.x] = rr;
+        if (blk.x == 0) iters[b] = it;   // updates done; final once the instance stops
     }
 }
 
 __global__ void cg_finish_kernel(long long ndof, const double *x, double *delta, const int *state,
                                  const int *iters, int *iters_out, unsigned long long *total, int B) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const long long t = (long long)blk.x * blockDim.x + threadIdx.x;
+    const int b = blk.y;
     if (state[b] == 0) return;
     if (t < ndof) delta[(size_t)b * ndof + t] = x[(size_t)b * ndof + t];
     if (t == 0 && iters_out) iters_out[b] = iters[b];
@@ -689,20 +695,21 @@ __device__ __forceinline__ double pt_vertex(const double *rdg, int nx, int ny, i
 __global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const double *z,
                                    double *t, const double *part, const double *tol2,
                                    int *n_running) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state[b] != 1) return;
     {
         const double bb = sum_parts(part + ((size_t)b * 5 + 4) * a.nblk, a.nblk);
         const double rr = sum_parts(part + ((size_t)b * 5 + 3) * a.nblk, a.nblk);
         if (!(rr > tol2[0] * bb)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (blk.x == 0 && threadIdx.x == 0) {
                 state[b] = rr == rr ? 2 : 3;
                 atomicSub(n_running, 1);
             }
             return;
         }
     }
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long cell = (long long)blk.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     const size_t base = (size_t)b * a.ncell;
     auto zat = [&](long long c, double v[4]) { load4(z, base + c, v); };
@@ -716,9 +723,10 @@ __global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const
 // b0 = P^T t (level-0 vertex grid)
 __global__ void mg_restrict_dg_kernel(MipArgs a, const int *state, const double *t, VG g,
                                       double *b0) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
     b0[(size_t)b * g.nv + v] = pt_vertex(t + (size_t)b * a.ncell * 4, a.nx, a.ny, x, y, sqrt(a.hx * a.hy));
@@ -756,9 +764,10 @@ __device__ __forceinline__ double stencil_apply(const TS *Sb, const double *x, V
 template <typename TS>
 __global__ void mg_vertex_kernel(const int *state, VG g, const TS *S, const double *x_in,
                                  const double *bv, double *out, int mode) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
     const TS *Sb = st_of(S, b, g.nv);
@@ -774,9 +783,10 @@ __global__ void mg_vertex_kernel(const int *state, VG g, const TS *S, const doub
 
 // coarse b_c = R r_f (R = transpose of bilinear interpolation)
 __global__ void mg_vrestrict_kernel(const int *state, VG gf, const double *rf, VG gc, double *bc) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= gc.nv) return;
     const int X = (int)(v % gc.nvx), Y = (int)(v / gc.nvx);
     const double *r = rf + (size_t)b * gf.nv;
@@ -795,9 +805,10 @@ __global__ void mg_vrestrict_kernel(const int *state, VG gf, const double *rf, V
 
 // probing: e = indicator of the vertices of colour (cx, cy) (coordinates mod 3)
 __global__ void mg_colour_kernel(const int *state, VG g, int cx, int cy, double *e) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
     e[(size_t)b * g.nv + v] = (x % 3 == cx && y % 3 == cy) ? 1.0 : 0.0;
@@ -805,9 +816,10 @@ __global__ void mg_colour_kernel(const int *state, VG g, int cx, int cy, double 
 
 // t = A (P e) on the DG space
 __global__ void mg_probe_dg_kernel(MipArgs a, const int *state, const double *e, VG g, double *t) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long cell = (long long)blk.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     const double sqa = sqrt(a.hx * a.hy);
     const double *eb = e + (size_t)b * g.nv;
@@ -820,9 +832,10 @@ __global__ void mg_probe_dg_kernel(MipArgs a, const int *state, const double *e,
 // S[v][offset to the colour-(cx,cy) vertex of v's 3x3 neighbourhood] = z[v]
 __global__ void mg_scatter_kernel(const int *state, VG g, int cx, int cy, const double *z,
                                   double *S) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
     const int mx = ((cx - x) % 3 + 3) % 3, my = ((cy - y) % 3 + 3) % 3;
@@ -841,9 +854,10 @@ __device__ __forceinline__ double p_weight(int fine, int coarse) {
 }
 
 __global__ void mg_galerkin_kernel(const int *state, VG gf, const double *Sf, VG gc, double *Sc) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= gc.nv) return;
     const int X = (int)(v % gc.nvx), Y = (int)(v / gc.nvx);
     const double *Sb = st_of(Sf, b, gf.nv);
@@ -882,9 +896,10 @@ __global__ void mg_galerkin_kernel(const int *state, VG gf, const double *Sf, VG
 
 // omega / diagonal plane of the smoother
 __global__ void mg_wdiag_kernel(const int *state, VG g, double *S) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     double *Sb = st_of(S, b, g.nv);
     Sb[9 * g.nv + v] = kOmegaV / Sb[4 * g.nv + v];
@@ -892,16 +907,18 @@ __global__ void mg_wdiag_kernel(const int *state, VG g, double *S) {
 
 // FP32 copy of an instance's stencil planes (the V-cycle's copy)
 __global__ void mg_round_kernel(const int *state, long long n, const double *x, float *y) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blk.x * blockDim.x + threadIdx.x;
     if (t < n) y[(size_t)b * n + t] = (float)x[(size_t)b * n + t];
 }
 
 __global__ void mg_zero_kernel(const int *state, long long n, double *x) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state && state[b] != 1) return;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blk.x * blockDim.x + threadIdx.x;
     if (t < n) x[(size_t)b * n + t] = 0.0;
 }
 
@@ -991,9 +1008,10 @@ __global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const i
                                                               const double *r, const double *x0,
                                                               VG g, const double *z, double *z_out,
                                                               double *part, int s) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state[b] != 1) return;
-    const long long cell = (long long)blockIdx.x * kCgBlock + threadIdx.x;
+    const long long cell = (long long)blk.x * kCgBlock + threadIdx.x;
     double rz = 0.0, dummy = 0.0;
     const size_t base = (size_t)b * a.ncell;
     if (cell < a.ncell) {
@@ -1016,14 +1034,15 @@ __global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const i
         store4(z_out, base + cell, zn);
     }
     block_sum2(rz, dummy);
-    if (threadIdx.x == 0) slot(part, b, s, a.nblk)[blockIdx.x] = rz;
+    if (threadIdx.x == 0) slot(part, b, s, a.nblk)[blk.x] = rz;
 }
 
 // two damped Jacobi sweeps from zero: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - S x1)
 __global__ void mg_vpre_kernel(const int *state, VG g, const float *S, const double *bv, double *x2) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
     const float *Sb = st_of(S, b, g.nv);
@@ -1056,9 +1075,10 @@ __device__ __forceinline__ double prolong_at(const double *c, VG gc, int x, int 
 // x3 = x2 + P x_c, x4 = x3 + w D^-1 (b - S x3)
 __global__ void mg_vpost1_kernel(const int *state, VG g, const float *S, const double *bv,
                                  const double *x2, VG gc, const double *xc, double *x4) {
-    const int b = blockIdx.y;
+    const Blk blk = xcd_block();
+    const int b = blk.y;
     if (state[b] != 1) return;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const size_t o = (size_t)b * g.nv;
     const float *Sb = st_of(S, b, g.nv);

@@ -143,6 +143,28 @@ __device__ __forceinline__ bool quad_uses_a(int q) { return q == 0 || q == 3; }
 template <typename T>
 struct Vec4 { T x, y, z, w; };
 
+// Logical block (x, y) of a 2D grid (x: cells or vertices of an instance, y: instance),
+// renumbered for the XCDs.  The hardware hands workgroups to the 8 XCDs in turn by linear id
+// (x fastest), and each XCD has its own L2.  When the row of blocks is a multiple of 8 long,
+// XCD k takes the k-th eighth of every instance's blocks: the neighbouring rows that a block
+// gathers are then mostly loaded by blocks of its own XCD, and every XCD still works on every
+// instance (instances that stop early leave the load balanced).  Any one-to-one renumbering is
+// correct; otherwise the numbering is left as it is.
+struct Blk {
+    int x, y;
+};
+__device__ __forceinline__ Blk xcd_block() {
+    const unsigned gx = gridDim.x;
+    Blk o;
+    o.y = (int)blockIdx.y;
+    if (gx & 7u) {
+        o.x = (int)blockIdx.x;
+        return o;
+    }
+    o.x = (int)((blockIdx.x & 7u) * (gx >> 3) + (blockIdx.x >> 3));
+    return o;
+}
+
 // sweep input block from rho (2D: both diagonal layouts and sigma_t; 1D: natural order)
 template <typename T>
 __device__ __forceinline__ void write_sweep_input(int dim, long long ncell, int B, int b, int nx,
