@@ -39,7 +39,9 @@ METRIC = "cell-dir updates/s; solves/s + p50/p99 latency @1e-6 vs plain GPU SI-D
 # HBM traffic of the sweep kernel measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE),
 # valid only while the kernel source is the one the counters were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep2d_c2_batch_traffic.json")
-SWEEP_SRC = os.path.join(ROOT, "paper_2402_10488_amd", "csrc", "sweep.hip")
+# the sources the sweep kernel is compiled from (its own file and the shared layout header)
+SWEEP_SRCS = [os.path.join(ROOT, "paper_2402_10488_amd", "csrc", n)
+              for n in ("sweep.hip", "rte_internal.h")]
 
 
 def log(*a):
@@ -89,8 +91,11 @@ def cpu_baseline(args, mode, rom_arrays):
 
 
 def sweep_source_hash():
-    with open(SWEEP_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in SWEEP_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(launch_cd):

@@ -73,12 +73,16 @@ namespace rte {
 // min(d + 1, m, nx + ny - 1 - d) cells (m = min(nx, ny), M = max(nx, ny)); the same count for
 // anti-diagonals (x + y = d) and diagonals (x - y + ny - 1 = d).  Arithmetic only, so a sweep
 // step never waits on a memory load for its position.
+// With len(e) = (e + 1) - max(0, e + 1 - m) - max(0, e + 1 - M), the count is
+// tri(d) - tri(d - m) - tri(d - M) for tri(x) = x (x + 1) / 2 on x > 0 and 0 otherwise: no branch,
+// so the lanes of a sweep step that sit in different parts of the grid do not diverge.
+__host__ __device__ __forceinline__ int tri_pos(int x) {
+    x = x > 0 ? x : 0;
+    return (x * (x + 1)) >> 1;
+}
 __host__ __device__ __forceinline__ int diag_off(int nx, int ny, int d) {
     const int m = nx < ny ? nx : ny, M = nx < ny ? ny : nx;
-    if (d <= m) return d * (d + 1) / 2;
-    if (d <= M) return m * (m + 1) / 2 + (d - m) * m;
-    const int e = d - M;
-    return m * (m + 1) / 2 + (M - m) * m + e * (m - 1) - e * (e - 1) / 2;
+    return tri_pos(d) - tri_pos(d - m) - tri_pos(d - M);
 }
 __host__ __device__ __forceinline__ int pos_a(int nx, int ny, int x, int y) {
     const int d = x + y;

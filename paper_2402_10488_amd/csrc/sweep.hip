@@ -121,17 +121,17 @@ __device__ __forceinline__ DirConst<T> uni(DirConst<T> d) {
     return d;
 }
 
-// Cross-lane move "lane j receives lane j-1" as a DPP whole-wave shift (wave_shr:1); lane 0
-// keeps its own value (it is overwritten by the caller).
+// Cross-lane move "lane j receives lane j-1" as a DPP whole-wave shift (wave_shr:1); lane 0 has
+// no source and reads 0 (bound_ctrl), so the result needs no copy of the old value (lane 0's is
+// set by the caller where it is used).
 __device__ __forceinline__ float shfl_up1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138,
-                                                      0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double shfl_up1(double v) {
     const long long b = __double_as_longlong(v);
     const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
-    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
-    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+    const int l2 = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, true);
+    const int h2 = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, true);
     return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
 }
 
@@ -295,11 +295,27 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
         // issued as soon as a direction's values exist, and the compiler counts them exactly.
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
         if (WF || cur.ok) {
-            if (cur.ok && lane == 0) {
+            // lane 0 takes its y-inflow from the boundary (first band) or from the ring.  Its
+            // position is wave-uniform, so the branch is scalar and the ring read is one LDS
+            // broadcast to every lane, kept by lane 0 only.
+            {
+                const int i0 = __builtin_amdgcn_readfirstlane(cur.i);
+                const int k0 = __builtin_amdgcn_readfirstlane(cur.k);
+                T r0v[DG], r1v[DG];
+                if (k0 == 0 || i0 < 0 || i0 >= nx || k0 >= nb) {
+#pragma unroll
+                    for (int d = 0; d < DG; ++d) { r0v[d] = gy; r1v[d] = T(0); }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < DG; ++d) {
+                        r0v[d] = ring[(i0 * DG + d) * 2];
+                        r1v[d] = ring[(i0 * DG + d) * 2 + 1];
+                    }
+                }
 #pragma unroll
                 for (int d = 0; d < DG; ++d) {
-                    if (cur.k == 0) { yi0[d] = gy; yi1[d] = T(0); }
-                    else { yi0[d] = ring[(cur.i * DG + d) * 2]; yi1[d] = ring[(cur.i * DG + d) * 2 + 1]; }
+                    yi0[d] = lane == 0 ? r0v[d] : yi0[d];
+                    yi1[d] = lane == 0 ? r1v[d] : yi1[d];
                 }
             }
             if (cur.i == 0) {
