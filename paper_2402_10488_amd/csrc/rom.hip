@@ -35,9 +35,9 @@ template <typename T> __device__ __forceinline__ int drow(int q, int i);
 template <> __device__ __forceinline__ int drow<float>(int q, int i) { return 4 * q + i; }
 template <> __device__ __forceinline__ int drow<double>(int q, int i) { return q + 4 * i; }
 
-// grid: x = split index, y = instance tile (16 instances), z = r tile (16 ranks); one wave each.
-// ypart[b][split][r]
-template <typename T>
+// grid: x = split index, y = instance tile (16 instances); one wave each, holding all RT rank
+// tiles of 16 so that every value of rho* and rho is read once.  ypart[b][split][r]
+template <typename T, int RT>
 __global__ void __launch_bounds__(64) rom_project_kernel(long long ndof, int K, int B, int r,
                                                          int nsplit, long long per_split,
                                                          const T *U_iso, const double *sigma_s,
@@ -48,14 +48,15 @@ __global__ void __launch_bounds__(64) rom_project_kernel(long long ndof, int K, 
     const int lane = threadIdx.x;
     const int split = blockIdx.x;
     const int b0 = blockIdx.y * 16;
-    const int r0 = blockIdx.z * 16;
     const int n = lane & 15;          // instance within tile (B operand column) / rank row of A
     const int kq = lane >> 4;         // 0..3
     const int b = b0 + n;
     const bool live_b = b < B && (!kind || kind[b] == want);
-    const int rr = r0 + n;
-    const bool live_r = rr < r;
-    V acc = {0, 0, 0, 0};
+    // only the ROMSA instances' partials are read; a tile without one has nothing to do
+    if (__builtin_amdgcn_ballot_w64(live_b) == 0) return;
+    V acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = V{0, 0, 0, 0};
     const long long k_begin = (long long)split * per_split;
     long long k_end = k_begin + per_split;
     if (k_end > ndof) k_end = ndof;
@@ -63,34 +64,100 @@ __global__ void __launch_bounds__(64) rom_project_kernel(long long ndof, int K, 
     const double *rp = rho_prev + (size_t)(live_b ? b : 0) * ndof;
     const double *ss = sigma_s + (size_t)(live_b ? b : 0) * (ndof / K);
     // each group of 16 dofs: lane (n, kq) holds dofs k0 + 4 kq + s, s = 0..3, for 4 MFMA steps
-    for (long long k0 = k_begin; k0 < k_end; k0 += 16) {
-        T bv[4], av[4];
+    // per rank tile.  A trip loads two groups before their products, so two groups' loads are in
+    // flight together.
+    auto load_group = [&](long long k0, T (&bv)[4], T (&av)[RT][4]) __attribute__((always_inline)) {
+        const long long kb = k0 + 4 * kq;
+        if (live_b && kb + 3 < k_end) {
+            // 4 consecutive dofs (16-byte aligned pairs: ndof and kb are multiples of 4)
+            const double2 s01 = *reinterpret_cast<const double2 *>(rs + kb);
+            const double2 s23 = *reinterpret_cast<const double2 *>(rs + kb + 2);
+            const double2 p01 = *reinterpret_cast<const double2 *>(rp + kb);
+            const double2 p23 = *reinterpret_cast<const double2 *>(rp + kb + 2);
+            bv[0] = (T)(ss[kb / K] * (s01.x - p01.x));
+            bv[1] = (T)(ss[(kb + 1) / K] * (s01.y - p01.y));
+            bv[2] = (T)(ss[(kb + 2) / K] * (s23.x - p23.x));
+            bv[3] = (T)(ss[(kb + 3) / K] * (s23.y - p23.y));
+        } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const long long k = k0 + 4 * kq + s;
-            const bool kin = k < k_end;
-            bv[s] = (live_b && kin) ? (T)(ss[k / K] * (rs[k] - rp[k])) : T(0);
-            av[s] = (live_r && kin) ? U_iso[(size_t)k * r + rr] : T(0);
+            for (int s = 0; s < 4; ++s) {
+                const long long k = kb + s;
+                bv[s] = (live_b && k < k_end) ? (T)(ss[k / K] * (rs[k] - rp[k])) : T(0);
+            }
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = mfma(av[s], bv[s], acc);
-    }
-    // D[m][n]: m = rank offset, n = instance offset
+        for (int t = 0; t < RT; ++t) {
+            const int rr = t * 16 + n;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = drow<T>(kq, i);
-        const int rk = r0 + m;
-        if (b < B && rk < r) ypart[((size_t)b * nsplit + split) * r + rk] = (double)acc[i];
+            for (int s = 0; s < 4; ++s) {
+                const long long k = kb + s;
+                av[t][s] = (rr < r && k < k_end) ? U_iso[(size_t)k * r + rr] : T(0);
+            }
+        }
+    };
+    auto product = [&](const T (&bv)[4], const T (&av)[RT][4]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[t] = mfma(av[t][s], bv[s], acc[t]);
+    };
+    for (long long k0 = k_begin; k0 < k_end; k0 += 32) {
+        T bv0[4], av0[RT][4], bv1[4], av1[RT][4];
+        load_group(k0, bv0, av0);
+        const bool two = k0 + 16 < k_end;
+        if (two) load_group(k0 + 16, bv1, av1);
+        product(bv0, av0);
+        if (two) product(bv1, av1);
     }
+    // D[m][n]: m = rank offset within the tile, n = instance offset
+    if (!live_b) return;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rk = t * 16 + drow<T>(kq, i);
+            if (rk < r) ypart[((size_t)b * nsplit + split) * r + rk] = (double)acc[t][i];
+        }
 }
 
-// one wave per instance: y = sum of splits; A = A0 + sum psi_k A_k; LU with partial pivoting;
-// dc = A^{-1} y; singular -> status 1 and kind falls back to DSA (want -> 1).
-__global__ void __launch_bounds__(64) rom_solve_kernel(int B, int r, int m, int nsplit,
-                                                       const double *ypart, const double *A0,
-                                                       const double *Ak, const double *psi,
-                                                       int *kind, int want, int *status,
-                                                       double *dc) {
+// The reduced system of every ROMSA instance, grid (r + ceil(r^2 / 256), B) x 256 threads:
+//   blocks i < r:  y[b][i] = sum over the splits of ypart[b][split][i]  (each thread a fixed
+//                  stride of splits, then a fixed-order tree in LDS: no dependence on scheduling)
+//   later blocks:  A[b] = A0 + sum_k psi[b][k] A_k, one entry per thread
+__global__ void __launch_bounds__(256) rom_assemble_kernel(int B, int r, int m, int nsplit,
+                                                           const double *ypart, const double *A0,
+                                                           const double *Ak, const double *psi,
+                                                           const int *kind, int want, double *y,
+                                                           double *A) {
+    const int b = blockIdx.y;
+    if (kind && kind[b] != want) return;
+    const int t = threadIdx.x;
+    if ((int)blockIdx.x < r) {
+        __shared__ double sh[256];
+        const int i = blockIdx.x;
+        double s = 0.0;
+        for (int k = t; k < nsplit; k += 256) s += ypart[((size_t)b * nsplit + k) * r + i];
+        sh[t] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (t < h) sh[t] += sh[t + h];
+            __syncthreads();
+        }
+        if (t == 0) y[(size_t)b * r + i] = sh[0];
+        return;
+    }
+    const long long e = (long long)(blockIdx.x - r) * 256 + t;
+    if (e >= (long long)r * r) return;
+    double a = A0[e];
+    for (int k = 0; k < m; ++k) a += psi[(size_t)b * m + k] * Ak[(size_t)k * r * r + e];
+    A[(size_t)b * r * r + e] = a;
+}
+
+// one wave per instance: LU with partial pivoting of the assembled A; dc = A^{-1} y;
+// singular -> status 1 and kind falls back to DSA (want -> 1).
+__global__ void __launch_bounds__(64) rom_solve_kernel(int B, int r, const double *yv,
+                                                       const double *Av, int *kind, int want,
+                                                       int *status, double *dc) {
     __shared__ double A[64][65];
     __shared__ double y[64];
     __shared__ int piv_row;
@@ -98,14 +165,8 @@ __global__ void __launch_bounds__(64) rom_solve_kernel(int B, int r, int m, int 
     const int i = threadIdx.x;
     if (kind && kind[b] != want) return;
     if (i < r) {
-        double s = 0.0;
-        for (int k = 0; k < nsplit; ++k) s += ypart[((size_t)b * nsplit + k) * r + i];
-        y[i] = s;
-        for (int j = 0; j < r; ++j) {
-            double a = A0[i * r + j];
-            for (int k = 0; k < m; ++k) a += psi[(size_t)b * m + k] * Ak[((size_t)k * r + i) * r + j];
-            A[i][j] = a;
-        }
+        y[i] = yv[(size_t)b * r + i];
+        for (int j = 0; j < r; ++j) A[i][j] = Av[((size_t)b * r + i) * r + j];
     }
     __syncthreads();
     // scale of A for the singularity test
@@ -177,17 +238,26 @@ __global__ void __launch_bounds__(64) rom_lift_kernel(long long ndof, int B, int
     const int b = b0 + n;
     // singular reduced systems (status 1) leave delta untouched
     const bool live_b = b < B && (!kind || kind[b] == want) && status[b] == 0;
+    if (__builtin_amdgcn_ballot_w64(live_b) == 0) return;    // no ROMSA instance in the tile
     const int rpad = (r + 3) & ~3;
+    // the B operand (this instance's reduced coefficients) is the same for every dof tile
+    T bcol[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int kk = 4 * q + kq;
+        bcol[q] = (live_b && kk < r) ? (T)dc[(size_t)b * r + kk] : T(0);
+    }
     for (int t = 0; t < tiles; ++t) {
         const long long m0 = ((long long)blockIdx.x * tiles + t) * 16;
         if (m0 >= ndof) break;
         V acc = {0, 0, 0, 0};
         const long long mrow = m0 + n;          // A operand row (dof) of this lane
-        for (int k0 = 0; k0 < rpad; k0 += 4) {
-            const int kk = k0 + kq;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (4 * q >= rpad) break;
+            const int kk = 4 * q + kq;
             const T a = (mrow < ndof && kk < r) ? U_rho[(size_t)mrow * r + kk] : T(0);
-            const T bb = (live_b && kk < r) ? (T)dc[(size_t)b * r + kk] : T(0);
-            acc = mfma(a, bb, acc);
+            acc = mfma(a, bcol[q], acc);
         }
         if (live_b) {
 #pragma unroll
@@ -225,13 +295,24 @@ __global__ void __launch_bounds__(64) romig_load_kernel(long long ncell, int K, 
 }  // namespace
 
 size_t rom_split(const rte_problem *p, const rte_rom *rom) {
-    // enough splits that (splits x instance tiles x rank tiles) fills the chip, each split >= 1024 dofs
-    const long long btiles = (p->B + 15) / 16, rtiles = (rom->r + 15) / 16;
-    long long want = (2048 + btiles * rtiles - 1) / (btiles * rtiles);
-    long long maxs = (p->ndof + 1023) / 1024;
-    if (want > maxs) want = maxs;
-    if (want < 1) want = 1;
-    return (size_t)want;
+    // splits of 256 dofs (16 groups of 16): with 16-instance tiles a C2-sized batch gives about
+    // 16 waves per compute unit.  The count depends on the mesh only, so an instance's reduced
+    // load is summed in the same order whatever batch it is in.
+    (void)rom;
+    const long long n = (p->ndof + 255) / 256;
+    return (size_t)(n < 1 ? 1 : n);
+}
+
+// reduced system assembly and its LU solve (both correction and initial guess)
+void launch_rom_system(const rte_problem *p, const rte_rom *rom, const double *psi,
+                       const int *kind, int want_kind, int *status, const RomSpace &w,
+                       hipStream_t s) {
+    const int r = rom->r;
+    const unsigned ablk = cdiv((long long)r * r, 256);
+    hipLaunchKernelGGL(rom_assemble_kernel, dim3(r + ablk, p->B), dim3(256), 0, s, p->B, r, rom->m,
+                       w.nsplit, w.ypart, rom->d_A0, rom->d_A, psi, kind, want_kind, w.y, w.A);
+    hipLaunchKernelGGL(rom_solve_kernel, dim3(p->B), dim3(64), 0, s, p->B, r, w.y, w.A,
+                       const_cast<int *>(kind), want_kind, status, w.dc);
 }
 
 hipError_t launch_rom_initial_guess(const rte_problem *p, const rte_rom *rom, const double *psi,
@@ -242,8 +323,7 @@ hipError_t launch_rom_initial_guess(const rte_problem *p, const rte_rom *rom, co
     hipLaunchKernelGGL(romig_load_kernel, dim3(nsplit, p->B), dim3(64), 0, s, p->ncell, p->K, r,
                        nsplit, per_split, rom->d_U_iso, p->source, sqrt(p->hx * p->hy),
                        p->inflow, rom->d_b_in, w.ypart);
-    hipLaunchKernelGGL(rom_solve_kernel, dim3(p->B), dim3(64), 0, s, p->B, r, rom->m, nsplit,
-                       w.ypart, rom->d_A0, rom->d_A, psi, (int *)nullptr, 0, status, w.dc);
+    launch_rom_system(p, rom, psi, nullptr, 0, status, w, s);
     const int tiles = 4;
     dim3 gl(cdiv(p->ndof, 16 * tiles), cdiv(p->B, 16));
     hipLaunchKernelGGL(rom_lift_kernel<double>, gl, dim3(64), 0, s, p->ndof, p->B, r, tiles,
@@ -260,19 +340,21 @@ hipError_t launch_rom_correct(const rte_problem *p, const rte_rom *rom, const do
     const int nsplit = w.nsplit;
     long long per_split = (ndof + nsplit - 1) / nsplit;
     per_split = (per_split + 15) / 16 * 16;
-    dim3 gp(nsplit, cdiv(p->B, 16), cdiv(r, 16));
-    if (fp32)
-        hipLaunchKernelGGL(rom_project_kernel<float>, gp, dim3(64), 0, s, ndof, p->K, p->B, r,
-                           nsplit, per_split, rom->d_U_iso_f, p->sigma_s, rho_star, rho_prev, kind,
-                           want_kind, w.ypart);
-    else
-        hipLaunchKernelGGL(rom_project_kernel<double>, gp, dim3(64), 0, s, ndof, p->K, p->B, r,
-                           nsplit, per_split, rom->d_U_iso, p->sigma_s, rho_star, rho_prev, kind,
-                           want_kind, w.ypart);
+    dim3 gp(nsplit, cdiv(p->B, 16));
+    const int rt = (r + 15) / 16;                      // 1..4 rank tiles (r <= 64)
+    if (fp32) {
+        auto *k = rt == 1 ? rom_project_kernel<float, 1> : rt == 2 ? rom_project_kernel<float, 2>
+                : rt == 3 ? rom_project_kernel<float, 3> : rom_project_kernel<float, 4>;
+        hipLaunchKernelGGL(k, gp, dim3(64), 0, s, ndof, p->K, p->B, r, nsplit, per_split,
+                           rom->d_U_iso_f, p->sigma_s, rho_star, rho_prev, kind, want_kind, w.ypart);
+    } else {
+        auto *k = rt == 1 ? rom_project_kernel<double, 1> : rt == 2 ? rom_project_kernel<double, 2>
+                : rt == 3 ? rom_project_kernel<double, 3> : rom_project_kernel<double, 4>;
+        hipLaunchKernelGGL(k, gp, dim3(64), 0, s, ndof, p->K, p->B, r, nsplit, per_split,
+                           rom->d_U_iso, p->sigma_s, rho_star, rho_prev, kind, want_kind, w.ypart);
+    }
     // the solve may turn `want` instances into DSA ones (kind is written); the lift then skips them
-    hipLaunchKernelGGL(rom_solve_kernel, dim3(p->B), dim3(64), 0, s, p->B, r, rom->m, nsplit,
-                       w.ypart, rom->d_A0, rom->d_A, psi, const_cast<int *>(kind), want_kind,
-                       status, w.dc);
+    launch_rom_system(p, rom, psi, kind, want_kind, status, w, s);
     const int tiles = 4;
     dim3 gl(cdiv(ndof, 16 * tiles), cdiv(p->B, 16));
     if (fp32)

@@ -126,6 +126,8 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
         L.rom.nsplit = (int)rom_split(p, rom);
         L.rom.ypart = c.take<double>(B * (size_t)L.rom.nsplit * rom->r);
         L.rom.dc = c.take<double>(B * (size_t)rom->r);
+        L.rom.y = c.take<double>(B * (size_t)rom->r);
+        L.rom.A = c.take<double>(B * (size_t)rom->r * rom->r);
         L.rom_status = c.take<int>(B);
     }
     if (gm_m > 0) {

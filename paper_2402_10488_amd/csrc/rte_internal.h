@@ -324,7 +324,8 @@ size_t cg_blocks_per_instance(const rte_problem *p);
 
 // ROM correction
 struct RomSpace {
-    double *y;        // [B][r]
+    double *y;        // [B][r] reduced load
+    double *A;        // [B][r][r] reduced operator A0 + sum_k psi_k A_k
     double *ypart;    // [B][nsplit][r] split-K partials
     double *dc;       // [B][r]
     int nsplit;
