@@ -303,6 +303,17 @@ __device__ __forceinline__ void store4(double *v, long long idx, const double x[
     *reinterpret_cast<double4 *>(v + idx * 4) = t;
 }
 
+// FP32 storage of the preconditioner's vectors (values widened to FP64 on load)
+__device__ __forceinline__ void load4(const float *v, long long idx, double x[4]) {
+    const float4 t = *reinterpret_cast<const float4 *>(v + idx * 4);
+    x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+}
+__device__ __forceinline__ void store4(float *v, long long idx, const double x[4]) {
+    float4 t;
+    t.x = (float)x[0]; t.y = (float)x[1]; t.z = (float)x[2]; t.w = (float)x[3];
+    *reinterpret_cast<float4 *>(v + idx * 4) = t;
+}
+
 __device__ __forceinline__ double cfv(const MipArgs &a, int b, int k, long long cell) {
     return a.cf[((size_t)b * kCf + k) * a.ncell + cell];
 }
@@ -469,11 +480,12 @@ __global__ void __launch_bounds__(kCgBlock) cg_warm_kernel(MipArgs a, const doub
 // (alpha = 0 when d = 0 or the quotient is not a positive finite number); r and A d come from
 // cg_warm_kernel.  The stopping test stays relative to ||b||: slot 3 starts as the partials of
 // (b, b), so the test before the first iteration stops only a zero (or NaN) right-hand side.
+template <typename TZ>
 __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const double *rho_star,
                                                             const double *rho_prev, const int *kind,
                                                             int want, const double *d,
                                                             const double *q, double *x, double *r,
-                                                            double *z, double *part, int *state,
+                                                            TZ *z, double *part, int *state,
                                                             int *iters, int *n_running, int bj) {
     const Blk blk = xcd_block();
     const int b = blk.y;
@@ -513,8 +525,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
         store4(r, gi, rv);
         if (bj) {
             binv_apply(a, b, cell, rv, zv);
-            if (bj == 2)
-                for (int k = 0; k < 4; ++k) zv[k] *= kOmegaDG;
+            for (int k = 0; k < 4; ++k) zv[k] = (double)(TZ)(bj == 2 ? kOmegaDG * zv[k] : zv[k]);
             store4(z, gi, zv);
             for (int k = 0; k < 4; ++k) rz += rv[k] * zv[k];
         }
@@ -534,8 +545,9 @@ __global__ void __launch_bounds__(kCgBlock) cg_setup_kernel(MipArgs a, const dou
 }
 
 // iteration it >= 1: convergence test on the previous residual, p = z + beta p_old, q = A p
+template <typename TZ>
 __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, double rtol2,
-                                                             int maxit, const double *z,
+                                                             int maxit, const TZ *z,
                                                              const double *p_old, double *p_new,
                                                              double *q, double *part, int *state,
                                                              int *iters, int *n_running) {
@@ -587,9 +599,10 @@ __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, 
     if (threadIdx.x == 0) slot(part, b, 2, nb)[blk.x] = pq;
 }
 
+template <typename TZ>
 __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, const double *p,
                                                              const double *q, double *x, double *r,
-                                                             double *z, double *part,
+                                                             TZ *z, double *part,
                                                              const int *state, int *iters, int bj) {
     const Blk blk = xcd_block();
     const int b = blk.y;
@@ -612,8 +625,7 @@ __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, 
         store4(r, gi, rv);
         if (bj) {
             binv_apply(a, b, cell, rv, zv);
-            if (bj == 2)
-                for (int k = 0; k < 4; ++k) zv[k] *= kOmegaDG;
+            for (int k = 0; k < 4; ++k) zv[k] = (double)(TZ)(bj == 2 ? kOmegaDG * zv[k] : zv[k]);
             store4(z, gi, zv);
             for (int k = 0; k < 4; ++k) rz_new += rv[k] * zv[k];
         }
@@ -672,7 +684,8 @@ __device__ __forceinline__ void p_cell(const double *xv, int nvx, int i, int j, 
 }
 
 // P^T: vertex (x, y) gathers from the (up to four) cells having it as a corner
-__device__ __forceinline__ double pt_vertex(const double *rdg, int nx, int ny, int x, int y,
+template <typename TZ>
+__device__ __forceinline__ double pt_vertex(const TZ *rdg, int nx, int ny, int x, int y,
                                             double sqa) {
     double s = 0.0;
     for (int cy = 0; cy < 2; ++cy)
@@ -692,8 +705,9 @@ __device__ __forceinline__ double pt_vertex(const double *rdg, int nx, int ny, i
 // (the matvec kernel's test, on the same fixed-order sums): an instance that passes it stops
 // here, so it skips the rest of the preconditioner and the next iteration.  Every block reaches
 // the same decision; block 0 records it.
-__global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const double *z,
-                                   double *t, const double *part, const double *tol2,
+template <typename TZ>
+__global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const TZ *z,
+                                   TZ *t, const double *part, const double *tol2,
                                    int *n_running) {
     const Blk blk = xcd_block();
     const int b = blk.y;
@@ -721,7 +735,8 @@ __global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const
 }
 
 // b0 = P^T t (level-0 vertex grid)
-__global__ void mg_restrict_dg_kernel(MipArgs a, const int *state, const double *t, VG g,
+template <typename TZ>
+__global__ void mg_restrict_dg_kernel(MipArgs a, const int *state, const TZ *t, VG g,
                                       double *b0) {
     const Blk blk = xcd_block();
     const int b = blk.y;
@@ -1004,9 +1019,10 @@ __global__ void __launch_bounds__(256) mg_coarse_kernel(const int *state, VG g, 
 // coarse correction, post-smoothing and (r, z) in one pass:
 //   z' = z + P x0,  z_out = z' + omega D^-1 (r - A z'),  partial of (r, z_out) into slot s.
 // z' of the neighbour cells is formed on the fly; z_out must not alias z (other workgroups read z).
+template <typename TZ>
 __global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const int *state,
                                                               const double *r, const double *x0,
-                                                              VG g, const double *z, double *z_out,
+                                                              VG g, const TZ *z, TZ *z_out,
                                                               double *part, int s) {
     const Blk blk = xcd_block();
     const int b = blk.y;
@@ -1030,7 +1046,11 @@ __global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const i
         load4(r, base + cell, rv);
         for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
         binv_apply(a, b, cell, y, dz);
-        for (int k = 0; k < 4; ++k) { zn[k] = zc[k] + kOmegaDG * dz[k]; rz += rv[k] * zn[k]; }
+        // (r, z) of the value as stored, so that the CG's beta matches the z it reads
+        for (int k = 0; k < 4; ++k) {
+            zn[k] = (double)(TZ)(zc[k] + kOmegaDG * dz[k]);
+            rz += rv[k] * zn[k];
+        }
         store4(z_out, base + cell, zn);
     }
     block_sum2(rz, dummy);
@@ -1383,7 +1403,7 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
                 for (int cx = 0; cx < 3; ++cx) {
                     hipLaunchKernelGGL(mg_colour_kernel, gv, dim3(256), 0, s, all, g, cx, cy, c.mg.e);
                     hipLaunchKernelGGL(mg_probe_dg_kernel, gc, dim3(256), 0, s, a, all, c.mg.e, g, c.mg.t);
-                    hipLaunchKernelGGL(mg_restrict_dg_kernel, gv, dim3(256), 0, s, a, all, c.mg.t, g, L.rv);
+                    hipLaunchKernelGGL(mg_restrict_dg_kernel<double>, gv, dim3(256), 0, s, a, all, c.mg.t, g, L.rv);
                     hipLaunchKernelGGL(mg_scatter_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.rv, L.S);
                 }
         } else {
@@ -1408,22 +1428,31 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
     return hipGetLastError();
 }
 
-hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot_id, hipStream_t s) {
+namespace {
+template <typename TZ>
+hipError_t mg_precond_t(const rte_problem *p, const CGSpace &c, int slot_id, hipStream_t s) {
     const MipArgs a = mip_args(p, c);
     const dim3 gc(blocks_for(p->ncell, 256), p->B);
     const MGLevel &L0 = c.mg.lv[0];
     const VG g0 = vg_of(L0);
-    // c.z holds the pre-smoothed z = omega D^-1 r (written with r by the CG kernels);
+    TZ *z = reinterpret_cast<TZ *>(c.z);
+    TZ *t = reinterpret_cast<TZ *>(c.mg.t);
+    // z holds the pre-smoothed z = omega D^-1 r (written with r by the CG kernels);
     // residual t = r - A z and the coarse right-hand side P^T t
-    hipLaunchKernelGGL(mg_resid_dg_kernel, gc, dim3(256), 0, s, a, c.state, c.r, c.z, c.mg.t,
+    hipLaunchKernelGGL(mg_resid_dg_kernel<TZ>, gc, dim3(256), 0, s, a, c.state, c.r, z, t,
                        c.part, c.tol2, c.n_running);
-    hipLaunchKernelGGL(mg_restrict_dg_kernel, dim3(blocks_for(L0.nv, 256), p->B), dim3(256), 0, s,
-                       a, c.state, c.mg.t, g0, L0.bv);
+    hipLaunchKernelGGL(mg_restrict_dg_kernel<TZ>, dim3(blocks_for(L0.nv, 256), p->B), dim3(256),
+                       0, s, a, c.state, t, g0, L0.bv);
     const double *x0 = vcycle(p, c, 0, s);
-    // coarse correction and post-smoothing; the preconditioned residual goes to c.mg.t
-    hipLaunchKernelGGL(mg_post_dg_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, c.state,
-                       c.r, x0, g0, c.z, c.mg.t, c.part, slot_id);
+    // coarse correction and post-smoothing; the preconditioned residual goes to t
+    hipLaunchKernelGGL(mg_post_dg_kernel<TZ>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, c.state,
+                       c.r, x0, g0, z, t, c.part, slot_id);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_mg_precond(const rte_problem *p, const CGSpace &c, int slot_id, hipStream_t s) {
+    return c.zf32 ? mg_precond_t<float>(p, c, slot_id, s) : mg_precond_t<double>(p, c, slot_id, s);
 }
 
 size_t cg_blocks_per_instance(const rte_problem *p) {
@@ -1450,9 +1479,15 @@ hipError_t launch_cg_setup(const rte_problem *p, const CGSpace &c, const double 
                            rho_prev, kind, want_kind, guess, c.r, c.q, c.part);
     // bj = 1: block-Jacobi preconditioner; bj = 2: first smoothing step of the multigrid one
     const int bj = c.mg.L == 0 ? 1 : 2;
-    hipLaunchKernelGGL(cg_setup_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, rho_star,
-                       rho_prev, kind, want_kind, guess, c.q, c.x, c.r, c.z, c.part, c.state,
-                       c.iters, c.n_running, bj);
+    if (c.zf32)
+        hipLaunchKernelGGL(cg_setup_kernel<float>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
+                           rho_star, rho_prev, kind, want_kind, guess, c.q, c.x, c.r,
+                           reinterpret_cast<float *>(c.z), c.part, c.state, c.iters, c.n_running,
+                           bj);
+    else
+        hipLaunchKernelGGL(cg_setup_kernel<double>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
+                           rho_star, rho_prev, kind, want_kind, guess, c.q, c.x, c.r, c.z, c.part,
+                           c.state, c.iters, c.n_running, bj);
     if (bj == 2) {                                        // hierarchy built by launch_dsa_build
         if (c.precond[0]) return hipGraphLaunch(c.precond[0], s);
         return launch_mg_precond(p, c, 0, s);
@@ -1466,12 +1501,21 @@ hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, d
     double *p_new = (it & 1) ? c.p1 : c.p0;
     const double *p_old = (it & 1) ? c.p0 : c.p1;
     const double *z = c.mg.L == 0 ? c.z : c.mg.t;    // preconditioned residual
-    hipLaunchKernelGGL(cg_matvec_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, it,
-                       rtol * rtol, maxit, z, p_old, p_new, c.q, c.part, c.state, c.iters,
-                       c.n_running);
     const int bj = c.mg.L == 0 ? 1 : 2;
-    hipLaunchKernelGGL(cg_update_kernel, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, it, p_new,
-                       c.q, c.x, c.r, c.z, c.part, c.state, c.iters, bj);
+    if (c.zf32) {
+        hipLaunchKernelGGL(cg_matvec_kernel<float>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
+                           it, rtol * rtol, maxit, reinterpret_cast<const float *>(z), p_old,
+                           p_new, c.q, c.part, c.state, c.iters, c.n_running);
+        hipLaunchKernelGGL(cg_update_kernel<float>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
+                           it, p_new, c.q, c.x, c.r, reinterpret_cast<float *>(c.z), c.part,
+                           c.state, c.iters, bj);
+    } else {
+        hipLaunchKernelGGL(cg_matvec_kernel<double>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
+                           it, rtol * rtol, maxit, z, p_old, p_new, c.q, c.part, c.state, c.iters,
+                           c.n_running);
+        hipLaunchKernelGGL(cg_update_kernel<double>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
+                           it, p_new, c.q, c.x, c.r, c.z, c.part, c.state, c.iters, bj);
+    }
     if (bj == 2) {
         if (c.precond[it & 1]) return hipGraphLaunch(c.precond[it & 1], s);
         return launch_mg_precond(p, c, it & 1, s);

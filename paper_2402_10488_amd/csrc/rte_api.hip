@@ -111,6 +111,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
                 g.rv = c.take<double>(B * (size_t)g.nv);
             }
             L.cg.mg.cinv = nullptr;
+            L.cg.zf32 = prec == RTE_MIXED && L.cg.mg.L > 0;
             if (L.cg.mg.L > 0) {
                 L.cg.mg.t = c.take<double>(B * nd);
                 L.cg.mg.e = c.take<double>(B * (size_t)L.cg.mg.lv[0].nv);

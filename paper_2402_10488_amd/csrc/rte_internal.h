@@ -295,6 +295,9 @@ struct CGSpace {
     int *n_running;                    // [1]
     double *tol2;                      // [1] the call's squared relative tolerance
     int nblk;                          // blocks per instance
+    int zf32;                          // 1: z and the multigrid residual t held in FP32 (mixed
+                                       // precision with the multigrid preconditioner; the
+                                       // buffers keep their FP64 size)
     // the multigrid preconditioner's launches captured as HIP graphs, one per parity slot of
     // its (r, z) partial sums (null: launched one by one); valid for this carve-up only
     hipGraphExec_t precond[2] = {nullptr, nullptr};
