@@ -1131,50 +1131,96 @@ struct SmallLevels {
     const float *S[kMaxLevels];
 };
 
+// n values from global memory into LDS, U loads in flight per thread before their stores
+template <typename T, int U>
+__device__ __forceinline__ void copy_to_lds(const T *src, T *dst, long long n, int t, int nt) {
+    for (long long v0 = t; v0 < n; v0 += (long long)U * nt) {
+        T tmp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long v = v0 + (long long)u * nt;
+            tmp[u] = v < n ? src[v] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long v = v0 + (long long)u * nt;
+            if (v < n) dst[v] = tmp[u];
+        }
+    }
+}
+
+// LDS layout: per level l, four vectors of nv doubles (xa, xb, bv, rv) at sh + o[l] + k nv, then
+// every level's FP32 stencil planes at (float *)sh + os[l].  The shapes and offsets sit in LDS
+// and every address is sh plus an integer, so the compiler keeps LDS accesses as ds_ operations:
+// arrays of pointers or kernel-argument arrays indexed by the runtime level would go through
+// private memory and turn each LDS access into a flat one.
+struct SmallDesc {
+    int nvx[kMaxLevels], nvy[kMaxLevels], nv[kMaxLevels], o[kMaxLevels], os[kMaxLevels];
+};
+
 __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state, SmallLevels sl,
                                                                const double *b_top, double *x_top,
                                                                int nsweep, const double *cinv) {
     extern __shared__ double sh[];
+    __shared__ SmallDesc d;
     const int b = blockIdx.x;
     if (state[b] != 1) return;
-    double *xa[kMaxLevels], *xb[kMaxLevels], *bv[kMaxLevels], *rv[kMaxLevels];
-    float *Sl[kMaxLevels];
-    double *q = sh;
-    for (int l = 0; l < sl.n; ++l) {
-        xa[l] = q; q += sl.nv[l];
-        xb[l] = q; q += sl.nv[l];
-        bv[l] = q; q += sl.nv[l];
-        rv[l] = q; q += sl.nv[l];
-    }
-    float *fq = reinterpret_cast<float *>(q);
-    for (int l = 0; l < sl.n; ++l) { Sl[l] = fq; fq += kStencilPlanes * sl.nv[l]; }
     const int t = threadIdx.x, nt = blockDim.x;
-    for (int l = 0; l < sl.n; ++l) {
-        const float *src = st_of(sl.S[l], b, sl.nv[l]);
-        for (long long v = t; v < kStencilPlanes * sl.nv[l]; v += nt) Sl[l][v] = src[v];
+    float *shf = reinterpret_cast<float *>(sh);
+    {
+        int o = 0;
+#pragma unroll
+        for (int l = 0; l < kMaxLevels; ++l)
+            if (l < sl.n) o += 4 * (int)sl.nv[l];
+        int os = 2 * o;
+#pragma unroll
+        for (int l = 0; l < kMaxLevels; ++l) {
+            if (l < sl.n) {
+                const long long nv = sl.nv[l];
+                copy_to_lds<float, 12>(st_of(sl.S[l], b, nv), shf + os, kStencilPlanes * nv, t, nt);
+                if (t == 0) {
+                    d.nvx[l] = sl.nvx[l];
+                    d.nvy[l] = sl.nvy[l];
+                    d.nv[l] = (int)nv;
+                    d.os[l] = os;
+                }
+                os += kStencilPlanes * (int)nv;
+            }
+        }
+        if (t == 0) {
+            int oo = 0;
+#pragma unroll
+            for (int l = 0; l < kMaxLevels; ++l)
+                if (l < sl.n) { d.o[l] = oo; oo += 4 * (int)sl.nv[l]; }
+        }
+        // level 0's right-hand side (bv of level 0 sits at 2 nv[0])
+        copy_to_lds<double, 4>(b_top + (size_t)b * sl.nv[0], sh + 2 * sl.nv[0], sl.nv[0], t, nt);
     }
-    for (long long v = t; v < sl.nv[0]; v += nt) bv[0][v] = b_top[(size_t)b * sl.nv[0] + v];
     __syncthreads();
-    auto grid_of = [&](int l) { VG g; g.nvx = sl.nvx[l]; g.nvy = sl.nvy[l]; g.nv = sl.nv[l]; return g; };
-    auto S_of = [&](int l) { return static_cast<const float *>(Sl[l]); };
+    const int n_lev = sl.n;
+    auto grid_of = [&](int l) { VG g; g.nvx = d.nvx[l]; g.nvy = d.nvy[l]; g.nv = d.nv[l]; return g; };
+    auto vec = [&](int l, int k) { return sh + d.o[l] + k * d.nv[l]; };   // 0 xa, 1 xb, 2 bv, 3 rv
+    auto S_of = [&](int l) { return static_cast<const float *>(shf + d.os[l]); };
     // down: two pre-smoothing sweeps, residual, restriction
-    for (int l = 0; l < sl.n - 1; ++l) {
+    for (int l = 0; l < n_lev - 1; ++l) {
         const VG g = grid_of(l);
         const float *S = S_of(l);
         const float *wd = S + 9 * g.nv;
-        for (long long v = t; v < g.nv; v += nt) xa[l][v] = wd[v] * bv[l][v];
+        double *xa = vec(l, 0), *xb = vec(l, 1), *bv = vec(l, 2), *rv = vec(l, 3);
+        for (long long v = t; v < g.nv; v += nt) xa[v] = wd[v] * bv[v];
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
             const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-            xb[l][v] = xa[l][v] + wd[v] * (bv[l][v] - stencil_apply(S, xa[l], g, vx, vy));
+            xb[v] = xa[v] + wd[v] * (bv[v] - stencil_apply(S, xa, g, vx, vy));
         }
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
             const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-            rv[l][v] = bv[l][v] - stencil_apply(S, xb[l], g, vx, vy);
+            rv[v] = bv[v] - stencil_apply(S, xb, g, vx, vy);
         }
         __syncthreads();
         const VG gc = grid_of(l + 1);
+        double *bc = vec(l + 1, 2);
         for (long long v = t; v < gc.nv; v += nt) {
             const int X = (int)(v % gc.nvx), Y = (int)(v / gc.nvx);
             double acc = 0.0;
@@ -1184,68 +1230,73 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int x = 2 * X + dx;
                     if (x < 0 || x >= g.nvx) continue;
-                    acc += (dx == 0 ? 1.0 : 0.5) * (dy == 0 ? 1.0 : 0.5) * rv[l][(long long)y * g.nvx + x];
+                    acc += (dx == 0 ? 1.0 : 0.5) * (dy == 0 ? 1.0 : 0.5) * rv[(long long)y * g.nvx + x];
                 }
             }
-            bv[l + 1][v] = acc;
+            bc[v] = acc;
         }
         __syncthreads();
     }
     // coarsest from zero: the exact solve when the inverse exists, else damped Jacobi sweeps;
     // the result ends in xb
-    if (cinv) {
-        const int l = sl.n - 1;
-        const int n = (int)sl.nv[l];
-        const double *Ci = cinv + (size_t)b * n * n;
-        for (int v = t; v < n; v += nt) {
-            double acc = 0.0;
-            for (int w = 0; w < n; ++w) acc += Ci[v * n + w] * bv[l][w];
-            xb[l][v] = acc;
-        }
-        __syncthreads();
-    } else {
-        const int l = sl.n - 1;
-        const VG g = grid_of(l);
-        const float *S = S_of(l);
-        const float *wd = S + 9 * g.nv;
-        for (long long v = t; v < g.nv; v += nt) xb[l][v] = wd[v] * bv[l][v];
-        __syncthreads();
-        for (int k = 1; k < nsweep; ++k) {
-            for (long long v = t; v < g.nv; v += nt) {
-                const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-                xa[l][v] = xb[l][v] + wd[v] * (bv[l][v] - stencil_apply(S, xb[l], g, vx, vy));
+    {
+        const int l = n_lev - 1;
+        double *xa = vec(l, 0), *xb = vec(l, 1), *bv = vec(l, 2);
+        if (cinv) {
+            const int n = d.nv[l];
+            const double *Ci = cinv + (size_t)b * n * n;
+            for (int v = t; v < n; v += nt) {
+                double acc = 0.0;
+#pragma unroll 8
+                for (int w = 0; w < n; ++w) acc += Ci[v * n + w] * bv[w];
+                xb[v] = acc;
             }
             __syncthreads();
-            for (long long v = t; v < g.nv; v += nt) xb[l][v] = xa[l][v];
+        } else {
+            const VG g = grid_of(l);
+            const float *S = S_of(l);
+            const float *wd = S + 9 * g.nv;
+            for (long long v = t; v < g.nv; v += nt) xb[v] = wd[v] * bv[v];
             __syncthreads();
+            for (int k = 1; k < nsweep; ++k) {
+                for (long long v = t; v < g.nv; v += nt) {
+                    const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
+                    xa[v] = xb[v] + wd[v] * (bv[v] - stencil_apply(S, xb, g, vx, vy));
+                }
+                __syncthreads();
+                for (long long v = t; v < g.nv; v += nt) xb[v] = xa[v];
+                __syncthreads();
+            }
         }
     }
     // up: prolongation-correction, two post-smoothing sweeps (result in xb)
-    for (int l = sl.n - 2; l >= 0; --l) {
+    for (int l = n_lev - 2; l >= 0; --l) {
         const VG g = grid_of(l), gc = grid_of(l + 1);
         const float *S = S_of(l);
         const float *wd = S + 9 * g.nv;
+        double *xa = vec(l, 0), *xb = vec(l, 1), *bv = vec(l, 2);
+        const double *c = vec(l + 1, 1);
         for (long long v = t; v < g.nv; v += nt) {
             const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
             const int X0 = x / 2, Y0 = y / 2;
             const int X1 = (x & 1) ? X0 + 1 : X0, Y1 = (y & 1) ? Y0 + 1 : Y0;
-            const double *c = xb[l + 1];
-            xb[l][v] += 0.25 * (c[(long long)Y0 * gc.nvx + X0] + c[(long long)Y0 * gc.nvx + X1] +
-                                c[(long long)Y1 * gc.nvx + X0] + c[(long long)Y1 * gc.nvx + X1]);
+            xb[v] += 0.25 * (c[(long long)Y0 * gc.nvx + X0] + c[(long long)Y0 * gc.nvx + X1] +
+                             c[(long long)Y1 * gc.nvx + X0] + c[(long long)Y1 * gc.nvx + X1]);
         }
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
             const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-            xa[l][v] = xb[l][v] + wd[v] * (bv[l][v] - stencil_apply(S, xb[l], g, vx, vy));
+            xa[v] = xb[v] + wd[v] * (bv[v] - stencil_apply(S, xb, g, vx, vy));
         }
         __syncthreads();
         for (long long v = t; v < g.nv; v += nt) {
             const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-            xb[l][v] = xa[l][v] + wd[v] * (bv[l][v] - stencil_apply(S, xa[l], g, vx, vy));
+            xb[v] = xa[v] + wd[v] * (bv[v] - stencil_apply(S, xa, g, vx, vy));
         }
         __syncthreads();
     }
-    for (long long v = t; v < sl.nv[0]; v += nt) x_top[(size_t)b * sl.nv[0] + v] = xb[0][v];
+    const double *x0 = vec(0, 1);
+    for (long long v = t; v < sl.nv[0]; v += nt) x_top[(size_t)b * sl.nv[0] + v] = x0[v];
 }
 
 MipArgs mip_args(const rte_problem *p, int nblk) {
