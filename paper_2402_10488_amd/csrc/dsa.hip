@@ -734,17 +734,23 @@ __global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const
     store4(t, base + cell, y);
 }
 
-// b0 = P^T t (level-0 vertex grid)
+// b0 = P^T t (level-0 vertex grid); with x0 non-null also level 0's first smoothing step from
+// zero, x0 = omega b0 / diag (the tenth plane of S0)
 template <typename TZ>
 __global__ void mg_restrict_dg_kernel(MipArgs a, const int *state, const TZ *t, VG g,
-                                      double *b0) {
+                                      double *b0, const float *S0, double *x0) {
     const Blk blk = xcd_block();
     const int b = blk.y;
     if (state && state[b] != 1) return;
     const long long v = (long long)blk.x * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
     const int x = (int)(v % g.nvx), y = (int)(v / g.nvx);
-    b0[(size_t)b * g.nv + v] = pt_vertex(t + (size_t)b * a.ncell * 4, a.nx, a.ny, x, y, sqrt(a.hx * a.hy));
+    const double bv = pt_vertex(t + (size_t)b * a.ncell * 4, a.nx, a.ny, x, y, sqrt(a.hx * a.hy));
+    b0[(size_t)b * g.nv + v] = bv;
+    if (x0) {
+        const double wd = S0[((size_t)b * kStencilPlanes + 9) * g.nv + v];
+        x0[(size_t)b * g.nv + v] = wd * bv;
+    }
 }
 
 // ---- vertex grids: 9-point stencils in planes, S[b][(dy+1)*3 + dx+1][v], and a tenth plane
@@ -796,8 +802,10 @@ __global__ void mg_vertex_kernel(const int *state, VG g, const TS *S, const doub
     out[o + v] = res;
 }
 
-// coarse b_c = R r_f (R = transpose of bilinear interpolation)
-__global__ void mg_vrestrict_kernel(const int *state, VG gf, const double *rf, VG gc, double *bc) {
+// coarse b_c = R r_f (R = transpose of bilinear interpolation); with xc non-null also the coarse
+// level's first smoothing step from zero, x_c = omega b_c / diag (the tenth plane of Sc)
+__global__ void mg_vrestrict_kernel(const int *state, VG gf, const double *rf, VG gc, double *bc,
+                                    const float *Sc, double *xc) {
     const Blk blk = xcd_block();
     const int b = blk.y;
     if (state && state[b] != 1) return;
@@ -816,6 +824,10 @@ __global__ void mg_vrestrict_kernel(const int *state, VG gf, const double *rf, V
         }
     }
     bc[(size_t)b * gc.nv + v] = s;
+    if (xc) {
+        const double wd = st_of(Sc, b, gc.nv)[9 * gc.nv + v];
+        xc[(size_t)b * gc.nv + v] = wd * s;
+    }
 }
 
 // probing: e = indicator of the vertices of colour (cx, cy) (coordinates mod 3)
@@ -1379,6 +1391,14 @@ int small_start(const rte_problem *p, const CGSpace &c) {
     return ls;
 }
 
+// true when vcycle treats level l with the grid-wide kernels (neither the LDS small-level kernel
+// nor the coarsest solve): such a level starts from x = omega b / diag in xb
+bool vertex_grid_level(const rte_problem *p, const CGSpace &c, int l) {
+    const int ls = small_start(p, c);
+    if (l == ls && ls < c.mg.L) return false;
+    return l != c.mg.L - 1;
+}
+
 // one V-cycle on level l for the right-hand side lv[l].bv; returns the buffer holding x_l
 double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
     const MGLevel &L = c.mg.lv[l];
@@ -1418,14 +1438,14 @@ double *vcycle(const rte_problem *p, const CGSpace &c, int l, hipStream_t s) {
     }
     const MGLevel &C = c.mg.lv[l + 1];
     const VG gcv = vg_of(C);
-    // two pre-smoothing sweeps from zero, residual, restriction
+    // pre-smoothing from zero (the first step, x = omega b / diag, was written into xb by the
+    // kernel that formed b), residual, restriction
     if (kVertexSweeps == 2)
         hipLaunchKernelGGL(mg_vpre_kernel, grid, dim3(256), 0, s, c.state, g, L.S32, L.bv, L.xb);
-    else
-        hipLaunchKernelGGL(mg_vertex_kernel<float>, grid, dim3(256), 0, s, c.state, g, L.S32, L.xb, L.bv, L.xb, 0);
     hipLaunchKernelGGL(mg_vertex_kernel<float>, grid, dim3(256), 0, s, c.state, g, L.S32, L.xb, L.bv, L.rv, 2);
+    const bool x_first = vertex_grid_level(p, c, l + 1);
     hipLaunchKernelGGL(mg_vrestrict_kernel, dim3(blocks_for(C.nv, 256), p->B), dim3(256), 0, s,
-                       c.state, g, L.rv, gcv, C.bv);
+                       c.state, g, L.rv, gcv, C.bv, C.S32, x_first ? C.xb : nullptr);
     double *xc = vcycle(p, c, l + 1, s);
     // coarse correction with the first post-smoothing sweep, then the second sweep
     hipLaunchKernelGGL(mg_vpost1_kernel, grid, dim3(256), 0, s, c.state, g, L.S32, L.bv, L.xb, gcv, xc, L.xa);
@@ -1454,7 +1474,8 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
                 for (int cx = 0; cx < 3; ++cx) {
                     hipLaunchKernelGGL(mg_colour_kernel, gv, dim3(256), 0, s, all, g, cx, cy, c.mg.e);
                     hipLaunchKernelGGL(mg_probe_dg_kernel, gc, dim3(256), 0, s, a, all, c.mg.e, g, c.mg.t);
-                    hipLaunchKernelGGL(mg_restrict_dg_kernel<double>, gv, dim3(256), 0, s, a, all, c.mg.t, g, L.rv);
+                    hipLaunchKernelGGL(mg_restrict_dg_kernel<double>, gv, dim3(256), 0, s, a, all, c.mg.t, g, L.rv,
+                                       nullptr, nullptr);
                     hipLaunchKernelGGL(mg_scatter_kernel, gv, dim3(256), 0, s, all, g, cx, cy, L.rv, L.S);
                 }
         } else {
@@ -1492,8 +1513,10 @@ hipError_t mg_precond_t(const rte_problem *p, const CGSpace &c, int slot_id, hip
     // residual t = r - A z and the coarse right-hand side P^T t
     hipLaunchKernelGGL(mg_resid_dg_kernel<TZ>, gc, dim3(256), 0, s, a, c.state, c.r, z, t,
                        c.part, c.tol2, c.n_running);
+    // a grid-wide level 0 gets its first smoothing step (into xb) with the restriction
+    const bool x_first = vertex_grid_level(p, c, 0);
     hipLaunchKernelGGL(mg_restrict_dg_kernel<TZ>, dim3(blocks_for(L0.nv, 256), p->B), dim3(256),
-                       0, s, a, c.state, t, g0, L0.bv);
+                       0, s, a, c.state, t, g0, L0.bv, L0.S32, x_first ? L0.xb : nullptr);
     const double *x0 = vcycle(p, c, 0, s);
     // coarse correction and post-smoothing; the preconditioned residual goes to t
     hipLaunchKernelGGL(mg_post_dg_kernel<TZ>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, c.state,
