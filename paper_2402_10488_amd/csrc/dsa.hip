@@ -174,6 +174,8 @@ struct MipArgs {
     //        halves, so the rounded smoother stays exactly symmetric
     const double *cf;
     const float *binv;
+    // cf rounded to FP32 (mixed precision): read by the preconditioner's operator applications
+    const float *cf32;
 };
 constexpr int kCf = 5;
 constexpr int kBinv = 10;
@@ -314,8 +316,16 @@ __device__ __forceinline__ void store4(float *v, long long idx, const double x[4
     *reinterpret_cast<float4 *>(v + idx * 4) = t;
 }
 
+template <typename TC>
+__device__ __forceinline__ const TC *cf_of(const MipArgs &a);
+template <>
+__device__ __forceinline__ const double *cf_of<double>(const MipArgs &a) { return a.cf; }
+template <>
+__device__ __forceinline__ const float *cf_of<float>(const MipArgs &a) { return a.cf32; }
+
+template <typename TC = double>
 __device__ __forceinline__ double cfv(const MipArgs &a, int b, int k, long long cell) {
-    return a.cf[((size_t)b * kCf + k) * a.ncell + cell];
+    return (double)cf_of<TC>(a)[((size_t)b * kCf + k) * a.ncell + cell];
 }
 
 // z = B^-1 r with the stored inverse of the diagonal block (symmetric by construction)
@@ -332,11 +342,12 @@ __device__ __forceinline__ void binv_apply(const MipArgs &a, int b, long long ce
 }
 
 // y = A x at cell (i,j), with x read through a functor (to form p = z + beta p_old on the fly);
-// the operator's coefficients come from the per-cell planes (no divisions here)
-template <typename F>
+// the operator's coefficients come from the per-cell planes (no divisions here), FP64 or (TC =
+// float, inside the mixed-precision preconditioner) their FP32 copy
+template <typename TC = double, typename F>
 __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y[4]) {
     const long long cell = (long long)j * a.nx + i;
-    const double sa = cfv(a, b, 0, cell), Dx = cfv(a, b, 1, cell), Dy = cfv(a, b, 2, cell);
+    const double sa = cfv<TC>(a, b, 0, cell), Dx = cfv<TC>(a, b, 1, cell), Dy = cfv<TC>(a, b, 2, cell);
     double xc[4], xn[4], M[4];
     xat(cell, xc);
     const double vx = a.vol_x * Dx, vy = a.vol_y * Dy;
@@ -346,8 +357,8 @@ __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y
     y[2] = (sa + vy) * xc[2];
     y[3] = (sa + vx + vy) * xc[3];
     if (i > 0) {
-        const double tl = a.th_x * cfv(a, b, 1, cell - 1);
-        const double k = cfv(a, b, 3, cell - 1) * a.ihx;
+        const double tl = a.th_x * cfv<TC>(a, b, 1, cell - 1);
+        const double k = cfv<TC>(a, b, 3, cell - 1) * a.ihx;
         face_minus(k, tx, M); addx(M, xc, y);
         xat(cell - 1, xn);
         couple_pm(k, tl, tx, M); addx(M, xn, y);
@@ -355,8 +366,8 @@ __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y
         face_minus(fmax(a.kx, kMipC * Dx * a.ihx) * a.ihx, tx, M); addx(M, xc, y);
     }
     if (i + 1 < a.nx) {
-        const double tr = a.th_x * cfv(a, b, 1, cell + 1);
-        const double k = cfv(a, b, 3, cell) * a.ihx;
+        const double tr = a.th_x * cfv<TC>(a, b, 1, cell + 1);
+        const double k = cfv<TC>(a, b, 3, cell) * a.ihx;
         face_plus(k, tx, M); addx(M, xc, y);
         xat(cell + 1, xn);
         couple_mp(k, tx, tr, M); addx(M, xn, y);
@@ -364,8 +375,8 @@ __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y
         face_plus(fmax(a.kx, kMipC * Dx * a.ihx) * a.ihx, tx, M); addx(M, xc, y);
     }
     if (j > 0) {
-        const double tb = a.th_y * cfv(a, b, 2, cell - a.nx);
-        const double k = cfv(a, b, 4, cell - a.nx) * a.ihy;
+        const double tb = a.th_y * cfv<TC>(a, b, 2, cell - a.nx);
+        const double k = cfv<TC>(a, b, 4, cell - a.nx) * a.ihy;
         face_minus(k, ty, M); addy(M, xc, y);
         xat(cell - a.nx, xn);
         couple_pm(k, tb, ty, M); addy(M, xn, y);
@@ -373,8 +384,8 @@ __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y
         face_minus(fmax(a.ky, kMipC * Dy * a.ihy) * a.ihy, ty, M); addy(M, xc, y);
     }
     if (j + 1 < a.ny) {
-        const double tt = a.th_y * cfv(a, b, 2, cell + a.nx);
-        const double k = cfv(a, b, 4, cell) * a.ihy;
+        const double tt = a.th_y * cfv<TC>(a, b, 2, cell + a.nx);
+        const double k = cfv<TC>(a, b, 4, cell) * a.ihy;
         face_plus(k, ty, M); addy(M, xc, y);
         xat(cell + a.nx, xn);
         couple_mp(k, ty, tt, M); addy(M, xn, y);
@@ -384,7 +395,8 @@ __device__ void mip_apply(const MipArgs &a, int b, int i, int j, F xat, double y
 }
 
 // per-cell operator data and the inverse of the diagonal block, once per solve
-__global__ void mip_prepare_kernel(MipArgs a, const int *mask, double *cf, float *binv) {
+__global__ void mip_prepare_kernel(MipArgs a, const int *mask, double *cf, float *binv,
+                                   float *cf32) {
     const Blk blk = xcd_block();
     const int b = blk.y;
     if (mask && mask[b] != 1) return;
@@ -400,6 +412,14 @@ __global__ void mip_prepare_kernel(MipArgs a, const int *mask, double *cf, float
     c[2 * a.ncell] = cc.Dy;
     c[3 * a.ncell] = kr;
     c[4 * a.ncell] = kt;
+    if (cf32) {
+        float *c32 = cf32 + (size_t)b * kCf * a.ncell + cell;
+        c32[0] = (float)cc.sa;
+        c32[1 * a.ncell] = (float)cc.Dx;
+        c32[2 * a.ncell] = (float)cc.Dy;
+        c32[3 * a.ncell] = (float)kr;
+        c32[4 * a.ncell] = (float)kt;
+    }
     double A[16], col[4][4];
     mip_diag(a, b, i, j, A);
     for (int k = 0; k < 4; ++k) {
@@ -728,7 +748,7 @@ __global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const
     const size_t base = (size_t)b * a.ncell;
     auto zat = [&](long long c, double v[4]) { load4(z, base + c, v); };
     double y[4], rv[4];
-    mip_apply(a, b, (int)(cell % a.nx), (int)(cell / a.nx), zat, y);
+    mip_apply<TZ>(a, b, (int)(cell % a.nx), (int)(cell / a.nx), zat, y);
     load4(r, base + cell, rv);
     for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
     store4(t, base + cell, y);
@@ -1053,7 +1073,7 @@ __global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const i
         };
         double y[4], zc[4], rv[4], dz[4], zn[4];
         const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
-        mip_apply(a, b, i, j, zat, y);
+        mip_apply<TZ>(a, b, i, j, zat, y);
         zat(cell, zc);
         load4(r, base + cell, rv);
         for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
@@ -1334,12 +1354,14 @@ MipArgs mip_args(const rte_problem *p, int nblk) {
     a.sigma_s = p->sigma_s;
     a.cf = nullptr;
     a.binv = nullptr;
+    a.cf32 = nullptr;
     return a;
 }
 MipArgs mip_args(const rte_problem *p, const CGSpace &c) {
     MipArgs a = mip_args(p, c.nblk);
     a.cf = c.cf;
     a.binv = c.binv;
+    a.cf32 = c.cf32;
     return a;
 }
 
@@ -1460,7 +1482,7 @@ hipError_t launch_dsa_build(const rte_problem *p, const CGSpace &c, const int *m
     const MipArgs a = mip_args(p, c);
     const int *all = mask;        // the selected instances (every instance if null)
     const dim3 gc(blocks_for(p->ncell, 256), p->B);
-    hipLaunchKernelGGL(mip_prepare_kernel, gc, dim3(256), 0, s, a, mask, c.cf, c.binv);
+    hipLaunchKernelGGL(mip_prepare_kernel, gc, dim3(256), 0, s, a, mask, c.cf, c.binv, c.cf32);
     for (int l = 0; l < c.mg.L; ++l) {
         const MGLevel &L = c.mg.lv[l];
         const VG g = vg_of(L);

@@ -112,6 +112,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
             }
             L.cg.mg.cinv = nullptr;
             L.cg.zf32 = prec == RTE_MIXED && L.cg.mg.L > 0;
+            L.cg.cf32 = L.cg.zf32 ? c.take<float>(B * (size_t)p->ncell * 5) : nullptr;
             if (L.cg.mg.L > 0) {
                 L.cg.mg.t = c.take<double>(B * nd);
                 L.cg.mg.e = c.take<double>(B * (size_t)L.cg.mg.lv[0].nv);

@@ -297,7 +297,9 @@ struct CGSpace {
     int nblk;                          // blocks per instance
     int zf32;                          // 1: z and the multigrid residual t held in FP32 (mixed
                                        // precision with the multigrid preconditioner; the
-                                       // buffers keep their FP64 size)
+                                       // buffers keep their FP64 size), and the preconditioner
+                                       // applies the operator with cf32
+    float *cf32;                       // [B][5][ncell] cf rounded to FP32 (zf32 only, else null)
     // the multigrid preconditioner's launches captured as HIP graphs, one per parity slot of
     // its (r, z) partial sums (null: launched one by one); valid for this carve-up only
     hipGraphExec_t precond[2] = {nullptr, nullptr};
