@@ -80,14 +80,94 @@ def cpu_baseline(args, mode, rom_arrays):
     res = sisa(d, "romsad" if mode == "romsad" else mode, eps=args.eps, rom=rom, theta=args.theta)
     dt = time.perf_counter() - t0
     cd = d.nc * d.nv * res.n_sweep
-    return {"value": cd / dt, "unit": "cell-dir updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 instance (seed 20000) of the {args.n}x{args.n} lattice, {args.nphi} "
-                      f"directions, {mode}, FP64, tol {args.eps:g}: {res.n_sweep} sweeps in "
-                      f"{dt:.1f}s; oracle ROM from {args.cpu_train} training solves"
-                      if mode == "romsad" else
-                      f"1 instance (seed 20000) of the {args.n}x{args.n} lattice, {args.nphi} "
-                      f"directions, {mode}, FP64, tol {args.eps:g}: {res.n_sweep} sweeps in {dt:.1f}s",
-            "solves_per_s": 1.0 / dt}
+    rom_note = f"; oracle ROM from {args.cpu_train} training solves" if mode == "romsad" else ""
+    one = {"value": cd / dt, "cores": 1, "solves_per_s": 1.0 / dt,
+           "sample": f"1 instance (seed 20000) of the {args.n}x{args.n} lattice, {args.nphi} "
+                     f"directions, {mode}, FP64, tol {args.eps:g}: {res.n_sweep} sweeps in "
+                     f"{dt:.1f}s{rom_note}"}
+    k = host_cores() if args.cpu_cores <= 0 else args.cpu_cores
+    if k <= 1:
+        return dict(one, unit="cell-dir updates/s", kind="oracle")
+    allc = cpu_all_cores(args, mode, k)
+    return {"value": allc["value"], "unit": "cell-dir updates/s", "cores": k, "kind": "oracle",
+            "sample": f"{k} instances (seeds 20000-{20000 + k - 1}) of the {args.n}x{args.n} "
+                      f"lattice, {args.nphi} directions, {mode}, FP64, tol {args.eps:g}, one oracle "
+                      f"process per host core started together: {sum(allc['sweeps'])} sweeps in "
+                      f"{allc['wall_s']:.1f}s wall{rom_note} (each process, untimed)",
+            "solves_per_s": allc["solves_per_s"], "one_core": one}
+
+
+# One oracle instance per host process, for the all-cores CPU baseline: builds its inputs and
+# (ROMSAD) its own correction ROM untimed, reports "ready", waits for a line on stdin, then times
+# its solve.  Runs the oracle only (numpy/scipy and the oracle's C sweep); it never touches the GPU.
+CPU_WORKER = r"""
+import json, sys, time
+cfg = json.loads(sys.argv[1])
+sys.path.insert(0, cfg["root"])
+import rte_workloads as W
+from oracle.problem import discretize
+from oracle.sisa import sisa
+from oracle import rom as orom
+plane = W.c2_lattice([cfg["seed"]], n=cfg["n"], n_phi=cfg["nphi"])
+d = discretize(plane, 0)
+rom = None
+if cfg["mode"] == "romsad":
+    train = W.c2_lattice([30000 + i for i in range(cfg["train"])], n=cfg["n"], n_phi=cfg["nphi"])
+    discs = [discretize(train, b) for b in range(train.B)]
+    rom = orom.build_correction_rom(discs, orom.plane_affine(discs[0]), orom.plane_psi,
+                                    window=cfg["window"], r=cfg["rank"], eps_train=cfg["eps_train"])
+print("ready", flush=True)
+sys.stdin.readline()
+t0 = time.perf_counter()
+res = sisa(d, cfg["mode"], eps=cfg["eps"], rom=rom, theta=cfg["theta"])
+dt = time.perf_counter() - t0
+print(json.dumps({"cd": d.nc * d.nv * res.n_sweep, "n_sweep": res.n_sweep, "s": dt}), flush=True)
+"""
+
+
+def host_cores():
+    """Host cores this process may use, capped at 16 (one GPU's share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_all_cores(args, mode, k, timeout_s=300.0):
+    """k oracle processes, one instance each (seeds 20000 .. 20000 + k - 1), started together
+    once every process has built its inputs: aggregate cell-direction updates/s over the wall
+    time from the start signal to the last finish."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = []
+    try:
+        for i in range(k):
+            cfg = {"root": ROOT, "seed": 20000 + i, "n": args.n, "nphi": args.nphi,
+                   "mode": "romsad" if mode == "romsad" else mode, "eps": args.eps,
+                   "theta": args.theta, "train": args.cpu_train, "window": args.window,
+                   "rank": args.rank, "eps_train": args.eps_train}
+            procs.append(subprocess.Popen([sys.executable, "-c", CPU_WORKER, json.dumps(cfg)],
+                                          stdin=subprocess.PIPE, stdout=subprocess.PIPE,
+                                          text=True, env=env))
+        for p in procs:
+            if p.stdout.readline().strip() != "ready":
+                raise RuntimeError("oracle worker failed before its solve")
+        t0 = time.perf_counter()
+        for p in procs:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+        res = [json.loads(p.stdout.readline()) for p in procs]
+        wall = time.perf_counter() - t0
+        for p in procs:
+            p.wait(timeout=timeout_s)
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+    cd = sum(r["cd"] for r in res)
+    return {"value": cd / wall, "wall_s": wall, "solves_per_s": k / wall,
+            "sweeps": [r["n_sweep"] for r in res]}
 
 
 def sweep_source_hash():
@@ -280,6 +360,8 @@ def main():
     ap.add_argument("--baseline-instances", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-train", type=int, default=4)
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="oracle processes of the CPU baseline (0: the host's cores, at most 16)")
     ap.add_argument("--no-f-form", action="store_true")
     ap.add_argument("--pgmres-instances", type=int, default=64,
                     help="instances of the batch solved by DSA-preconditioned GMRES (0: skip)")
