@@ -4,9 +4,22 @@ import sys
 import numpy as np
 
 
+_capman = None
+
+
+def set_capture_manager(capman):
+    global _capman
+    _capman = capman
+
+
 def say(*a):
-    """Print and flush the case name before a GPU step (so a fault names its case)."""
-    print(*a, flush=True)
+    """Print and flush the case name before a GPU step (so a fault names its case).  Under
+    pytest the line bypasses output capture, so a long test shows its progress as it runs."""
+    if _capman is not None:
+        with _capman.global_and_fixture_disabled():
+            print(*a, flush=True)
+    else:
+        print(*a, flush=True)
     sys.stdout.flush()
 
 
