@@ -707,16 +707,29 @@ __device__ __forceinline__ void p_cell(const double *xv, int nvx, int i, int j, 
 template <typename TZ>
 __device__ __forceinline__ double pt_vertex(const TZ *rdg, int nx, int ny, int x, int y,
                                             double sqa) {
-    double s = 0.0;
+    // the (up to four) cells' values are loaded before the sum: a missing cell reads cell (0, 0)
+    // and a select leaves it out; the sum keeps its order and its terms
+    double rv[4][4];
+    bool ok[4];
+#pragma unroll
     for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
         for (int cx = 0; cx < 2; ++cx) {
             const int i = x - 1 + cx, j = y - 1 + cy;     // cell; the vertex is its corner (1-cx, 1-cy)
-            if (i < 0 || j < 0 || i >= nx || j >= ny) continue;
+            const int k = cy * 2 + cx;
+            ok[k] = i >= 0 && j >= 0 && i < nx && j < ny;
+            load4(rdg, ok[k] ? (long long)j * nx + i : 0LL, rv[k]);
+        }
+    double s = 0.0;
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+            const int k = cy * 2 + cx;
             const double sx = cx == 0 ? 1.0 : -1.0;       // corner a = 1 - cx: sign +1 if a == 1
             const double sy = cy == 0 ? 1.0 : -1.0;
-            double r[4];
-            load4(rdg, (long long)j * nx + i, r);
-            s += sqa * (0.25 * r[0] + sx * r[1] / (4.0 * kS3) + sy * r[2] / (4.0 * kS3) + sx * sy * r[3] / 12.0);
+            const double *r = rv[k];
+            s = ok[k] ? s + sqa * (0.25 * r[0] + sx * r[1] / (4.0 * kS3) + sy * r[2] / (4.0 * kS3) + sx * sy * r[3] / 12.0) : s;
         }
     return s;
 }
@@ -786,17 +799,25 @@ __device__ __forceinline__ TS *st_of(TS *S, int b, long long nv) {
 template <typename TS>
 __device__ __forceinline__ double stencil_apply(const TS *Sb, const double *x, VG g, int vx,
                                                 int vy) {
+    // the nine (coefficient, value) pairs are loaded before the sum: a neighbour outside the
+    // grid reads the vertex itself and a select leaves it out, so no load waits behind a branch;
+    // the sum keeps its order and its terms
     const TS *st = Sb + (long long)vy * g.nvx + vx;
-    double s = 0.0;
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = vy + dy;
-        if (yy < 0 || yy >= g.nvy) continue;
+    double cv[9], xv[9];
+    bool ok[9];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-            const int xx = vx + dx;
-            if (xx < 0 || xx >= g.nvx) continue;
-            s += (double)st[((dy + 1) * 3 + dx + 1) * g.nv] * x[(long long)yy * g.nvx + xx];
+            const int k = (dy + 1) * 3 + dx + 1;
+            const int yy = vy + dy, xx = vx + dx;
+            ok[k] = yy >= 0 && yy < g.nvy && xx >= 0 && xx < g.nvx;
+            cv[k] = (double)st[k * g.nv];
+            xv[k] = x[ok[k] ? (long long)yy * g.nvx + xx : (long long)vy * g.nvx + vx];
         }
-    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s = ok[k] ? s + cv[k] * xv[k] : s;
     return s;
 }
 
@@ -833,16 +854,27 @@ __global__ void mg_vrestrict_kernel(const int *state, VG gf, const double *rf, V
     if (v >= gc.nv) return;
     const int X = (int)(v % gc.nvx), Y = (int)(v / gc.nvx);
     const double *r = rf + (size_t)b * gf.nv;
-    double s = 0.0;
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int y = 2 * Y + dy;
-        if (y < 0 || y >= gf.nvy) continue;
+    // the nine fine values are loaded before the sum (a point outside the grid reads the centre
+    // and a select leaves it out); the sum keeps its order and its terms
+    double rv[9];
+    bool ok[9];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-            const int x = 2 * X + dx;
-            if (x < 0 || x >= gf.nvx) continue;
-            s += (dx == 0 ? 1.0 : 0.5) * (dy == 0 ? 1.0 : 0.5) * r[(long long)y * gf.nvx + x];
+            const int k = (dy + 1) * 3 + dx + 1;
+            const int y = 2 * Y + dy, x = 2 * X + dx;
+            ok[k] = y >= 0 && y < gf.nvy && x >= 0 && x < gf.nvx;
+            rv[k] = r[ok[k] ? (long long)y * gf.nvx + x : (long long)(2 * Y) * gf.nvx + 2 * X];
         }
-    }
+    double s = 0.0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int k = (dy + 1) * 3 + dx + 1;
+            s = ok[k] ? s + (dx == 0 ? 1.0 : 0.5) * (dy == 0 ? 1.0 : 0.5) * rv[k] : s;
+        }
     bc[(size_t)b * gc.nv + v] = s;
     if (xc) {
         const double wd = st_of(Sc, b, gc.nv)[9 * gc.nv + v];
