@@ -1169,18 +1169,56 @@ __global__ void mg_vpost1_kernel(const int *state, VG g, const float *S, const d
     const double *cb = xc + (size_t)b * gc.nv;
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
     const float *st = Sb + v;
-    double sx3 = 0.0;
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = vy + dy;
-        if (yy < 0 || yy >= g.nvy) continue;
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int xx = vx + dx;
-            if (xx < 0 || xx >= g.nvx) continue;
-            const long long w = (long long)yy * g.nvx + xx;
-            sx3 += st[((dy + 1) * 3 + dx + 1) * g.nv] * (x2[o + w] + prolong_at(cb, gc, xx, yy));
+    // Every load is issued before the arithmetic.  The coarse values that the prolongation at
+    // the nine neighbours reads all lie in the 3 x 3 coarse patch from (PX, PY) = ((vx - 1) >> 1,
+    // (vy - 1) >> 1): for a fine offset d the two coarse columns (X0, X1) are patch columns
+    // kP0/kP1[d + 1] of an even vx and kQ0/kQ1[d + 1] of an odd one (rows likewise).  Patch
+    // entries outside the coarse grid are clamped in and used only by neighbours outside the
+    // fine grid, which a select leaves out of the sum; such a neighbour's x2 reads the centre.
+    constexpr int kP0[3] = {0, 1, 1}, kP1[3] = {1, 1, 2}, kQ0[3] = {0, 0, 1}, kQ1[3] = {0, 1, 1};
+    const int PX = (vx - 1) >> 1, PY = (vy - 1) >> 1;
+    const bool ex = (vx & 1) == 0, ey = (vy & 1) == 0;
+    double cp[3][3], xn[9];
+    float cv[9];
+    bool ok[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int Y = min(max(PY + r, 0), gc.nvy - 1), X = min(max(PX + q, 0), gc.nvx - 1);
+            cp[r][q] = cb[(long long)Y * gc.nvx + X];
         }
-    }
-    const double x3 = x2[o + v] + prolong_at(cb, gc, vx, vy);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int k = (dy + 1) * 3 + dx + 1;
+            const int yy = vy + dy, xx = vx + dx;
+            ok[k] = yy >= 0 && yy < g.nvy && xx >= 0 && xx < g.nvx;
+            cv[k] = st[k * g.nv];
+            xn[k] = x2[o + (ok[k] ? (long long)yy * g.nvx + xx : v)];
+        }
+    auto pick = [&](int re, int ro, int ce, int co) -> double {
+        const double e = ex ? cp[re][ce] : cp[re][co];
+        const double d = ex ? cp[ro][ce] : cp[ro][co];
+        return ey ? e : d;
+    };
+    double sx3 = 0.0, x3 = 0.0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int k = (dy + 1) * 3 + dx + 1;
+            const int a = dx + 1, c = dy + 1;
+            // prolong_at's sum (Y0 X0, Y0 X1, Y1 X0, Y1 X1) on the patch values
+            const double pv = 0.25 * (pick(kP0[c], kQ0[c], kP0[a], kQ0[a]) +
+                                       pick(kP0[c], kQ0[c], kP1[a], kQ1[a]) +
+                                       pick(kP1[c], kQ1[c], kP0[a], kQ0[a]) +
+                                       pick(kP1[c], kQ1[c], kP1[a], kQ1[a]));
+            const double xv = xn[k] + pv;
+            if (k == 4) x3 = xv;
+            sx3 = ok[k] ? sx3 + cv[k] * xv : sx3;
+        }
     x4[o + v] = x3 + Sb[9 * g.nv + v] * (bv[o + v] - sx3);
 }
 
