@@ -22,6 +22,7 @@
 //     and the volume term 12 D/h^2 on the dofs of degree 1 in that direction, plus sigma_a.
 //     Per-instance scalars are re-derived by every block from fixed-order partial sums, so no
 //     grid-wide synchronization is needed and the result does not depend on block scheduling.
+#include <type_traits>
 #include <algorithm>
 
 #include "rte_internal.h"
@@ -339,6 +340,60 @@ __device__ __forceinline__ void binv_apply(const MipArgs &a, int b, long long ce
     z[1] = m01 * r[0] + m11 * r[1] + m12 * r[2] + m13 * r[3];
     z[2] = m02 * r[0] + m12 * r[1] + m22 * r[2] + m23 * r[3];
     z[3] = m03 * r[0] + m13 * r[1] + m23 * r[2] + m33 * r[3];
+}
+
+// y = A x at cell (i,j) with every load (the five cells' x and the coefficients) issued before
+// the arithmetic: a missing neighbour reads the cell itself, and its coupling is applied to zero
+// (its coefficients are the cell's own, finite, so the term vanishes).  No load waits behind a
+// boundary branch, at the price of registers: used where the register count stays within the
+// occupancy the kernel had (the mixed-precision DG residual of the multigrid).
+template <typename TC, typename F>
+__device__ void mip_apply_hoisted(const MipArgs &a, int b, int i, int j, F xat, double y[4]) {
+    const long long cell = (long long)j * a.nx + i;
+    const bool hl = i > 0, hr = i + 1 < a.nx, hd = j > 0, hu = j + 1 < a.ny;
+    const long long cl = hl ? cell - 1 : cell, cr = hr ? cell + 1 : cell;
+    const long long cd = hd ? cell - a.nx : cell, cu = hu ? cell + a.nx : cell;
+    const double sa = cfv<TC>(a, b, 0, cell), Dx = cfv<TC>(a, b, 1, cell), Dy = cfv<TC>(a, b, 2, cell);
+    const double Dxl = cfv<TC>(a, b, 1, cl), kal = cfv<TC>(a, b, 3, cl);
+    const double Dxr = cfv<TC>(a, b, 1, cr), kar = cfv<TC>(a, b, 3, cell);
+    const double Dyd = cfv<TC>(a, b, 2, cd), kad = cfv<TC>(a, b, 4, cd);
+    const double Dyu = cfv<TC>(a, b, 2, cu), kau = cfv<TC>(a, b, 4, cell);
+    double xc[4], xl[4], xr[4], xd[4], xu[4], xn[4], M[4];
+    xat(cell, xc);
+    xat(cl, xl);
+    xat(cr, xr);
+    xat(cd, xd);
+    xat(cu, xu);
+    const double vx = a.vol_x * Dx, vy = a.vol_y * Dy;
+    const double tx = a.th_x * Dx, ty = a.th_y * Dy;
+    y[0] = sa * xc[0];
+    y[1] = (sa + vx) * xc[1];
+    y[2] = (sa + vy) * xc[2];
+    y[3] = (sa + vx + vy) * xc[3];
+    {
+        const double k = hl ? kal * a.ihx : fmax(a.kx, kMipC * Dx * a.ihx) * a.ihx;
+        face_minus(k, tx, M); addx(M, xc, y);
+        for (int q = 0; q < 4; ++q) xn[q] = hl ? xl[q] : 0.0;
+        couple_pm(k, a.th_x * Dxl, tx, M); addx(M, xn, y);
+    }
+    {
+        const double k = hr ? kar * a.ihx : fmax(a.kx, kMipC * Dx * a.ihx) * a.ihx;
+        face_plus(k, tx, M); addx(M, xc, y);
+        for (int q = 0; q < 4; ++q) xn[q] = hr ? xr[q] : 0.0;
+        couple_mp(k, tx, a.th_x * Dxr, M); addx(M, xn, y);
+    }
+    {
+        const double k = hd ? kad * a.ihy : fmax(a.ky, kMipC * Dy * a.ihy) * a.ihy;
+        face_minus(k, ty, M); addy(M, xc, y);
+        for (int q = 0; q < 4; ++q) xn[q] = hd ? xd[q] : 0.0;
+        couple_pm(k, a.th_y * Dyd, ty, M); addy(M, xn, y);
+    }
+    {
+        const double k = hu ? kau * a.ihy : fmax(a.ky, kMipC * Dy * a.ihy) * a.ihy;
+        face_plus(k, ty, M); addy(M, xc, y);
+        for (int q = 0; q < 4; ++q) xn[q] = hu ? xu[q] : 0.0;
+        couple_mp(k, ty, a.th_y * Dyu, M); addy(M, xn, y);
+    }
 }
 
 // y = A x at cell (i,j), with x read through a functor (to form p = z + beta p_old on the fly);
@@ -761,7 +816,10 @@ __global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const
     const size_t base = (size_t)b * a.ncell;
     auto zat = [&](long long c, double v[4]) { load4(z, base + c, v); };
     double y[4], rv[4];
-    mip_apply<TZ>(a, b, (int)(cell % a.nx), (int)(cell / a.nx), zat, y);
+    if constexpr (std::is_same<TZ, float>::value)
+        mip_apply_hoisted<TZ>(a, b, (int)(cell % a.nx), (int)(cell / a.nx), zat, y);
+    else
+        mip_apply<TZ>(a, b, (int)(cell % a.nx), (int)(cell / a.nx), zat, y);
     load4(r, base + cell, rv);
     for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
     store4(t, base + cell, y);
