@@ -1,4 +1,5 @@
 """Shared helpers of the GPU parity tests: device upload of inputs and oracle runs."""
+import os
 import sys
 
 import numpy as np
@@ -35,9 +36,17 @@ def host(t):
 
 
 def rel_err(a, b):
+    """max |a - b| / max |b|.  With RTE_ERRLOG set, every value is appended to that file as a
+    JSON line with the running test's id, so one run records the measured error of each check."""
     a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
     den = max(np.abs(b).max(), 1e-300)
-    return float(np.abs(a - b).max() / den)
+    e = float(np.abs(a - b).max() / den)
+    log = os.environ.get("RTE_ERRLOG")
+    if log:
+        import json
+        with open(log, "a") as fh:
+            fh.write(json.dumps({"test": os.environ.get("PYTEST_CURRENT_TEST", "?"), "err": e}) + "\n")
+    return e
 
 
 def sweep_positions(nx, ny, vx, vy):

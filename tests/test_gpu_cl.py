@@ -33,7 +33,7 @@ def test_cl_sweep_matches_oracle(R, precision):
     rs = torch.zeros((plane.B, P.ndof), dtype=torch.float64, device="cuda")
     rte.sweep(P, dev(rho_in), rho_star_out=rs, precision=precision)
     rs = host(rs)
-    tol = 1e-12 if precision == "fp64" else 2e-5
+    tol = 1e-12 if precision == "fp64" else 2e-6
     for b, d in enumerate(discs):
         assert rel_err(rs[b], d.sweep(rho_in[b])[0]) < tol
 
@@ -54,7 +54,7 @@ def test_cl_si_dsa_matches_oracle(R, family):
     for b in range(plane.B):
         ref = sisa(discretize(plane, b), "si_dsa", eps=1e-10)
         assert res.n_sweep[b] == ref.n_sweep
-        assert rel_err(rho[b], ref.rho) < 1e-11
+        assert rel_err(rho[b], ref.rho) < 1e-12
 
 
 def test_cl_homogeneous_romsad_matches_oracle(R):
@@ -80,6 +80,6 @@ def test_cl_homogeneous_romsad_matches_oracle(R):
         ref = sisa(d, "romsad", eps=1e-10, rom=rom, theta=5)
         assert res.n_sweep[b] == ref.n_sweep
         assert list(res.kind[b, :res.n_sweep[b] - 1]) == ref.kinds
-        assert rel_err(rho[b], ref.rho) < 1e-11
+        assert rel_err(rho[b], ref.rho) < 1e-12
         # the paper's observation on this family: ROMSAD needs far fewer sweeps than SI-DSA
         assert ref.n_sweep < sisa(d, "si_dsa", eps=1e-10).n_sweep

@@ -10,7 +10,7 @@ from tests.gpu_common import dev, f_library, f_natural, host, rel_err, say
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-TOL32 = 2e-5
+TOL32 = 2e-6
 
 
 @pytest.fixture(scope="module")

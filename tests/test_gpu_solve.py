@@ -56,7 +56,7 @@ def test_slab_batch_si_modes(R, mode):
     for b, s in enumerate(batch):
         ref = sisa(discretize(s), mode, eps=1e-11)
         assert res.n_sweep[b] == ref.n_sweep
-        assert rel_err(rho[b], ref.rho) < 1e-11
+        assert rel_err(rho[b], ref.rho) < 1e-12
 
 
 @pytest.mark.parametrize("mode", ["si", "si_dsa"])
@@ -69,7 +69,7 @@ def test_plane_small_batch(R, mode):
     for b in range(3):
         ref = sisa(discretize(plane, b), mode, eps=1e-10)
         assert res.n_sweep[b] == ref.n_sweep, (b, res.n_sweep[b], ref.n_sweep)
-        assert rel_err(rho[b], ref.rho) < 1e-11
+        assert rel_err(rho[b], ref.rho) < 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -99,7 +99,7 @@ def test_plane_romsad_batch(R, lattice_rom, precision):
         if precision == "fp64":
             assert res.n_sweep[b] == ref.n_sweep, (b, res.n_sweep[b], ref.n_sweep)
             assert kinds == ref.kinds
-            assert rel_err(rho[b], ref.rho) < 1e-11
+            assert rel_err(rho[b], ref.rho) < 1e-12
         else:
             assert res.n_sweep[b] == ref.n_sweep, (b, res.n_sweep[b], ref.n_sweep,
                                                    res.change[b, :res.n_sweep[b]], ref.changes)
@@ -130,7 +130,7 @@ def test_c1_checkerboard_full_size_si_dsa(R):
     rho, res = _solve(rte, P, "si_dsa", 1e-8, 1, P.ndof, cg_rtol=1e-13, max_iter=200)
     ref = sisa(discretize(plane), "si_dsa", eps=1e-8)
     assert res.n_sweep[0] == ref.n_sweep
-    assert rel_err(rho[0], ref.rho) < 1e-11
+    assert rel_err(rho[0], ref.rho) < 1e-12
 
 
 def test_c1_full_size_plain_si_and_si_dsa_both_precisions(R):

@@ -175,3 +175,44 @@ def test_table2_cross_regime_ranks():
         sv = np.linalg.svd(np.stack(M, 1), compute_uv=False)
         got = [R.pod_rank(sv, e) for e in gold["eps_pod"]]
         assert got == gold[key], (key, got)
+
+
+def _two_material_snapshots(mu):
+    d = discretize(W.two_material(*mu))
+    r = sisa(d, "si_dsa", eps=1e-12, relative=False, want_f=True, window=5)
+    assert r.converged
+    hist = [np.zeros_like(r.f)] + r.window
+    return r.f.reshape(-1), [(r.f - hist[l]).reshape(-1) for l in range(min(r.n_sweep, 5))]
+
+
+@pytest.mark.slow
+def test_table4_two_material_ranks():
+    """Paper Table 4 caption: r_p = 21/44/53 and r_c = 49/101/123 (window 3), 54/120/147
+    (window 5) for eps_POD = 1e-6/1e-9/1e-10 on the two-material training set (451 SI-DSA
+    solves).  The oracle's spectrum gives ranks one above the printed r_p (22/45/54) and 1-3 above
+    the printed r_c: at the printed r_p the energy ratio it drops, 1 - sum_{k<=r} l_k / sum l_k,
+    lies 3%, 15% and 18% above the threshold (1.03e-6, 1.15e-9, 1.18e-10), so the printed ranks
+    sit just past the oracle's.  The pin is that closeness: every printed rank within one (r_p)
+    or three (r_c) of the oracle's, and the energy dropped at the printed r_p within 25% of
+    eps_POD.  Table 2's uniform-mesh ranks are reproduced exactly (test above); this problem's
+    non-uniform mesh is where the two differ, and no reading of the basis scaling or angular
+    weighting tried (orthonormal per cell, reference-cell, sqrt(w_j)) lands on the printed
+    values."""
+    from multiprocessing import Pool
+    gold = json.load(open(os.path.join(GOLDEN, "table4_two_material_ranks.json")))
+    with Pool(min(8, os.cpu_count() or 1)) as pool:
+        out = pool.map(_two_material_snapshots, W.two_material_training())
+    F = np.stack([o[0] for o in out], 1)
+    sv = np.linalg.svd(F, compute_uv=False)
+    got = [R.pod_rank(sv, e) for e in gold["eps_pod"]]
+    assert all(abs(g - p) <= 1 for g, p in zip(got, gold["r_p"])), (got, gold["r_p"])
+    for e, rp in zip(gold["eps_pod"], gold["r_p"]):
+        dropped = R.pod_dropped(sv, rp)
+        assert e <= dropped < 1.25 * e, (e, rp, dropped)
+    for w, key in ((3, "r_c_window3"), (5, "r_c_window5")):
+        dF = np.stack([c for o in out for c in o[1][:w]], 1)
+        svc = np.linalg.svd(dF, compute_uv=False)
+        got = [R.pod_rank(svc, e) for e in gold["eps_pod"]]
+        assert all(abs(g - p) <= 3 for g, p in zip(got, gold[key])), (key, got, gold[key])
+    # the paper's ordering r_p <= r_c(3) <= r_c(5) at every tolerance
+    assert all(a <= b for a, b in zip(gold["r_p"], gold["r_c_window3"]))
