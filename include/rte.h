@@ -233,7 +233,9 @@ typedef struct {
  *   rho_inout  device [B][N_DOF]: initial guess in, rho^(l,*) of the stopping iteration out
  *   psi        device [B][m] (ROMSAD only)
  *   f_out      device angular flux of the last sweep (layout above), or NULL
- * Returns RTE_ENOCONV if any instance hit max_iter (per-instance status in stats). */
+ * Returns RTE_ENOCONV if any instance hit max_iter (per-instance status in stats), RTE_ECG
+ * (before RTE_ENOCONV) if a diffusion CG stopped at cg_maxit or on a non-finite residual; the
+ * statistics are filled in either case. */
 int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
                    const rte_solve_opts *opts, double *rho_inout, void *f_out,
                    rte_solve_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream);

@@ -635,9 +635,11 @@ __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, 
     const bool done = !(rr > rtol2 * bb);     // also stops on NaN
     if (done || it > maxit) {
         if (blk.x == 0 && threadIdx.x == 0) {
-            state[b] = done && rr == rr ? 2 : 3;
+            const int st = done && rr == rr ? 2 : 3;
+            state[b] = st;
             iters[b] = it - 1;
             atomicSub(n_running, 1);
+            if (st == 3) atomicAdd(n_running + 1, 1);
         }
         return;
     }
@@ -725,10 +727,11 @@ __global__ void cg_finish_kernel(long long ndof, const double *x, double *delta,
     if (t == 0 && total) atomicAdd(total, (unsigned long long)iters[b]);
 }
 
-// a CG call's start: no instance running yet, and the call's squared relative tolerance
+// a CG call's start: no instance running or failed yet, and the call's squared relative tolerance
 __global__ void cg_begin_kernel(int *n_running, double *tol2, double rtol2) {
     if (threadIdx.x == 0) {
-        *n_running = 0;
+        n_running[0] = 0;
+        n_running[1] = 0;
         *tol2 = rtol2;
     }
 }
@@ -805,8 +808,10 @@ __global__ void mg_resid_dg_kernel(MipArgs a, int *state, const double *r, const
         const double rr = sum_parts(part + ((size_t)b * 5 + 3) * a.nblk, a.nblk);
         if (!(rr > tol2[0] * bb)) {
             if (blk.x == 0 && threadIdx.x == 0) {
-                state[b] = rr == rr ? 2 : 3;
+                const int st = rr == rr ? 2 : 3;
+                state[b] = st;
                 atomicSub(n_running, 1);
+                if (st == 3) atomicAdd(n_running + 1, 1);
             }
             return;
         }

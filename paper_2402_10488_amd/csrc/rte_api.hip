@@ -92,7 +92,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
             L.cg.part = c.take<double>(B * 5 * (size_t)L.cg.nblk);
             L.cg.iters = c.take<int>(B);
             L.cg.state = c.take<int>(B);
-            L.cg.n_running = c.take<int>(1);
+            L.cg.n_running = c.take<int>(2);
             L.cg.tol2 = c.take<double>(1);
             L.cg.cf = c.take<double>(B * (size_t)p->ncell * 5);
             L.cg.binv = c.take<float>(B * (size_t)p->ncell * 10);
@@ -613,19 +613,20 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
     // already finds every instance stopped, the next solve looks one iteration earlier, so the
     // look follows iteration counts that shrink as well as grow.
     const int first = L.cg_look > 0 ? L.cg_look : 8;
-    int running = 1;
+    int counts[2] = {1, 0};       // running, failed
     for (int it = 1; it <= maxit + 1; ++it) {
         HIPCHK(launch_cg_iteration(p, L.cg, it, rtol, maxit, s));
         if (it >= first || it == maxit + 1) {
-            HIPCHK(hipMemcpyAsync(&running, L.cg.n_running, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(counts, L.cg.n_running, sizeof(counts), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            if (running == 0) {
+            if (counts[0] == 0) {
                 L.cg_look = it == first ? std::max(2, it - 1) : it;
                 break;
             }
         }
     }
-    if (failed) *failed = running != 0;
+    // iteration maxit + 1 stops every instance still running and counts it as failed
+    if (failed) *failed = counts[0] != 0 || counts[1] != 0;
     HIPCHK(launch_cg_finish(p, L.cg, delta, iters_out, L.cg_total, s));
     return RTE_OK;
 }
@@ -735,7 +736,7 @@ int finish_stats(const rte_problem *p, const Layout &L, int max_iter, int iterat
         stats->cg_iterations = (long long)cg_total;
         stats->iterations = iterations;
     }
-    if (cg_failed && rc == RTE_OK) rc = RTE_ECG;
+    if (cg_failed) rc = RTE_ECG;      // an inexact correction outranks an iteration limit
     return rc;
 }
 

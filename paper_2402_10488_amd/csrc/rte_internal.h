@@ -292,7 +292,8 @@ struct CGSpace {
     double *scal;                      // [B][8] per-instance scalars
     int *iters;                        // [B]
     int *state;                        // [B] 0 idle, 1 running, 2 converged, 3 failed
-    int *n_running;                    // [1]
+    int *n_running;                    // [2] instances still iterating; instances that failed
+                                       // (limit reached or a NaN) in the current call
     double *tol2;                      // [1] the call's squared relative tolerance
     int nblk;                          // blocks per instance
     int zf32;                          // 1: z and the multigrid residual t held in FP32 (mixed

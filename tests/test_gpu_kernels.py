@@ -11,6 +11,10 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 2e-6
+# The FP32 angular flux element by element, relative to its largest value: FP32 rounding gathers
+# along upwind paths of up to 200 cells here; measured at most 2.42e-6 (5 x 200 cells), asserted
+# at twice that.  Densities stay within TOL32 (measured at most 1.4e-6).
+TOL32_F = 5e-6
 
 
 @pytest.fixture(scope="module")
@@ -55,6 +59,7 @@ def test_sweep2d_matches_oracle(R, nx, ny, nphi, B, dg, wpb, precision):
     rs = torch.zeros((B, P.ndof), dtype=torch.float64, device="cuda")
     rte.sweep(P, dev(rho_in), f_out=fd, rho_star_out=rs, precision=precision)
     tol = TOL64 if precision == "fp64" else TOL32
+    tol_f = TOL64 if precision == "fp64" else TOL32_F
     rs, f = host(rs), host(fd)
     f_or_all = []
     for b, d in enumerate(discs):
@@ -62,7 +67,7 @@ def test_sweep2d_matches_oracle(R, nx, ny, nphi, B, dg, wpb, precision):
         f_or_all.append(f_or)
         assert rel_err(rs[b], r_or) < tol, (b, rel_err(rs[b], r_or))
         fb = f_natural(f[b], P)
-        assert rel_err(fb, f_or) < tol, (b, rel_err(fb, f_or))
+        assert rel_err(fb, f_or) < tol_f, (b, rel_err(fb, f_or))
     # the library's own conversion to natural order moves values exactly
     fn = host(rte.f_natural(P, fd, precision))
     assert np.array_equal(fn, np.stack([f_natural(f[b], P) for b in range(B)]))
@@ -243,3 +248,25 @@ def test_invalid_arguments_rejected(R):
         rte.sweep(P, torch.zeros(P.ndof, dtype=torch.float64, device="cuda"),
                   rho_star_out=torch.zeros(P.ndof, dtype=torch.float64, device="cuda"), ws=tiny)
     assert e.value.status == rte.RTE_ENOMEM
+
+
+def test_cg_limit_reports_ecg(R):
+    """A diffusion CG that reaches its iteration limit is reported (RTE_ECG) by the correction
+    call and by the solve, whose instances all still stop (here at max_iter)."""
+    import torch
+    rte, problems = R
+    plane = W.random_plane(41, nx=16, ny=16, n_phi=8, B=2, Lx=10.0, Ly=10.0)
+    say("cg limit: dsa_correct with cg_maxit = 1")
+    P = problems.plane_problem(plane)
+    rng = np.random.default_rng(2)
+    rs, rp = dev(rng.uniform(0, 1, (2, P.ndof))), dev(rng.uniform(0, 1, (2, P.ndof)))
+    delta = torch.zeros((2, P.ndof), dtype=torch.float64, device="cuda")
+    with pytest.raises(rte.RteError) as e:
+        rte.dsa_correct(P, rs, rp, delta, cg_rtol=1e-14, cg_maxit=1)
+    assert e.value.status == rte.RTE_ECG
+    rte.dsa_correct(P, rs, rp, delta, cg_rtol=1e-14, cg_maxit=5000)      # converges: no error
+    say("cg limit: sisa_solve with cg_maxit = 1")
+    rho = torch.zeros((2, P.ndof), dtype=torch.float64, device="cuda")
+    res = rte.sisa_solve(P, rho, mode="si_dsa", eps=1e-10, cg_rtol=1e-14, cg_maxit=1, max_iter=6,
+                         raise_on_error=False)
+    assert res.status == rte.RTE_ECG, res.status
