@@ -180,6 +180,22 @@ int rte_workspace_size(const rte_problem *p, rte_mode mode, const rte_rom *rom,
 int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
               int zero_inflow, rte_precision prec, void *ws, size_t ws_bytes, rte_stream_t stream);
 
+/* rte_sweep without a workspace argument, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The sweep's
+ * input block and partial densities live in a library-owned device array of
+ * RTE_NOALLOC_SCRATCH_BYTES per GPU, held from the library's first use on that GPU until the
+ * process ends; the call itself allocates and frees nothing.  Arguments, layouts and results are
+ * those of rte_sweep (the same kernels run).
+ *   Returns RTE_ENOMEM, before any device work, when the problem needs more scratch than
+ *   RTE_NOALLOC_SCRATCH_BYTES (the rte_workspace_size of mode RTE_SI, max_iter 1, for prec;
+ *   one 128 x 128 instance with 64 directions needs about 11 MB in FP64).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (different
+ * streams, or host threads) race and must be serialized by the caller. */
+#define RTE_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int rte_sweep_noalloc(const rte_problem *p, const double *rho_in, void *f_out,
+                      double *rho_star_out, int zero_inflow, rte_precision prec,
+                      rte_stream_t stream);
+
 /* Quadrature reduction rho = sum_j w_j f_j (definition under eq. (dg_matrix_vec)).
  *   f     device angular flux in the layout above, double or float per prec;
  *   rho_out device [B][N_DOF] */

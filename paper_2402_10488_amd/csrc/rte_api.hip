@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -755,6 +756,65 @@ int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *r
     const int fp32 = prec == RTE_MIXED;
     HIPCHK(launch_source(p, rho_in, L.src, nullptr, fp32, s));
     return do_sweep(p, L, L.src, f_out, rho_star_out, nullptr, nullptr, zero_inflow, fp32, s);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device memory of rte_sweep_noalloc: the sweep's input block and partial densities live here
+// instead of in a caller workspace.  Each device that loads the library holds its own copy for
+// the life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name on the host is a stand-in, not
+// a device address).  Nothing in it has to start at zero: the source kernel writes the whole
+// input block and every partial slot is written in full by the sweep before it is reduced.
+static __device__ __align__(256) unsigned char scratch[RTE_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+struct ScratchAddr {
+    std::once_flag once;
+    void *ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+ScratchAddr g_scratch_addr[kMaxScratchDevices];
+
+// the current device's address of `scratch`, looked up once per device with that device current
+int scratch_address(void **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return RTE_EUNSUPPORTED;
+    ScratchAddr &a = g_scratch_addr[dev];
+    std::call_once(a.once, [&a] {
+        void *ptr = nullptr;
+        a.err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (a.err == hipSuccess) a.ptr = ptr;
+    });
+    if (a.err != hipSuccess) return device_error(a.err);
+    if (!a.ptr) return RTE_EDEVICE;
+    *out = a.ptr;
+    return RTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rte_sweep_noalloc(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
+                      int zero_inflow, rte_precision prec, rte_stream_t stream) {
+    if (!p || !rho_in || (!f_out && !rho_star_out)) return RTE_EINVAL;
+    if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
+    size_t need = 0;
+    {
+        Carver sizing(nullptr, 0);
+        carve(sizing, p, RTE_SI, nullptr, prec, 1);
+        need = sizing.off;
+    }
+    if (need > (size_t)RTE_NOALLOC_SCRATCH_BYTES) return RTE_ENOMEM;
+    void *ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    return rte_sweep(p, rho_in, f_out, rho_star_out, zero_inflow, prec, ws,
+                     (size_t)RTE_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int rte_scalar_flux(const rte_problem *p, const void *f, double *rho_out, rte_precision prec,

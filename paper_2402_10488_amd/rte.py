@@ -84,7 +84,7 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum",
             "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
             "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve", "rte_f_natural",
-            "rte_last_device_error"]
+            "rte_last_device_error", "rte_sweep_noalloc"]
 
 
 def _load():
@@ -118,6 +118,7 @@ def _load():
     L.rte_workspace_size.argtypes = [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_size_t)]
     L.rte_sweep.argtypes = [P, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
+    L.rte_sweep_noalloc.argtypes = [P, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
     L.rte_scalar_flux.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
     L.rte_f_natural.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
     L.rte_dsa_correct.argtypes = [P, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
@@ -305,6 +306,18 @@ def sweep(p: Problem, rho_in, f_out=None, rho_star_out=None, zero_inflow=False, 
     ws = ws if ws is not None else p.workspace("si", None, precision)
     _check(lib.rte_sweep(p.handle, _ptr(rho_in), _ptr(f_out), _ptr(rho_star_out), int(zero_inflow),
                          PRECISIONS[precision], _ptr(ws), ws.numel(), _stream()), "rte_sweep")
+
+
+def sweep_noalloc(p: Problem, rho_in, f_out=None, rho_star_out=None, zero_inflow=False,
+                  precision="fp64"):
+    """rte_sweep on the library's own per-device scratch array: no workspace, no allocation.
+    Calls on one GPU share that array and must not overlap."""
+    _check(lib.rte_sweep_noalloc(p.handle, _ptr(rho_in), _ptr(f_out), _ptr(rho_star_out),
+                                 int(zero_inflow), PRECISIONS[precision], _stream()),
+           "rte_sweep_noalloc")
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20      # RTE_NOALLOC_SCRATCH_BYTES of include/rte.h
 
 
 def f_shape(p: Problem):
