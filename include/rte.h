@@ -112,6 +112,19 @@ void rte_problem_destroy(rte_problem *p);
  * partial-density order. */
 int rte_problem_create_tuned(const rte_problem_desc *desc, int dg, int wpb, rte_problem **out);
 
+/* Autotuner measurement: times the 2D sweep (source prologue, sweep, partial-density reduction:
+ * one iteration's sweep of rte_sisa_solve; with f_out != NULL the angular flux is written too, as
+ * rte_sweep does) of the batch described by desc under each candidate schedule (dg[i], wpb[i]) of
+ * rte_problem_create_tuned.  ms_out[i] receives the average milliseconds per sweep over `reps`
+ * timed sweeps after `warmup` untimed ones (HIP events on the stream), or -1 for a candidate the
+ * library does not run as given (unknown values, or one the LDS budget would change).
+ *   rho_in   device [B][N_DOF] density swept;  f_out  device angular flux (layout above) or NULL
+ * A setup call, not a hot one: it creates a handle and allocates and frees a workspace per
+ * candidate, and synchronizes the stream.  2D only (RTE_EUNSUPPORTED otherwise). */
+int rte_tune_sweep(const rte_problem_desc *desc, rte_precision prec, int n_cand, const int *dg,
+                   const int *wpb, const double *rho_in, void *f_out, int warmup, int reps,
+                   double *ms_out, rte_stream_t stream);
+
 /* Selects the preconditioner of the 2D diffusion CG: on != 0 (default) the two-level
  * multigrid (block-Jacobi smoothing on the DG space, continuous-Q1 vertex-grid coarse space with
  * Galerkin operators, one V-cycle); on == 0 block-Jacobi alone.  Changes the workspace size; call
@@ -232,6 +245,16 @@ typedef struct {
     int cg_maxit;             /* diffusion CG iteration limit per correction */
     rte_precision precision;
     int poll_every;           /* host reads the active-instance count every poll_every iterations */
+    int graph_cg_iters;       /* 0: every kernel launched from the host, which reads the decision's
+                                 counts and the diffusion CG's running count as it goes.  > 0: one
+                                 outer iteration (sweep, reduction, stop test and switch, ROMSA and
+                                 diffusion correction for the instances that chose them, update) is
+                                 one HIP graph launch with no host read inside; the graph holds
+                                 min(cg_maxit, graph_cg_iters) CG iterations per correction, so an
+                                 instance needing more stops there and counts as a CG failure
+                                 (RTE_ECG).  The graph is captured on first use and kept by the
+                                 problem handle for the same workspace and arguments; the host
+                                 reads the active count every poll_every launches only. */
 } rte_solve_opts;
 
 /* Host-visible statistics (arrays supplied by the caller; any may be NULL). */

@@ -113,6 +113,7 @@ class PlaneDisc:
         self.G = plane.G[b].reshape(-1)[:, None] * load[None, :]        # [nc,4]
         self.g = np.asarray(plane.g[b], dtype=np.float64)
         self.block = plane.block.reshape(-1)
+        self.block_fields = getattr(plane, "block_fields", None)
         self.block_sigma_t = plane.block_sigma_t[b]
         self.block_sigma_s = plane.block_sigma_s[b]
         # the sweep's local matrix is V_j + sigma_t * mass; the C code adds sigma_t on the

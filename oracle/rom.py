@@ -39,7 +39,12 @@ class Affine:
 
 
 def plane_affine(disc) -> Affine:
-    """Block lattices: T_b = S_b = indicator of the dofs of material block b."""
+    """Block lattices: T_b = S_b = indicator of the dofs of material block b.  A medium given by
+    cell fields (sigma = sum_k coefficient_k field_k): T_k = S_k = the field on the diagonal."""
+    fields = getattr(disc, "block_fields", None)
+    if fields is not None:
+        diag = [sp.diags(np.repeat(np.asarray(f, np.float64).reshape(-1), 4)).tocsr() for f in fields]
+        return Affine(diag, diag)
     nb = int(disc.block.max()) + 1
     masks = [sp.diags(np.repeat((disc.block == b).astype(np.float64), 4)).tocsr() for b in range(nb)]
     return Affine(masks, masks)
@@ -145,6 +150,15 @@ def build_correction_rom(discs, affine, psi_fn, window=3, r=None, eps_pod=None,
                          eps_train=1e-10, relative=True, keep_full=False, dsa_factory=None,
                          first=0):
     dF = correction_snapshots(discs, window, eps_train, relative, dsa_factory, first)
+    return correction_rom_from_snapshots(dF, discs[0], affine, psi_fn, r, eps_pod, eps_train,
+                                         keep_full)
+
+
+def correction_rom_from_snapshots(dF, disc, affine, psi_fn, r=None, eps_pod=None,
+                                  eps_train=1e-10, keep_full=False):
+    """POD of given snapshot columns dF [N_v N_DOF, n_col] (thin SVD, Sec. 3.1), truncation at
+    rank r or by eq. (pod_truncation), and the reduced operators on the discretization ``disc``
+    (any instance: only its mesh and directions enter)."""
     U, sv, _ = np.linalg.svd(dF, full_matrices=False)
     if r is None:
         r = pod_rank(sv, eps_pod)
@@ -153,7 +167,7 @@ def build_correction_rom(discs, affine, psi_fn, window=3, r=None, eps_pod=None,
         r = min(r, U.shape[1])
         eps_eff = pod_dropped(sv, r)
     dU = np.ascontiguousarray(U[:, :r])
-    A0, At, As, U_rho, U_iso = reduced_operators(discs[0], dU, affine)
+    A0, At, As, U_rho, U_iso = reduced_operators(disc, dU, affine)
     return CorrectionROM(U_rho, U_iso, A0, At, As, sv, eps_eff, eps_train, psi_fn,
                          dU if keep_full else None)
 

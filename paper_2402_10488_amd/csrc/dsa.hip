@@ -717,14 +717,17 @@ __global__ void __launch_bounds__(kCgBlock) cg_update_kernel(MipArgs a, int it, 
 }
 
 __global__ void cg_finish_kernel(long long ndof, const double *x, double *delta, const int *state,
-                                 const int *iters, int *iters_out, unsigned long long *total, int B) {
+                                 const int *iters, int *iters_out, unsigned long long *total,
+                                 int *fails, int B) {
     const Blk blk = xcd_block();
     const long long t = (long long)blk.x * blockDim.x + threadIdx.x;
     const int b = blk.y;
-    if (state[b] == 0) return;
+    const int st = state[b];
+    if (st == 0) return;
     if (t < ndof) delta[(size_t)b * ndof + t] = x[(size_t)b * ndof + t];
     if (t == 0 && iters_out) iters_out[b] = iters[b];
     if (t == 0 && total) atomicAdd(total, (unsigned long long)iters[b]);
+    if (t == 0 && fails && st == 3) atomicAdd(fails, 1);
 }
 
 // a CG call's start: no instance running or failed yet, and the call's squared relative tolerance
@@ -1783,7 +1786,7 @@ hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delt
                             unsigned long long *total, hipStream_t s) {
     dim3 grid(blocks_for(p->ndof, 256), p->B);
     hipLaunchKernelGGL(cg_finish_kernel, grid, dim3(256), 0, s, p->ndof, c.x, delta, c.state,
-                       c.iters, iters_out, total, p->B);
+                       c.iters, iters_out, total, c.fails, p->B);
     return hipGetLastError();
 }
 

@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) rom_assemble_kernel(int B, int r, int m, 
 // singular -> status 1 and kind falls back to DSA (want -> 1).
 __global__ void __launch_bounds__(64) rom_solve_kernel(int B, int r, const double *yv,
                                                        const double *Av, int *kind, int want,
-                                                       int *status, double *dc) {
+                                                       int *status, double *dc, int *n_fallback) {
     __shared__ double A[64][65];
     __shared__ double y[64];
     __shared__ int piv_row;
@@ -208,6 +208,7 @@ __global__ void __launch_bounds__(64) rom_solve_kernel(int B, int r, const doubl
         if (i == 0) {
             if (status) status[b] = 1;
             if (kind) kind[b] = 1;           // this iteration falls back to DSA
+            if (n_fallback) atomicAdd(n_fallback, 1);
         }
         return;
     }
@@ -312,7 +313,8 @@ void launch_rom_system(const rte_problem *p, const rte_rom *rom, const double *p
     hipLaunchKernelGGL(rom_assemble_kernel, dim3(r + ablk, p->B), dim3(256), 0, s, p->B, r, rom->m,
                        w.nsplit, w.ypart, rom->d_A0, rom->d_A, psi, kind, want_kind, w.y, w.A);
     hipLaunchKernelGGL(rom_solve_kernel, dim3(p->B), dim3(64), 0, s, p->B, r, w.y, w.A,
-                       const_cast<int *>(kind), want_kind, status, w.dc);
+                       const_cast<int *>(kind), want_kind, status, w.dc,
+                       kind ? w.n_fallback : nullptr);
 }
 
 hipError_t launch_rom_initial_guess(const rte_problem *p, const rte_rom *rom, const double *psi,

@@ -2,9 +2,11 @@
 // iteration driver of Alg. 1 / Alg. 2.  Every arithmetic step runs in the kernels of
 // sweep.hip, iterate.hip, dsa.hip and rom.hip.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -46,6 +48,7 @@ struct Layout {
     RomSpace rom;
     int *rom_status;
     unsigned long long *cg_total;   // CG iterations summed over instances and calls
+    int *cg_fail;           // [1] diffusion CG failures (graph mode reads it at the end)
     int *flag;
     int *mask;              // [B] instances selected by rte_sisa_admit
     GmresSpace gm;          // DSA-preconditioned GMRES (rte_pgmres_solve)
@@ -78,6 +81,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     L.st.kinds = c.take<int>(B * (size_t)std::max(max_iter, 1));
     L.st.n_active = c.take<int>(3);
     L.cg_total = c.take<unsigned long long>(1);
+    L.cg_fail = c.take<int>(1);
     L.flag = c.take<int>(1);
     L.mask = c.take<int>(B);
     if (mode != RTE_SI) {
@@ -93,6 +97,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
             L.cg.part = c.take<double>(B * 5 * (size_t)L.cg.nblk);
             L.cg.iters = c.take<int>(B);
             L.cg.state = c.take<int>(B);
+            L.cg.fails = L.cg_fail;
             L.cg.n_running = c.take<int>(2);
             L.cg.tol2 = c.take<double>(1);
             L.cg.cf = c.take<double>(B * (size_t)p->ncell * 5);
@@ -131,6 +136,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
         L.rom.dc = c.take<double>(B * (size_t)rom->r);
         L.rom.y = c.take<double>(B * (size_t)rom->r);
         L.rom.A = c.take<double>(B * (size_t)rom->r * rom->r);
+        L.rom.n_fallback = L.st.n_active + 1;    // a singular system's instance takes DSA
         L.rom_status = c.take<int>(B);
     }
     if (gm_m > 0) {
@@ -252,6 +258,51 @@ struct ProfScope {
 };
 
 }  // namespace
+
+// One outer iteration of rte_sisa_solve / rte_sisa_iterate captured as a HIP graph, kept by the
+// problem handle for the workspace and arguments it was captured with (the graph's kernels hold
+// their device pointers), with the stream it is captured on and the pinned words and events
+// through which the host reads the active count.
+struct rte_iter_graph {
+    struct Exec {
+        hipGraphExec_t exec = nullptr;
+        int *h_active = nullptr;              // pinned host [2]: active counts of polled launches
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        ~Exec() {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+            if (h_active) (void)hipHostFree(h_active);
+        }
+    };
+    struct Key {
+        const void *ws;
+        size_t ws_bytes;
+        int mode;
+        unsigned long long rom;               // serial of the ROM (0: none)
+        const double *psi;
+        double *rho;
+        void *f_out;
+        double eps, eps_romsad, cg_rtol;
+        int max_iter, relative, theta, precision, depth;
+        bool operator==(const Key &o) const {
+            return ws == o.ws && ws_bytes == o.ws_bytes && mode == o.mode && rom == o.rom &&
+                   psi == o.psi && rho == o.rho && f_out == o.f_out && eps == o.eps &&
+                   eps_romsad == o.eps_romsad && cg_rtol == o.cg_rtol && max_iter == o.max_iter &&
+                   relative == o.relative && theta == o.theta && precision == o.precision &&
+                   depth == o.depth;
+        }
+    };
+    std::mutex mu;
+    hipStream_t cs = nullptr;                 // capture stream
+    Key key{};
+    bool valid = false;
+    std::shared_ptr<Exec> cur;
+    ~rte_iter_graph() {
+        cur.reset();
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
 
 int rte_problem::nparts() const { return nparts_for(this); }
 
@@ -442,6 +493,7 @@ void rte_problem_destroy(rte_problem *p) {
     if (p->d_mu) (void)hipFree(p->d_mu);
     if (p->d_widths) (void)hipFree(p->d_widths);
     if (p->d_vxy) (void)hipFree(p->d_vxy);
+    delete p->iter_graph;
     delete p;
 }
 
@@ -507,6 +559,8 @@ int rte_rom_create(const rte_problem *p, const rte_rom_desc *d, rte_rom **out) {
     r->ndof = p->ndof;
     r->eps_pod = d->eps_pod;
     r->eps_train = d->eps_train;
+    static std::atomic<unsigned long long> rom_serial{0};
+    r->serial = ++rom_serial;
     r->d_U_rho = r->d_U_iso = r->d_A0 = r->d_A = r->d_b_in = nullptr;
     r->d_U_rho_f = r->d_U_iso_f = nullptr;
     std::vector<float> tmp(nu);
@@ -656,6 +710,128 @@ int check_solve_args(const rte_problem *p, rte_mode mode, const rte_rom *rom, co
     return RTE_OK;
 }
 
+// One outer iteration of Alg. 1 (Alg. 2 for ROMSAD) for every active instance, enqueued with no
+// host read: the sweep and its reduction, the stop test and choice of correction, ROMSA for the
+// instances that chose it (a singular reduced system turns its instance into a DSA one on the
+// device), the diffusion correction for the DSA instances, and the update.  The 2D diffusion CG
+// runs `depth` iterations (an instance that converges stops inside and its kernels return at
+// once); iteration depth + 1 stops any instance still running and counts it as failed.
+int enqueue_iteration(const rte_problem *p, const Layout &L, rte_mode mode, const rte_rom *rom,
+                      const double *psi, const rte_solve_opts *o, double eps_romsad, double *rho,
+                      void *f_out, int depth, hipStream_t s) {
+    const int fp32 = o->precision == RTE_MIXED;
+    const bool corrected = mode != RTE_SI;
+    int rc = do_sweep(p, L, L.src, f_out, L.rho_star, rho, L.st.active, 0, fp32, s);
+    if (rc) return rc;
+    HIPCHK(launch_decide(p, L.st, o->max_iter, o->eps, o->relative, (int)mode, o->theta,
+                         eps_romsad, s));
+    if (mode == RTE_ROMSAD)
+        HIPCHK(launch_rom_correct(p, rom, psi, L.rho_star, rho, L.delta, L.rom_status, L.st.kind,
+                                  2, L.rom, fp32, s));
+    if (corrected) {
+        if (p->dim == 1) {
+            HIPCHK(launch_dsa1d(p, L.rho_star, rho, L.delta, L.st.kind, 1, L.dsa1d, s));
+        } else {
+            HIPCHK(launch_cg_setup(p, L.cg, L.rho_star, rho, L.st.kind, 1, L.delta, o->cg_rtol, s));
+            for (int it = 1; it <= depth + 1; ++it)
+                HIPCHK(launch_cg_iteration(p, L.cg, it, o->cg_rtol, depth, s));
+            HIPCHK(launch_cg_finish(p, L.cg, L.delta, L.cg.iters, L.cg_total, s));
+        }
+    }
+    HIPCHK(launch_update(p, L.st, L.rho_star, corrected ? L.delta : nullptr, rho, L.src, fp32, s));
+    return RTE_OK;
+}
+
+// The handle's outer-iteration graph for these arguments: the cached one, or a new capture of
+// enqueue_iteration on the handle's capture stream.
+int iteration_graph(const rte_problem *p, const Layout &L, rte_mode mode, const rte_rom *rom,
+                    const double *psi, const rte_solve_opts *o, double eps_romsad, double *rho,
+                    void *f_out, const void *ws, size_t ws_bytes,
+                    std::shared_ptr<rte_iter_graph::Exec> *out) {
+    if (!p->iter_graph) {
+        p->iter_graph = new (std::nothrow) rte_iter_graph();
+        if (!p->iter_graph) return RTE_ENOMEM;
+    }
+    rte_iter_graph &G = *p->iter_graph;
+    const int depth = mode != RTE_SI && p->dim == 2 ? std::min(o->cg_maxit, o->graph_cg_iters) : 0;
+    rte_iter_graph::Key k{ws, ws_bytes, (int)mode, rom ? rom->serial : 0ull, psi, rho, f_out,
+                          o->eps, eps_romsad, mode != RTE_SI ? o->cg_rtol : 0.0, o->max_iter,
+                          o->relative, o->theta, (int)o->precision, depth};
+    std::lock_guard<std::mutex> lock(G.mu);
+    if (G.valid && G.key == k) {
+        *out = G.cur;
+        return RTE_OK;
+    }
+    G.valid = false;
+    G.cur.reset();
+    if (!G.cs) HIPCHK(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
+    auto ex = std::make_shared<rte_iter_graph::Exec>();
+    HIPCHK(hipHostMalloc((void **)&ex->h_active, 2 * sizeof(int), hipHostMallocDefault));
+    for (hipEvent_t &e : ex->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // the library's per-kernel event timing stays out of the graph
+    const bool prof = g_prof.on;
+    g_prof.on = false;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal);
+    int rc = RTE_OK;
+    if (e == hipSuccess) {
+        rc = enqueue_iteration(p, L, mode, rom, psi, o, eps_romsad, rho, f_out, depth, G.cs);
+        const hipError_t ee = hipStreamEndCapture(G.cs, &g);
+        if (ee != hipSuccess && rc == RTE_OK) rc = device_error(ee);
+    } else {
+        rc = device_error(e);
+    }
+    g_prof.on = prof;
+    if (rc == RTE_OK && g) {
+        e = hipGraphInstantiate(&ex->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = device_error(e);
+    } else if (rc == RTE_OK) {
+        rc = RTE_EDEVICE;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (rc) return rc;
+    G.key = k;
+    G.cur = ex;
+    G.valid = true;
+    *out = ex;
+    return RTE_OK;
+}
+
+// Graph mode of run_iterations: one graph launch per outer iteration.  After every poll_every-th
+// launch the active count is copied to pinned host memory behind an event; the host waits for
+// that event only after it has queued the next launch, so the device never idles on the read.
+// Launches after every instance stopped change nothing (every kernel is predicated on the
+// instance's state).
+int run_graph_iterations(const rte_problem *p, const Layout &L, rte_mode mode, const rte_rom *rom,
+                         const double *psi, const rte_solve_opts *o, double eps_romsad,
+                         double *rho, void *f_out, int n_max, const void *ws, size_t ws_bytes,
+                         hipStream_t s, int *iterations, bool *cg_failed) {
+    std::shared_ptr<rte_iter_graph::Exec> ex;
+    int rc = iteration_graph(p, L, mode, rom, psi, o, eps_romsad, rho, f_out, ws, ws_bytes, &ex);
+    if (rc) return rc;
+    const int poll = o->poll_every > 0 ? o->poll_every : 1;
+    int pending = -1;                       // slot of the last poll not yet read
+    for (int l = 1; l <= n_max; ++l) {
+        HIPCHK(hipGraphLaunch(ex->exec, s));
+        *iterations = l;
+        if (l % poll != 0 && l != n_max) continue;
+        const int slot = l & 1;
+        HIPCHK(hipMemcpyAsync(ex->h_active + slot, L.st.n_active, sizeof(int),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ex->ev[slot], s));
+        if (pending >= 0) {
+            HIPCHK(hipEventSynchronize(ex->ev[pending]));
+            if (ex->h_active[pending] == 0) break;
+        }
+        pending = slot;
+    }
+    int fails = 0;
+    HIPCHK(hipMemcpyAsync(&fails, L.cg_fail, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *cg_failed = *cg_failed || fails > 0;
+    return RTE_OK;
+}
+
 // Up to n_max outer iterations (Alg. 1; Alg. 2 for ROMSAD) of every active instance; returns
 // early once no instance is active.  SI looks at the active count every poll_every iterations.
 // The modes with a diffusion solve wait on the device inside every iteration anyway, so they
@@ -663,11 +839,16 @@ int check_solve_args(const rte_problem *p, rte_mode mode, const rte_rom *rom, co
 // loop ends with the iteration in which the last instance stopped.
 int run_iterations(const rte_problem *p, const Layout &L, rte_mode mode, const rte_rom *rom,
                    const double *psi, const rte_solve_opts *o, double *rho, void *f_out, int n_max,
-                   hipStream_t s, int *iterations, bool *cg_failed) {
+                   const void *ws, size_t ws_bytes, hipStream_t s, int *iterations,
+                   bool *cg_failed) {
     const int fp32 = o->precision == RTE_MIXED;
     double eps_romsad = o->eps_romsad;
     if (mode == RTE_ROMSAD && eps_romsad < 0.0)
         eps_romsad = 0.1 * std::max(rom->eps_train, rom->eps_pod);   // eq. (romsad_parameters)
+    HIPCHK(launch_fill_int(L.cg_fail, 1, 0, s));
+    if (o->graph_cg_iters > 0)
+        return run_graph_iterations(p, L, mode, rom, psi, o, eps_romsad, rho, f_out, n_max, ws,
+                                    ws_bytes, s, iterations, cg_failed);
     const int poll = o->poll_every > 0 ? o->poll_every : 1;
     const bool corrected = mode != RTE_SI;
     int counts[3] = {1, 1, 1};                // active, taking DSA, taking ROMSA
@@ -682,15 +863,24 @@ int run_iterations(const rte_problem *p, const Layout &L, rte_mode mode, const r
         }
         // L.delta holds every instance's previous correction (zero before its first)
         const double *delta = corrected ? L.delta : nullptr;
-        // a singular reduced system sends its instance to DSA (kind 1) on the device, so after a
-        // ROM correction the diffusion solve runs whatever the count said
-        const bool rom_ran = mode == RTE_ROMSAD && counts[2] > 0;
-        if (rom_ran) {
-            ProfScope ps(RTE_PROF_ROM, s);
-            HIPCHK(launch_rom_correct(p, rom, psi, L.rho_star, rho, L.delta, L.rom_status,
-                                      L.st.kind, 2, L.rom, fp32, s));
+        // a singular reduced system sends its instance to DSA (kind 1) and adds it to the DSA
+        // count on the device; when the decision sent none there, the count is read again
+        bool need_dsa = corrected && counts[1] > 0;
+        if (mode == RTE_ROMSAD && counts[2] > 0) {
+            {
+                ProfScope ps(RTE_PROF_ROM, s);
+                HIPCHK(launch_rom_correct(p, rom, psi, L.rho_star, rho, L.delta, L.rom_status,
+                                          L.st.kind, 2, L.rom, fp32, s));
+            }
+            if (!need_dsa) {
+                int n_dsa = 0;
+                HIPCHK(hipMemcpyAsync(&n_dsa, L.st.n_active + 1, sizeof(int),
+                                      hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                need_dsa = n_dsa > 0;
+            }
         }
-        if (corrected && (counts[1] > 0 || rom_ran)) {
+        if (need_dsa) {
             int failed = 0;
             rc = do_dsa(p, L, L.rho_star, rho, L.delta, L.st.kind, 1, o->cg_rtol, o->cg_maxit,
                         L.cg.iters, &failed, L.delta, s);
@@ -817,6 +1007,55 @@ int rte_sweep_noalloc(const rte_problem *p, const double *rho_in, void *f_out, d
                      (size_t)RTE_NOALLOC_SCRATCH_BYTES, stream);
 }
 
+int rte_tune_sweep(const rte_problem_desc *desc, rte_precision prec, int n_cand, const int *dg,
+                   const int *wpb, const double *rho_in, void *f_out, int warmup, int reps,
+                   double *ms_out, rte_stream_t stream) {
+    if (!desc || !dg || !wpb || !rho_in || !ms_out || n_cand < 1 || warmup < 0 || reps < 1)
+        return RTE_EINVAL;
+    if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
+    if (desc->dim != 2) return RTE_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < n_cand; ++i) ms_out[i] = -1.0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (hipEvent_t &e : ev) HIPCHK(hipEventCreate(&e));
+    int rc = RTE_OK;
+    for (int i = 0; i < n_cand && rc == RTE_OK; ++i) {
+        if (dg[i] < 1 || wpb[i] < 1) continue;
+        rte_problem *p = nullptr;
+        const int cr = rte_problem_create_tuned(desc, dg[i], wpb[i], &p);
+        if (cr == RTE_EINVAL) continue;                       // not a schedule the sweep has
+        if (cr != RTE_OK) { rc = cr; break; }
+        // a schedule the LDS budget would change is not this candidate
+        if (p->tune.dg != dg[i] || p->tune.wpb != wpb[i]) { rte_problem_destroy(p); continue; }
+        size_t bytes = 0;
+        rte_workspace_size(p, RTE_SI, nullptr, prec, 1, &bytes);
+        void *ws = nullptr;
+        double *rs = nullptr;
+        hipError_t e = hipMalloc(&ws, bytes);
+        if (e == hipSuccess) e = hipMalloc((void **)&rs, sizeof(double) * (size_t)p->B * p->ndof);
+        if (e != hipSuccess) rc = device_error(e);
+        for (int k = 0; k < warmup && rc == RTE_OK; ++k)
+            rc = rte_sweep(p, rho_in, f_out, rs, 0, prec, ws, bytes, stream);
+        if (rc == RTE_OK) rc = hipEventRecord(ev[0], s) == hipSuccess ? RTE_OK : RTE_EDEVICE;
+        for (int k = 0; k < reps && rc == RTE_OK; ++k)
+            rc = rte_sweep(p, rho_in, f_out, rs, 0, prec, ws, bytes, stream);
+        if (rc == RTE_OK) {
+            e = hipEventRecord(ev[1], s);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e == hipSuccess) ms_out[i] = (double)ms / reps;
+            else rc = device_error(e);
+        }
+        (void)hipStreamSynchronize(s);
+        if (rs) (void)hipFree(rs);
+        if (ws) (void)hipFree(ws);
+        rte_problem_destroy(p);
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
 int rte_scalar_flux(const rte_problem *p, const void *f, double *rho_out, rte_precision prec,
                     rte_stream_t stream) {
     if (!p || !f || !rho_out) return RTE_EINVAL;
@@ -891,11 +1130,12 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     HIPCHK(launch_zero_rows(L.delta, p->B, p->ndof, nullptr, s));
     HIPCHK(launch_zero_u64(L.cg_total, 1, s));
     if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
-    PrecondGraphs graphs(p, L.cg, mode != RTE_SI && p->dim == 2);
+    PrecondGraphs graphs(p, L.cg, mode != RTE_SI && p->dim == 2 && o->graph_cg_iters <= 0);
     HIPCHK(launch_source(p, rho, L.src, nullptr, o->precision == RTE_MIXED, s));
     int iterations = 0;
     bool cg_failed = false;
-    rc = run_iterations(p, L, mode, rom, psi, o, rho, f_out, o->max_iter, s, &iterations, &cg_failed);
+    rc = run_iterations(p, L, mode, rom, psi, o, rho, f_out, o->max_iter, ws, ws_bytes, s,
+                        &iterations, &cg_failed);
     if (rc) return rc;
     return finish_stats(p, L, o->max_iter, iterations, cg_failed, nullptr, stats, s);
 }
@@ -1061,7 +1301,8 @@ int rte_sisa_iterate(const rte_problem *p, rte_mode mode, const rte_rom *rom, co
     if (!c.ok) return RTE_ENOMEM;
     int iterations = 0;
     bool cg_failed = false;
-    rc = run_iterations(p, L, mode, rom, psi, o, rho, nullptr, n_iter, s, &iterations, &cg_failed);
+    rc = run_iterations(p, L, mode, rom, psi, o, rho, nullptr, n_iter, ws, ws_bytes, s,
+                        &iterations, &cg_failed);
     if (rc) return rc;
     rc = finish_stats(p, L, o->max_iter, iterations, cg_failed, active_out, stats, s);
     return rc == RTE_ENOCONV ? RTE_OK : rc;     // slots still running are not an error here

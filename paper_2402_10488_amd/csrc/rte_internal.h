@@ -60,6 +60,9 @@ struct rte_problem {
     int n_cu;                 // compute units of the device the handle was created on
     int lds_per_cu;           // bytes of LDS per compute unit (and per workgroup)
     int nparts() const;       // 2D sweep partial-sum slots per instance for the current tuning
+    // the outer iteration of rte_sisa_solve / rte_sisa_iterate captured as a HIP graph for the
+    // last (workspace, arguments) it was used with; owned by the handle (rte_api.hip)
+    mutable struct rte_iter_graph *iter_graph;
 };
 
 namespace rte {
@@ -205,6 +208,7 @@ struct rte_rom {
     double *d_A0;      // device [r][r]
     double *d_A;       // device [m][r][r]
     double *d_b_in;    // device [4][r] reduced unit-inflow loads (zeros when not given)
+    unsigned long long serial;   // distinct for every ROM created in the process
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -294,6 +298,8 @@ struct CGSpace {
     int *state;                        // [B] 0 idle, 1 running, 2 converged, 3 failed
     int *n_running;                    // [2] instances still iterating; instances that failed
                                        // (limit reached or a NaN) in the current call
+    int *fails;                        // [1] or null: instances that stopped without converging,
+                                       // summed over every call until the caller clears it
     double *tol2;                      // [1] the call's squared relative tolerance
     int nblk;                          // blocks per instance
     int zf32;                          // 1: z and the multigrid residual t held in FP32 (mixed
@@ -335,6 +341,8 @@ struct RomSpace {
     double *ypart;    // [B][nsplit][r] split-K partials
     double *dc;       // [B][r]
     int nsplit;
+    int *n_fallback;  // [1] or null: incremented for every instance whose reduced system is
+                      // singular (sent to DSA for the iteration)
 };
 hipError_t launch_rom_correct(const rte_problem *p, const rte_rom *rom, const double *psi,
                               const double *rho_star, const double *rho_prev, double *delta,

@@ -212,6 +212,9 @@ def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=N
         del DX
     A0 = W.T @ GD @ W
     if classes is None:
+        if getattr(train_plane, "block_fields", None) is not None:
+            raise ValueError("the offline builder forms class-restricted operators; a medium "
+                             "given by cell fields needs its ROM built elsewhere")
         classes = train_plane.block.reshape(-1)
     classes = np.asarray(classes, dtype=np.int32).reshape(-1)
     ncls = int(classes.max()) + 1

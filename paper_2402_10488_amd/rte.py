@@ -54,7 +54,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("max_iter", ctypes.c_int), ("relative", ctypes.c_int),
                 ("theta", ctypes.c_int), ("eps_romsad", ctypes.c_double),
                 ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
-                ("precision", ctypes.c_int), ("poll_every", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("poll_every", ctypes.c_int),
+                ("graph_cg_iters", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -84,7 +85,7 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_sym_eig", "rte_combine", "rte_apply_streaming", "rte_direction_sum",
             "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
             "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve", "rte_f_natural",
-            "rte_last_device_error", "rte_sweep_noalloc"]
+            "rte_last_device_error", "rte_sweep_noalloc", "rte_tune_sweep"]
 
 
 def _load():
@@ -119,6 +120,9 @@ def _load():
                                      ctypes.POINTER(ctypes.c_size_t)]
     L.rte_sweep.argtypes = [P, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
     L.rte_sweep_noalloc.argtypes = [P, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
+    _ip = ctypes.POINTER(ctypes.c_int)
+    L.rte_tune_sweep.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int, ctypes.c_int, _ip, _ip,
+                                 _vp, _vp, ctypes.c_int, ctypes.c_int, _D, _vp]
     L.rte_scalar_flux.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
     L.rte_f_natural.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
     L.rte_dsa_correct.argtypes = [P, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
@@ -220,6 +224,7 @@ class Problem:
         _check(lib.rte_problem_create_tuned(ctypes.byref(d), int(dg), int(wpb), ctypes.byref(h)),
                "rte_problem_create")
         self.handle = h
+        self._desc = d            # host arrays it points to are kept above
         self.weights = np.asarray(weights, dtype=np.float64)
 
     def tuning(self):
@@ -320,6 +325,20 @@ def sweep_noalloc(p: Problem, rho_in, f_out=None, rho_star_out=None, zero_inflow
 NOALLOC_SCRATCH_BYTES = 32 << 20      # RTE_NOALLOC_SCRATCH_BYTES of include/rte.h
 
 
+def tune_sweep(p: Problem, candidates, rho_in, precision="mixed", f_out=None, warmup=1, reps=3):
+    """Milliseconds per 2D sweep of p's batch under each (dg, wpb) candidate (rte_tune_sweep);
+    -1 marks a candidate the library does not run as given."""
+    c = np.ascontiguousarray(candidates, dtype=np.int32).reshape(-1, 2)
+    dg = np.ascontiguousarray(c[:, 0])
+    wpb = np.ascontiguousarray(c[:, 1])
+    ms = np.zeros(len(c))
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    _check(lib.rte_tune_sweep(ctypes.byref(p._desc), PRECISIONS[precision], len(c), ip(dg), ip(wpb),
+                              _ptr(rho_in), _ptr(f_out), int(warmup), int(reps),
+                              ms.ctypes.data_as(_D), _stream()), "rte_tune_sweep")
+    return ms
+
+
 def f_shape(p: Problem):
     """Shape of the angular flux the library writes and reads: 2D (B, n_dir, ncell, 4), each
     direction's cells in its quadrant's diagonal order; 1D (B, ncell, n_dir, 2)."""
@@ -379,7 +398,10 @@ class SolveResult:
 def sisa_solve(p: Problem, rho_inout, mode="si_dsa", rom: Optional[Rom] = None, psi=None,
                eps=1e-8, max_iter=500, relative=True, theta=5, eps_romsad=-1.0, cg_rtol=1e-10,
                cg_maxit=5000, precision="fp64", poll_every=4, f_out=None, ws=None,
-               raise_on_error=True):
+               raise_on_error=True, graph_cg_iters=0):
+    """Alg. 1 (Alg. 2 for ROMSAD) on every instance.  graph_cg_iters > 0 runs each outer
+    iteration as one HIP graph launch holding that many diffusion CG iterations per correction
+    (rte_solve_opts.graph_cg_iters); 0 launches kernel by kernel."""
     ws = ws if ws is not None else p.workspace(mode, rom, precision, max_iter)
     B = p.B
     n_sweep = np.zeros(B, np.int32)
@@ -390,7 +412,8 @@ def sisa_solve(p: Problem, rho_inout, mode="si_dsa", rom: Optional[Rom] = None, 
                        st.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), change.ctypes.data_as(_D),
                        kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 0, 0)
     o = SolveOpts(float(eps), int(max_iter), int(relative), int(theta), float(eps_romsad),
-                  float(cg_rtol), int(cg_maxit), PRECISIONS[precision], int(poll_every))
+                  float(cg_rtol), int(cg_maxit), PRECISIONS[precision], int(poll_every),
+                  int(graph_cg_iters))
     rc = lib.rte_sisa_solve(p.handle, MODES[mode], rom.handle if rom else None, _ptr(psi),
                             ctypes.byref(o), _ptr(rho_inout), _ptr(f_out), ctypes.byref(stats),
                             _ptr(ws), ws.numel(), _stream())
@@ -409,14 +432,14 @@ class Session:
 
     def __init__(self, p: Problem, mode="romsad", rom: Optional[Rom] = None, psi=None, eps=1e-6,
                  max_iter=500, relative=True, theta=5, eps_romsad=-1.0, cg_rtol=1e-10,
-                 cg_maxit=5000, precision="mixed", poll_every=1, stream=None):
+                 cg_maxit=5000, precision="mixed", poll_every=1, stream=None, graph_cg_iters=0):
         import torch
         self.p, self.mode, self.rom, self.psi = p, mode, rom, psi
         self.max_iter = int(max_iter)
         self.stream = stream
         self.opts = SolveOpts(float(eps), int(max_iter), int(relative), int(theta),
                               float(eps_romsad), float(cg_rtol), int(cg_maxit),
-                              PRECISIONS[precision], int(poll_every))
+                              PRECISIONS[precision], int(poll_every), int(graph_cg_iters))
         with self._on_stream():
             self.ws = p.workspace(mode, rom, precision, max_iter)
             self.rho = torch.zeros((p.B, p.ndof), dtype=torch.float64, device="cuda")

@@ -85,7 +85,7 @@ class KeyPool:
 
     def __init__(self, n: int, n_phi: int, capacity: int, mode: str, rom_arrays=None,
                  precision="mixed", eps=1e-6, max_iter=500, theta=5, cg_rtol=1e-10,
-                 iters_per_round=1, keep_rho=False):
+                 iters_per_round=1, keep_rho=False, graph_cg_iters=0):
         import torch
         self.key = (n, n_phi)
         self.S = capacity
@@ -110,7 +110,8 @@ class KeyPool:
                 self.psi = torch.zeros((capacity, m), dtype=torch.float64, device="cuda")
             self.session = Session(self.P, mode, self.rom, self.psi, eps=eps, max_iter=max_iter,
                                    theta=theta, cg_rtol=cg_rtol, precision=precision,
-                                   poll_every=iters_per_round, stream=self.stream)
+                                   poll_every=iters_per_round, stream=self.stream,
+                                   graph_cg_iters=graph_cg_iters)
         self.stream.synchronize()
         total = self.session.ws.numel() + 8 * (4 * capacity * n * n + 4 * capacity)
         total += 8 * self.session.rho.numel()

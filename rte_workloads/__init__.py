@@ -25,8 +25,10 @@ __all__ = [
     "Slab", "Plane", "slab_uniform", "c0_slab", "cross_regime", "two_material",
     "window_demo", "plane_uniform", "c1_checkerboard", "c2_lattice", "c2_batch",
     "c2_training", "c3_requests", "c4_multiscale", "c4_training", "random_plane",
-    "homogeneous_medium", "lattice_medium",
-    "random_slab", "Request",
+    "homogeneous_medium", "lattice_medium", "pin_cell", "variable_scattering",
+    "homogeneous_training", "homogeneous_test", "lattice_training", "lattice_test",
+    "pin_cell_training", "pin_cell_test", "variable_scattering_training",
+    "variable_scattering_test", "random_slab", "Request",
 ]
 
 
@@ -151,6 +153,9 @@ class Plane:
     values [B, nblocks] the cell arrays were filled from (affine parameters).
     ``quad = ("cheb", N_phi)`` is the normalized Chebyshev rule on the unit circle,
     ``("cl", (N_phi, N_vz))`` the Chebyshev-Legendre rule on the sphere.
+    ``block_fields`` ([nblocks, ny, nx], optional) replaces the block indicators by cell fields:
+    then sigma = sum_k block_sigma[:, k] * block_fields[k] (a medium affine in its parameters
+    whose terms are not piecewise constant), and ``block`` is not a material map.
     """
     nx: int
     ny: int
@@ -166,6 +171,7 @@ class Plane:
     quad: Tuple = ("cheb", 64)
     name: str = "plane"
     seeds: Tuple[int, ...] = field(default_factory=tuple)
+    block_fields: Optional[np.ndarray] = None
 
     @property
     def B(self) -> int:
@@ -184,14 +190,14 @@ class Plane:
         return Plane(self.nx, self.ny, self.Lx, self.Ly, self.sigma_t[s], self.sigma_s[s],
                      self.G[s], self.g[s], self.block, self.block_sigma_t[s],
                      self.block_sigma_s[s], self.quad, f"{self.name}[{b}]",
-                     self.seeds[b:b + 1] if self.seeds else ())
+                     self.seeds[b:b + 1] if self.seeds else (), self.block_fields)
 
     def subset(self, idx: Sequence[int]) -> "Plane":
         idx = list(idx)
         return Plane(self.nx, self.ny, self.Lx, self.Ly, self.sigma_t[idx], self.sigma_s[idx],
                      self.G[idx], self.g[idx], self.block, self.block_sigma_t[idx],
                      self.block_sigma_s[idx], self.quad, self.name,
-                     tuple(self.seeds[i] for i in idx) if self.seeds else ())
+                     tuple(self.seeds[i] for i in idx) if self.seeds else (), self.block_fields)
 
 
 def _checker_blocks(nx: int, ny: int, nbx: int, nby: int) -> np.ndarray:
@@ -255,6 +261,93 @@ def lattice_medium(params: Sequence[Tuple[float, float]], n: int = 50,
     Gb[:, 12] = 1.0
     return Plane(n, n, 5.0, 5.0, _fill(block, bst), _fill(block, bss), _fill(block, Gb),
                  np.zeros((B, 4)), block, bst, bss, quad, f"lattice_{n}x{n}_B{B}")
+
+
+def homogeneous_training() -> List[float]:
+    """Sec. 4.3.1: mu_s = 0.9 + m / 200, m = 0..20."""
+    return [0.9 + m / 200.0 for m in range(21)]
+
+
+def homogeneous_test(n_test: int = 10, seed: int = 60000) -> List[float]:
+    """Test draws mu_s ~ U[0.9, 1.1] (Sec. 4.3.1 samples 10; its values are not published)."""
+    return [float(v) for v in np.random.default_rng(seed).uniform(0.9, 1.1, n_test)]
+
+
+def lattice_training() -> List[Tuple[float, float]]:
+    """Sec. 4.3.2: (mu_a, mu_s) = (95 + i, 0.5 + 0.1 j), i, j = 0..10 (121 pairs)."""
+    return [(95.0 + i, 0.5 + 0.1 * j) for i in range(11) for j in range(11)]
+
+
+def lattice_test(n_test: int = 10, seed: int = 60100) -> List[Tuple[float, float]]:
+    """Test draws (mu_a, mu_s) ~ U[95, 105] x U[0.5, 1.5]."""
+    r = np.random.default_rng(seed)
+    return [(float(a), float(b)) for a, b in zip(r.uniform(95, 105, n_test), r.uniform(0.5, 1.5, n_test))]
+
+
+def _centres(n: int, lo: float, hi: float) -> np.ndarray:
+    return lo + (np.arange(n) + 0.5) * (hi - lo) / n
+
+
+def pin_cell(params: Sequence[Tuple[float, float]], n: int = 80, quad=("cl", (30, 6))) -> Plane:
+    """Stand-in for the paper's pin-cell family (Sec. 4.3.3) on [-1, 1]^2 (stored as [0, 2]^2),
+    vacuum inflow: in the pin |x|, |y| <= 0.5 (cells whose centre lies there) sigma_a = mu_a,
+    sigma_s = mu_s; outside sigma_a = 0, sigma_s = 100; G = exp(-100 (x^2 + y^2)) at the cell
+    centres (the library takes cell-constant data).  Block 0 is the pin, block 1 the rest; one
+    instance per (mu_a, mu_s)."""
+    B = len(params)
+    xc = _centres(n, -1.0, 1.0)
+    inside = np.abs(xc) <= 0.5
+    block = np.where(inside[:, None] & inside[None, :], 0, 1).astype(np.int32)
+    mu_a = np.array([p[0] for p in params], np.float64)
+    mu_s = np.array([p[1] for p in params], np.float64)
+    bst = np.stack([mu_a + mu_s, np.full(B, 100.0)], axis=1)
+    bss = np.stack([mu_s, np.full(B, 100.0)], axis=1)
+    Gc = np.exp(-100.0 * (xc[None, :] ** 2 + xc[:, None] ** 2))
+    G = np.broadcast_to(Gc, (B, n, n)).copy()
+    return Plane(n, n, 2.0, 2.0, _fill(block, bst), _fill(block, bss), G, np.zeros((B, 4)),
+                 block, bst, bss, quad, f"pin_cell_{n}x{n}_B{B}")
+
+
+def pin_cell_training() -> List[Tuple[float, float]]:
+    """Sec. 4.3.3: (mu_a, mu_s) = (0.05 i, 0.05 j), i, j = 1..5 (25 pairs)."""
+    return [(0.05 * i, 0.05 * j) for i in range(1, 6) for j in range(1, 6)]
+
+
+def pin_cell_test(n_test: int = 10, seed: int = 60200) -> List[Tuple[float, float]]:
+    """Test draws (mu_a, mu_s) ~ U[0.05, 0.5]^2."""
+    r = np.random.default_rng(seed)
+    return [(float(a), float(b)) for a, b in zip(r.uniform(0.05, 0.5, n_test),
+                                                 r.uniform(0.05, 0.5, n_test))]
+
+
+def variable_scattering(mu_s: Sequence[float], n: int = 80, quad=("cl", (30, 6))) -> Plane:
+    """Stand-in for the paper's variable-scattering family (Sec. 4.3.4) on [-1, 1]^2 (stored as
+    [0, 2]^2), vacuum inflow, sigma_a = 0 and sigma_s = mu_s s(r) + 0.1 with
+    s(r) = r^4 (2 - r^2)^2 for r <= 1 and 1 beyond, G = (10 / pi) exp(-100 r^2); s and G at the
+    cell centres.  The medium is affine in mu_s with two cell fields, s and 1
+    (block_fields), whose coefficients are (mu_s, 0.1) for sigma_t and for sigma_s."""
+    B = len(mu_s)
+    xc = _centres(n, -1.0, 1.0)
+    r2 = xc[None, :] ** 2 + xc[:, None] ** 2
+    r = np.sqrt(r2)
+    shape = np.where(r <= 1.0, r2 ** 2 * (2.0 - r2) ** 2, 1.0)
+    fields = np.stack([shape, np.ones((n, n))])
+    coef = np.stack([np.asarray(mu_s, np.float64), np.full(B, 0.1)], axis=1)    # [B, 2]
+    sig = np.einsum("bk,kyx->byx", coef, fields)
+    G = np.broadcast_to((10.0 / np.pi) * np.exp(-100.0 * r2), (B, n, n)).copy()
+    return Plane(n, n, 2.0, 2.0, sig, sig.copy(), G, np.zeros((B, 4)),
+                 np.zeros((n, n), np.int32), coef, coef.copy(), quad,
+                 f"variable_scattering_{n}x{n}_B{B}", (), fields)
+
+
+def variable_scattering_training() -> List[float]:
+    """Sec. 4.3.4: 50 uniformly spaced mu_s over [49.9, 99.9]."""
+    return [float(v) for v in np.linspace(49.9, 99.9, 50)]
+
+
+def variable_scattering_test(n_test: int = 10, seed: int = 60300) -> List[float]:
+    """Test draws mu_s ~ U[49.9, 99.9]."""
+    return [float(v) for v in np.random.default_rng(seed).uniform(49.9, 99.9, n_test)]
 
 
 def c1_checkerboard(n: int = 128, n_phi: int = 64) -> Plane:
@@ -364,7 +457,7 @@ def stack(planes: Sequence[Plane], name: str = None) -> Plane:
     seeds = tuple(s for p in planes for s in p.seeds)
     return Plane(p0.nx, p0.ny, p0.Lx, p0.Ly, cat("sigma_t"), cat("sigma_s"), cat("G"), cat("g"),
                  p0.block, cat("block_sigma_t"), cat("block_sigma_s"), p0.quad,
-                 name or p0.name, seeds)
+                 name or p0.name, seeds, p0.block_fields)
 
 
 def c4_training(N: int = 64, n: int = 512, n_phi: int = 256) -> Plane:
