@@ -74,15 +74,21 @@ def _snapshot_job(job):
     return b, cols.shape[1]
 
 
-def correction_snapshots_parallel(spec, n_train, window, eps_train, n_rows, workdir, pool):
+def correction_snapshots_parallel(spec, n_train, window, eps_train, n_rows, workdir, pool,
+                                  log=None):
     """delta F of the correction ROM over the training instances 0..n_train-1 of the plane
     description ``spec`` = (generator name in rte_workloads, args), ``window`` columns each (every
-    training solve here takes more sweeps than the window); returns the [n_rows, n_cols] array."""
+    training solve here takes more sweeps than the window); returns the [n_rows, n_cols] array.
+    log (optional) is called with a line as training solves finish."""
     path = os.path.join(workdir, "snapshots.f64")
     shape = (n_rows, n_train * window)
     np.memmap(path, dtype=np.float64, mode="w+", shape=shape).flush()
     jobs = [(spec, b, window, eps_train, path, shape, b * window) for b in range(n_train)]
-    got = pool.map(_snapshot_job, jobs)
+    got = []
+    for item in pool.imap_unordered(_snapshot_job, jobs):
+        got.append(item)
+        if log and (len(got) % 8 == 0 or len(got) == n_train):
+            log(f"training solves finished: {len(got)} of {n_train}")
     assert all(n == window for _, n in got), got
     return np.array(np.memmap(path, dtype=np.float64, mode="r", shape=shape))
 
@@ -110,10 +116,11 @@ def solve_instances(spec, ids, mode, eps, theta=5, rom=None, n=None):
     return {b: (ns, kinds, ch, rho, conv) for b, ns, kinds, ch, rho, conv in out}, workers
 
 
-def build_correction_rom_parallel(spec, n_train, window, eps_train, r, workdir=None, n=None):
+def build_correction_rom_parallel(spec, n_train, window, eps_train, r=None, workdir=None, n=None,
+                                  eps_pod=None, log=None):
     """The oracle's correction ROM (Sec. 3.2.1) of training instances 0..n_train-1 of ``spec``:
-    snapshot columns from a pool, then the POD and reduced operators of
-    correction_rom_from_snapshots on the block-lattice affine split."""
+    snapshot columns from a pool, then the POD (rank r, or eq. (pod_truncation) with eps_pod) and
+    reduced operators of correction_rom_from_snapshots on the medium's affine split."""
     import tempfile
     from oracle import rom as orom
     from oracle.problem import discretize
@@ -121,9 +128,43 @@ def build_correction_rom_parallel(spec, n_train, window, eps_train, r, workdir=N
     with tempfile.TemporaryDirectory(dir=workdir) as tmp:
         with make_pool(n) as pool:
             dF = correction_snapshots_parallel(spec, n_train, window, eps_train,
-                                               d0.nv * d0.ndof, tmp, pool)
+                                               d0.nv * d0.ndof, tmp, pool, log)
     return orom.correction_rom_from_snapshots(dF, d0, orom.plane_affine(d0), orom.plane_psi,
-                                              r=r, eps_train=eps_train)
+                                              r=r, eps_pod=eps_pod, eps_train=eps_train, log=log)
+
+
+def build_roms_parallel(spec, n_train, window, eps_train, eps_pod=None, r_c=None, r_p=None,
+                        workdir=None, n=None, log=None):
+    """The oracle's correction ROM (Sec. 3.2.1) and parametric ROM (Sec. 3.1) of training
+    instances 0..n_train-1 of ``spec`` from one pool run of the training solves.  The first column
+    of every instance's window is f - f^(0) = f, the converged angular flux, so those columns are
+    the parametric snapshots; each ROM is then the POD of its columns (rank r_c / r_p, or eq.
+    (pod_truncation) with eps_pod) and its reduced operators, as build_correction_rom and
+    build_parametric_rom form them."""
+    import tempfile
+    from oracle import rom as orom
+    from oracle.problem import discretize
+    d0 = discretize(_plane(spec), 0)
+    with tempfile.TemporaryDirectory(dir=workdir) as tmp:
+        with make_pool(n) as pool:
+            dF = correction_snapshots_parallel(spec, n_train, window, eps_train,
+                                               d0.nv * d0.ndof, tmp, pool, log)
+    affine = orom.plane_affine(d0)
+    F = np.ascontiguousarray(dF[:, ::window])
+    U, sv, _ = np.linalg.svd(F, full_matrices=False)
+    del F
+    rp = orom.pod_rank(sv, eps_pod) if r_p is None else min(r_p, U.shape[1])
+    Ur = np.ascontiguousarray(U[:, :rp])
+    del U
+    if log:
+        log(f"parametric POD: rank {rp} of {n_train} solutions")
+    A0, At, As, U_rho, _ = orom.reduced_operators(d0, Ur, affine, log)
+    prom = orom.ParametricROM(Ur, U_rho, A0, At, As, sv, orom.plane_psi)
+    crom = orom.correction_rom_from_snapshots(dF, d0, affine, orom.plane_psi, r=r_c,
+                                              eps_pod=eps_pod, eps_train=eps_train, log=log)
+    if log:
+        log(f"correction POD: rank {crom.r} of {dF.shape[1]} columns")
+    return crom, prom
 
 
 def save_rom(path, rom):
@@ -149,7 +190,7 @@ def _main(argv):
     cfg = json.loads(argv[2])
     spec = (cfg["spec"][0], tuple(cfg["spec"][1]))
     rom = build_correction_rom_parallel(spec, cfg["n_train"], cfg["window"], cfg["eps_train"],
-                                        cfg["rank"], n=cfg.get("procs"))
+                                        r=cfg["rank"], n=cfg.get("procs"))
     save_rom(cfg["out"], rom)
     print("saved", cfg["out"], flush=True)
 

@@ -67,8 +67,9 @@ def pod_dropped(sv, r):
     return float(max(0.0, 1.0 - np.sum(sv[:r]) / np.sum(sv)))
 
 
-def reduced_operators(disc, U, affine: Affine):
-    """(A0, At[k], As[k]) for a basis U [N_v N_DOF, r] (Sec. 3.1.1)."""
+def reduced_operators(disc, U, affine: Affine, log=None):
+    """(A0, At[k], As[k]) for a basis U [N_v N_DOF, r] (Sec. 3.1.1).  log (optional) is called
+    with a line after every affine term."""
     nv, n = disc.nv, disc.ndof
     r = U.shape[1]
     Uj = U.reshape(nv, n, r)
@@ -78,7 +79,11 @@ def reduced_operators(disc, U, affine: Affine):
     for c in range(r):
         DU = disc.apply_D(Uj[:, :, c])                 # [nv, n]
         A0[:, c] = np.einsum("jnr,jn->r", Uj, DU)
-    At = [sum(Uj[j].T @ (T @ Uj[j]) for j in range(nv)) for T in affine.T]
+    At = []
+    for k, T in enumerate(affine.T):
+        At.append(sum(Uj[j].T @ (T @ Uj[j]) for j in range(nv)))
+        if log:
+            log(f"reduced operator: sigma_t term {k + 1} of {len(affine.T)}")
     As = [-(U_iso.T @ (S @ U_rho)) for S in affine.S]
     return A0, At, As, U_rho, U_iso
 
@@ -155,7 +160,7 @@ def build_correction_rom(discs, affine, psi_fn, window=3, r=None, eps_pod=None,
 
 
 def correction_rom_from_snapshots(dF, disc, affine, psi_fn, r=None, eps_pod=None,
-                                  eps_train=1e-10, keep_full=False):
+                                  eps_train=1e-10, keep_full=False, log=None):
     """POD of given snapshot columns dF [N_v N_DOF, n_col] (thin SVD, Sec. 3.1), truncation at
     rank r or by eq. (pod_truncation), and the reduced operators on the discretization ``disc``
     (any instance: only its mesh and directions enter)."""
@@ -167,7 +172,7 @@ def correction_rom_from_snapshots(dF, disc, affine, psi_fn, r=None, eps_pod=None
         r = min(r, U.shape[1])
         eps_eff = pod_dropped(sv, r)
     dU = np.ascontiguousarray(U[:, :r])
-    A0, At, As, U_rho, U_iso = reduced_operators(disc, dU, affine)
+    A0, At, As, U_rho, U_iso = reduced_operators(disc, dU, affine, log)
     return CorrectionROM(U_rho, U_iso, A0, At, As, sv, eps_eff, eps_train, psi_fn,
                          dU if keep_full else None)
 

@@ -121,17 +121,19 @@ __device__ __forceinline__ DirConst<T> uni(DirConst<T> d) {
     return d;
 }
 
-// Cross-lane move "lane j receives lane j-1" as a DPP whole-wave shift (wave_shr:1); lane 0 has
-// no source and reads 0 (bound_ctrl), so the result needs no copy of the old value (lane 0's is
-// set by the caller where it is used).
-__device__ __forceinline__ float shfl_up1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+// Cross-lane move "lane j receives lane j-1" as a DPP whole-wave shift (wave_shr:1).  Lane 0 has
+// no source lane; with bound_ctrl off it keeps the instruction's old operand, which is the value
+// lane 0 must receive (its inflow), so no select follows the shift.
+__device__ __forceinline__ float shfl_up1(float lane0, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(lane0), __float_as_int(v),
+                                                      0x138, 0xf, 0xf, false));
 }
-__device__ __forceinline__ double shfl_up1(double v) {
-    const long long b = __double_as_longlong(v);
+__device__ __forceinline__ double shfl_up1(double lane0, double v) {
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(lane0);
     const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
-    const int l2 = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, true);
-    const int h2 = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, true);
+    const int olo = (int)(o & 0xffffffffll), ohi = (int)(o >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(olo, lo, 0x138, 0xf, 0xf, false);
+    const int h2 = __builtin_amdgcn_update_dpp(ohi, hi, 0x138, 0xf, 0xf, false);
     return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
 }
 
@@ -271,16 +273,35 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
         c.sv = *reinterpret_cast<const Vec4<T> *>(src + (size_t)c.pos * 4);
         c.sg = sig_t[c.pos];
     };
+    int rw = 0;     // the wavefront that sums this step's partial densities (step mod W)
     // One step: the lane's cell `cur` is solved while `nxt` is prefetched.  The loop below runs
     // steps in pairs with the two records swapping roles, so the prefetched data is consumed where
     // it was loaded (no register copy at the loop edge that would make the load land in its own
     // step).
     auto step = [&](int t, const CellIn &cur, CellIn &nxt) __attribute__((always_inline)) {
+        // lane 0 takes its y-inflow from the boundary (first band) or from the ring.  Its position
+        // is wave-uniform, so the branch is scalar and the ring read is one LDS broadcast; the
+        // value enters the shift below as lane 0's operand.
+        T r0v[DG], r1v[DG];
+        {
+            const int i0 = __builtin_amdgcn_readfirstlane(cur.i);
+            const int k0 = __builtin_amdgcn_readfirstlane(cur.k);
+            if (k0 == 0 || i0 < 0 || i0 >= nx || k0 >= nb) {
+#pragma unroll
+                for (int d = 0; d < DG; ++d) { r0v[d] = gy; r1v[d] = T(0); }
+            } else {
+#pragma unroll
+                for (int d = 0; d < DG; ++d) {
+                    r0v[d] = ring[(i0 * DG + d) * 2];
+                    r1v[d] = ring[(i0 * DG + d) * 2 + 1];
+                }
+            }
+        }
         T yi0[DG], yi1[DG];
 #pragma unroll
         for (int d = 0; d < DG; ++d) {               // all lanes take part in the shift
-            yi0[d] = shfl_up1(ty0[d]);
-            yi1[d] = shfl_up1(ty1[d]);
+            yi0[d] = shfl_up1(r0v[d], ty0[d]);
+            yi1[d] = shfl_up1(r1v[d], ty1[d]);
         }
         // next position and prefetch of its cell data (overlaps this step's arithmetic)
         nxt.k = cur.k;
@@ -295,29 +316,6 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
         // issued as soon as a direction's values exist, and the compiler counts them exactly.
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
         if (WF || cur.ok) {
-            // lane 0 takes its y-inflow from the boundary (first band) or from the ring.  Its
-            // position is wave-uniform, so the branch is scalar and the ring read is one LDS
-            // broadcast to every lane, kept by lane 0 only.
-            {
-                const int i0 = __builtin_amdgcn_readfirstlane(cur.i);
-                const int k0 = __builtin_amdgcn_readfirstlane(cur.k);
-                T r0v[DG], r1v[DG];
-                if (k0 == 0 || i0 < 0 || i0 >= nx || k0 >= nb) {
-#pragma unroll
-                    for (int d = 0; d < DG; ++d) { r0v[d] = gy; r1v[d] = T(0); }
-                } else {
-#pragma unroll
-                    for (int d = 0; d < DG; ++d) {
-                        r0v[d] = ring[(i0 * DG + d) * 2];
-                        r1v[d] = ring[(i0 * DG + d) * 2 + 1];
-                    }
-                }
-#pragma unroll
-                for (int d = 0; d < DG; ++d) {
-                    yi0[d] = lane == 0 ? r0v[d] : yi0[d];
-                    yi1[d] = lane == 0 ? r1v[d] : yi1[d];
-                }
-            }
             if (cur.i == 0) {
 #pragma unroll
                 for (int d = 0; d < DG; ++d) { tx0[d] = gx; tx1[d] = T(0); }
@@ -372,7 +370,9 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
                 *reinterpret_cast<double4 *>(slot + ((size_t)wv * 64 + lane) * 4) = v;
             }
             __syncthreads();
-            if (wv == 0 && cur.ok) {
+            // the summing wavefront rotates with the step, so the W wavefronts (on different
+            // SIMDs) share that work evenly; the order of the sum is the same for all
+            if (wv == rw && cur.ok) {
                 double4 sum = *reinterpret_cast<const double4 *>(slot + (size_t)lane * 4);
                 for (int w2 = 1; w2 < W; ++w2) {
                     const double4 o = *reinterpret_cast<const double4 *>(slot + ((size_t)w2 * 64 + lane) * 4);
@@ -389,6 +389,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
         // them in order; without partial sums this compiler-only barrier does (no instruction:
         // the LDS executes one wavefront's accesses in program order).
         if constexpr (WF) asm volatile("" ::: "memory");
+        rw = rw + 1 == W ? 0 : rw + 1;
     };
     CellIn A, B;
     A.k = 0;

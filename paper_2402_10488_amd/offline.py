@@ -198,6 +198,7 @@ def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=N
         r = int(np.argmax(ratio >= 1.0 - eps_pod) + 1)
     r = min(r, int(np.sum(sv > sv[0] * 1e-13)))
     eps_eff = float(max(0.0, 1.0 - np.sum(sv[:r]) / np.sum(sv)))
+    say(f"POD of {ncol} columns: rank {r}, dropped energy {eps_eff:.3e}")
     Wh = V.cpu().numpy()[:, order[:r]] / sv[:r]                   # [ncol, r]
     W = torch.as_tensor(np.ascontiguousarray(Wh), device="cuda")
     X3 = X.view(ncol, Pm.n_dir, Pm.ndof)
@@ -211,6 +212,7 @@ def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=N
         GD[:, s0:s1] = gram(X, DX.view(s1 - s0, L), scratch=scratch)
         del DX
     A0 = W.T @ GD @ W
+    say("streaming operator projected")
     if classes is None:
         if getattr(train_plane, "block_fields", None) is not None:
             raise ValueError("the offline builder forms class-restricted operators; a medium "

@@ -42,7 +42,8 @@ def oracle_rom():
     say(f"c2 oracle ROM: {N_TRAIN} training solves in {oracle_pool.pool_size()} processes, "
         "then the SVD and reduced operators")
     return oracle_pool.build_correction_rom_parallel(("c2_training", (N_TRAIN, N, NPHI)), N_TRAIN,
-                                                     WINDOW, EPS_TRAIN, RANK)
+                                                     WINDOW, EPS_TRAIN, RANK,
+                                                     log=lambda m: say(f"  {m}"))
 
 
 @pytest.fixture(scope="module")
