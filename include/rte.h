@@ -380,6 +380,25 @@ int rte_gram(const void *X, rte_precision xprec, int nx, const void *Y, rte_prec
  * Sec. 3.1: F^T F = V Lambda^2 V^T). */
 int rte_sym_eig(double *A, int n, double *evals, double *evecs, rte_stream_t stream);
 
+/* Basis weights of the method of snapshots (Sec. 3.1): from the eigenpairs of F^T F (rte_sym_eig:
+ * evals [ncol], evecs [ncol][ncol] with eigenvectors as columns; device FP64, ncol <= 256) the
+ * singular values sv = sqrt(max(lambda, 0)) sorted descending (device [ncol]; ties keep index
+ * order), the rank -- r if r > 0, else the smallest rank whose share of the sum of singular values
+ * reaches 1 - eps_pod (eq. (pod_truncation)), capped at the count of singular values above
+ * 1e-13 of the largest -- in r_out (device int [1]), the dropped share 1 - sum_{k<r} sv_k / sum sv
+ * in eps_out (device [1]), and W = V Sigma^-1 of the kept columns, W[i][k] = v_i of the k-th
+ * largest eigenvalue / sv_k, in W (device [ncol][ncol], leading dimension ncol; columns k >= r
+ * are not written).  U = F W is then the POD basis. */
+int rte_pod_weights(const double *evals, const double *evecs, int ncol, int r, double eps_pod,
+                    double *sv, double *W, int *r_out, double *eps_out, rte_stream_t stream);
+
+/* C = alpha op(A) B for small dense FP64 matrices (device, row-major): op(A) = A [m][k]
+ * (trans_a = 0) or the transpose of A [k][m] (trans_a = 1); B [k][n], or NULL for the identity
+ * (then k == n and C = alpha op(A)); C [m][n].  The reduced products of the offline construction
+ * (W^T G W, the reduced inflow loads, signs).  RTE_EUNSUPPORTED beyond 2^26 entries of C. */
+int rte_small_gemm(int trans_a, int m, int n, int k, double alpha, const double *A, const double *B,
+                   double *C, rte_stream_t stream);
+
 /* out[c] = sum_col W[col][c] X[col] for X [ncol][len], W [ncol][r], out [r][len] (device FP64),
  * on the matrix cores (the basis U = F V Lambda^-1 of the method of snapshots). */
 int rte_combine(const double *X, int ncol, long long len, const double *W, int r, double *out,

@@ -6,7 +6,10 @@
 //                      (v_mfma_f64_16x16x4f64, split over the rows, fixed-order split sum)
 //   eigenpairs of G    cyclic Jacobi, one workgroup (the method of snapshots: F = U S V^T with
 //                      F^T F = V S^2 V^T, U = F V S^-1)
+//   basis weights      sorted singular values, the rank (fixed or by eq. (pod_truncation)) and
+//                      W = V S^-1 of the kept columns (pod_weights_kernel, one workgroup)
 //   basis              U = X W for a small W (v_mfma_f64_16x16x4f64)
+//   reduced products   W^T G W, reduced inflow loads (small_gemm_kernel)
 //   streaming operator y_j = D_j x_j of eq. (dg_matrix_vec) (upwind DG, no boundary load)
 //   direction sums     sum_j w_j x_j (density of a basis vector) and sum_j x_j (isotropic
 //                      projection), eq. (rho_basis)
@@ -319,6 +322,87 @@ __global__ void __launch_bounds__(256) inflow_load_kernel(int nx, int ny, long l
 
 using namespace rte;
 
+namespace rte {
+namespace {
+
+// POD of the method of snapshots (Sec. 3.1): eigenpairs (lambda_i, v_i) of F^T F give the
+// singular values sigma = sqrt(lambda) and the basis U = F V Sigma^-1.  One workgroup of up to
+// 256 threads: thread i ranks eigenvalue i (descending, ties by index, as a stable sort), the rank
+// and its truncation are chosen by thread 0, and thread i writes row i of W = V Sigma^-1 for the
+// kept columns (W [ncol][ncol], leading dimension ncol).
+__global__ void __launch_bounds__(256) pod_weights_kernel(const double *evals, const double *evecs,
+                                                          int ncol, int r_fixed, double eps_pod,
+                                                          double *sv, double *W, int *r_out,
+                                                          double *eps_out) {
+    __shared__ double lam[256];
+    __shared__ double svs[256];
+    __shared__ int order[256];
+    __shared__ int r_sh;
+    const int i = threadIdx.x;
+    if (i < ncol) lam[i] = evals[i];
+    __syncthreads();
+    if (i < ncol) {
+        int rank = 0;
+        for (int j = 0; j < ncol; ++j)
+            rank += (lam[j] > lam[i]) || (lam[j] == lam[i] && j < i);
+        order[rank] = i;
+        svs[rank] = sqrt(lam[i] > 0.0 ? lam[i] : 0.0);
+    }
+    __syncthreads();
+    if (i == 0) {
+        double total = 0.0;
+        for (int k = 0; k < ncol; ++k) total += svs[k];
+        int r = ncol;
+        if (r_fixed > 0) {
+            r = r_fixed < ncol ? r_fixed : ncol;
+        } else {                                  // eq. (pod_truncation): sum ratio >= 1 - eps
+            double acc = 0.0;
+            for (int k = 0; k < ncol; ++k) {
+                acc += svs[k];
+                if (acc / total >= 1.0 - eps_pod) { r = k + 1; break; }
+            }
+        }
+        int nz = 0;                               // singular values above rounding of the largest
+        for (int k = 0; k < ncol; ++k) nz += svs[k] > svs[0] * 1e-13;
+        if (r > nz) r = nz > 0 ? nz : 1;
+        double kept = 0.0;
+        for (int k = 0; k < r; ++k) kept += svs[k];
+        const double drop = total > 0.0 ? 1.0 - kept / total : 0.0;
+        *r_out = r;
+        *eps_out = drop > 0.0 ? drop : 0.0;
+        r_sh = r;
+    }
+    __syncthreads();
+    if (i < ncol) {
+        sv[i] = svs[i];
+        const int r = r_sh;
+        for (int k = 0; k < r; ++k) W[(size_t)i * ncol + k] = evecs[(size_t)i * ncol + order[k]] / svs[k];
+    }
+}
+
+// C[m][n] = alpha op(A)[m][k] B[k][n] (B null: the k x n identity, so C = alpha op(A)); op(A) = A
+// [m][k] or, transposed, A [k][m]; row-major FP64, one thread per entry, for the reduced (r x r,
+// ncol x r) products of the offline ROM construction.
+__global__ void small_gemm_kernel(int trans_a, int m, int n, int k, double alpha, const double *A,
+                                  const double *B, double *C) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)m * n) return;
+    const int row = (int)(t / n), col = (int)(t - (long long)row * n);
+    double s = 0.0;
+    if (B) {
+        for (int q = 0; q < k; ++q) {
+            const double a = trans_a ? A[(size_t)q * m + row] : A[(size_t)row * k + q];
+            s += a * B[(size_t)q * n + col];
+        }
+    } else {
+        s = trans_a ? A[(size_t)col * m + row] : A[(size_t)row * k + col];
+    }
+    C[t] = alpha * s;
+}
+
+}  // namespace
+}  // namespace rte
+
 extern "C" {
 
 int rte_pod_snapshots(const rte_problem *p, const double *f_final, const double *f_iter,
@@ -400,6 +484,26 @@ int rte_sym_eig(double *A, int n, double *evals, double *evecs, rte_stream_t str
     if (!A || !evals || !evecs || n < 1 || n > 256) return RTE_EINVAL;
     hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, A, n, evecs,
                        evals, 30);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_pod_weights(const double *evals, const double *evecs, int ncol, int r, double eps_pod,
+                    double *sv, double *W, int *r_out, double *eps_out, rte_stream_t stream) {
+    if (!evals || !evecs || !sv || !W || !r_out || !eps_out || ncol < 1 || ncol > 256 || r < 0)
+        return RTE_EINVAL;
+    if (r == 0 && !(eps_pod >= 0.0 && eps_pod < 1.0)) return RTE_EINVAL;
+    hipLaunchKernelGGL(rte::pod_weights_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, evals,
+                       evecs, ncol, r, eps_pod, sv, W, r_out, eps_out);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_small_gemm(int trans_a, int m, int n, int k, double alpha, const double *A, const double *B,
+                   double *C, rte_stream_t stream) {
+    if (!A || !C || m < 1 || n < 1 || k < 1 || (trans_a != 0 && trans_a != 1)) return RTE_EINVAL;
+    if (!B && k != n) return RTE_EINVAL;
+    if ((long long)m * n > (1LL << 26) || (long long)k > (1LL << 20)) return RTE_EUNSUPPORTED;
+    hipLaunchKernelGGL(rte::small_gemm_kernel, dim3(cdiv((long long)m * n, 256)), dim3(256), 0,
+                       (hipStream_t)stream, trans_a, m, n, k, alpha, A, B, C);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 

@@ -33,6 +33,8 @@ lib.rte_combine.argtypes = [_vp, _i, _ll, _vp, _i, _vp, _vp]
 lib.rte_apply_streaming.argtypes = [_vp, _vp, _i, _i, _vp, _vp]
 lib.rte_direction_sum.argtypes = [_vp, _vp, _i, _i, _i, _vp, _vp]
 lib.rte_inflow_loads.argtypes = [_vp, _vp, _i, _i, _vp, _vp]
+lib.rte_pod_weights.argtypes = [_vp, _vp, _i, _i, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
+lib.rte_small_gemm.argtypes = [_i, _i, _i, _i, ctypes.c_double, _vp, _vp, _vp, _vp]
 
 
 def _prec(t):
@@ -79,6 +81,37 @@ def sym_eig(G):
     V = torch.empty((n, n), dtype=torch.float64, device=G.device)
     _check(lib.rte_sym_eig(_ptr(A), n, _ptr(ev), _ptr(V), _stream()), "rte_sym_eig")
     return ev, V
+
+
+def pod_weights(ev, V, r=0, eps_pod=0.0):
+    """(sv descending [ncol], W [ncol, r] = V Sigma^-1 of the kept columns, r, dropped share) from
+    the eigenpairs of F^T F (rte_pod_weights); r = 0 truncates by eq. (pod_truncation)."""
+    import torch
+    n = ev.shape[0]
+    sv = torch.empty(n, dtype=torch.float64, device=ev.device)
+    W = torch.zeros((n, n), dtype=torch.float64, device=ev.device)
+    r_out = torch.zeros(1, dtype=torch.int32, device=ev.device)
+    e_out = torch.zeros(1, dtype=torch.float64, device=ev.device)
+    _check(lib.rte_pod_weights(_ptr(ev.contiguous()), _ptr(V.contiguous()), n, int(r),
+                               float(eps_pod), _ptr(sv), _ptr(W), _ptr(r_out), _ptr(e_out),
+                               _stream()), "rte_pod_weights")
+    rk = int(r_out.item())
+    return sv.cpu().numpy(), W[:, :rk].contiguous(), rk, float(e_out.item())
+
+
+def small_gemm(A, B=None, trans_a=False, alpha=1.0):
+    """alpha op(A) B on the device (rte_small_gemm); B None is the identity."""
+    import torch
+    A = A.contiguous()
+    m, k = (A.shape[1], A.shape[0]) if trans_a else A.shape
+    n = B.shape[1] if B is not None else k
+    if B is not None:
+        B = B.contiguous()
+        assert B.shape[0] == k
+    C = torch.empty((m, n), dtype=torch.float64, device=A.device)
+    _check(lib.rte_small_gemm(int(trans_a), m, n, k, float(alpha), _ptr(A), _ptr(B), _ptr(C),
+                              _stream()), "rte_small_gemm")
+    return C
 
 
 def combine(X, W):
@@ -190,17 +223,8 @@ def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=N
     scratch = torch.empty(4096 * ncol * ncol + 256, dtype=torch.float64, device="cuda")
     G = gram(X, X, scratch=scratch)
     ev, V = sym_eig(G)
-    ev_h = ev.cpu().numpy()
-    order = np.argsort(-ev_h, kind="stable")
-    sv = np.sqrt(np.clip(ev_h[order], 0.0, None))
-    if r is None:
-        ratio = np.cumsum(sv) / np.sum(sv)
-        r = int(np.argmax(ratio >= 1.0 - eps_pod) + 1)
-    r = min(r, int(np.sum(sv > sv[0] * 1e-13)))
-    eps_eff = float(max(0.0, 1.0 - np.sum(sv[:r]) / np.sum(sv)))
+    sv, W, r, eps_eff = pod_weights(ev, V, 0 if r is None else r, eps_pod or 0.0)
     say(f"POD of {ncol} columns: rank {r}, dropped energy {eps_eff:.3e}")
-    Wh = V.cpu().numpy()[:, order[:r]] / sv[:r]                   # [ncol, r]
-    W = torch.as_tensor(np.ascontiguousarray(Wh), device="cuda")
     X3 = X.view(ncol, Pm.n_dir, Pm.ndof)
     U_rho = combine(direction_sum(Pm, X3, True), W)               # [r, N_DOF]
     U_iso = combine(direction_sum(Pm, X3, False), W)
@@ -211,7 +235,7 @@ def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=N
         DX = apply_streaming(Pm, X3[s0:s1])
         GD[:, s0:s1] = gram(X, DX.view(s1 - s0, L), scratch=scratch)
         del DX
-    A0 = W.T @ GD @ W
+    A0 = small_gemm(W, small_gemm(GD, W), trans_a=True)
     say("streaming operator projected")
     if classes is None:
         if getattr(train_plane, "block_fields", None) is not None:
@@ -221,11 +245,13 @@ def build_correction_rom(train_plane, r=20, window=3, eps_train=1e-10, eps_pod=N
     classes = np.asarray(classes, dtype=np.int32).reshape(-1)
     ncls = int(classes.max()) + 1
     cls_d = torch.as_tensor(classes, device="cuda")
-    At = [W.T @ gram(X, X, cls_d, 4, Pm.ncell, k, scratch) @ W for k in range(ncls)]
+    At = [small_gemm(W, small_gemm(gram(X, X, cls_d, 4, Pm.ncell, k, scratch), W), trans_a=True)
+          for k in range(ncls)]
     sc_r = torch.empty(4096 * r * r + 256, dtype=torch.float64, device="cuda")
-    As = [-gram(U_iso, U_rho, cls_d, 4, Pm.ncell, k, sc_r) for k in range(ncls)]
+    As = [small_gemm(gram(U_iso, U_rho, cls_d, 4, Pm.ncell, k, sc_r), alpha=-1.0)
+          for k in range(ncls)]
     A = torch.stack(At + As).cpu().numpy()
-    b_in = (inflow_loads(Pm, X3) @ W).cpu().numpy()
+    b_in = small_gemm(inflow_loads(Pm, X3), W).cpu().numpy()
     torch.cuda.synchronize()
     return RomArrays(U_rho.T.contiguous().cpu().numpy(), U_iso.T.contiguous().cpu().numpy(),
                      A0.cpu().numpy(), A, sv, eps_eff, eps_train, np.asarray(n_sweep), b_in)

@@ -66,6 +66,40 @@ def test_symmetric_eigensolver(R):
         assert rel_err(S @ V, V * ev) < 1e-11
 
 
+def test_pod_weights_and_small_products(R):
+    """Ranking, truncation by eq. (pod_truncation), W = V S^-1 and the reduced products, against
+    numpy on the same eigenpairs (ties included)."""
+    rte, problems, offline = R
+    rng = np.random.default_rng(11)
+    n = 40
+    ev = np.concatenate([np.logspace(4, -20, n - 4), [5.0, 5.0, 0.0, -1e-18]])
+    rng.shuffle(ev)
+    V, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    order = np.argsort(-ev, kind="stable")
+    sv_ref = np.sqrt(np.clip(ev[order], 0.0, None))
+    nz = int(np.sum(sv_ref > sv_ref[0] * 1e-13))
+    for r_fix, eps_pod in ((0, 1e-6), (0, 1e-12), (7, 0.0), (n, 0.0)):
+        say(f"pod_weights r={r_fix} eps={eps_pod}")
+        sv, Wd, r, eps_eff = offline.pod_weights(dev(ev), dev(V), r_fix, eps_pod)
+        if r_fix:
+            r_ref = min(r_fix, nz)
+        else:
+            ratio = np.cumsum(sv_ref) / np.sum(sv_ref)
+            r_ref = min(int(np.argmax(ratio >= 1.0 - eps_pod) + 1), nz)
+        assert r == r_ref
+        assert rel_err(sv, sv_ref) < 1e-15
+        assert abs(eps_eff - max(0.0, 1.0 - sv_ref[:r].sum() / sv_ref.sum())) < 1e-14
+        assert rel_err(host(Wd), V[:, order[:r]] / sv_ref[:r]) < 1e-15
+    A = rng.normal(size=(33, 9))
+    B = rng.normal(size=(33, 5))
+    C = rng.normal(size=(9, 33))
+    say("small_gemm")
+    assert rel_err(host(offline.small_gemm(dev(A), dev(B), trans_a=True)), A.T @ B) < 1e-14
+    assert rel_err(host(offline.small_gemm(dev(C), dev(B), alpha=-2.0)), -2.0 * C @ B) < 1e-14
+    assert np.array_equal(host(offline.small_gemm(dev(C), alpha=-1.0)), -C)
+    assert np.array_equal(host(offline.small_gemm(dev(A), trans_a=True)), A.T)
+
+
 def test_offline_rom_matches_oracle_rom(R):
     """Same training set, window and rank: same singular values and the same ROMSA correction
     (a basis-independent output of the reduced model)."""
