@@ -355,9 +355,10 @@ def pgmres_leg(args, plane, rte, problems, romsad_solves_per_s):
 SERVE_KEYS = [(n, p) for n in (64, 128, 256) for p in (32, 64, 128)]
 
 
-def serve_capacity(n, n_phi):
-    """Slots of a key's pool: about 256M cell-direction updates per batched sweep, 16..64 slots."""
-    return int(min(64, max(16, (256 << 20) // (n * n * n_phi))))
+def serve_capacity(n, n_phi, batch_mcd=256, lo=16, hi=64):
+    """Slots of a key's pool: about batch_mcd million cell-direction updates per batched sweep,
+    lo..hi slots."""
+    return int(min(hi, max(lo, (batch_mcd << 20) // (n * n * n_phi))))
 
 
 def serving_leg(args, rte):
@@ -373,7 +374,9 @@ def serving_leg(args, rte):
                                                     eps_train=args.eps_train)
         torch.cuda.empty_cache()
     t_rom = time.perf_counter() - t0
-    pools = {k: serving.KeyPool(k[0], k[1], serve_capacity(*k), "romsad", roms[k],
+    cap = {k: serve_capacity(*k, args.serve_batch_mcd, args.serve_min_slots, args.serve_max_slots)
+           for k in SERVE_KEYS}
+    pools = {k: serving.KeyPool(k[0], k[1], cap[k], "romsad", roms[k],
                                 precision=args.precision, eps=args.eps, theta=args.theta,
                                 cg_rtol=args.cg_rtol, iters_per_round=args.serve_iters_per_round,
                                 graph_cg_iters=args.serve_graph_cg_iters)
@@ -419,7 +422,7 @@ def serving_leg(args, rte):
     res = srv.run(timed)
     out = serving.latency_summary(res, time.perf_counter() - tw)
     out.update({"rate_req_per_s": rate, "saturated": sat, "keys": len(SERVE_KEYS),
-                "capacity": {f"{k[0]}x{k[0]}/{k[1]}": serve_capacity(*k) for k in SERVE_KEYS},
+                "capacity": {f"{k[0]}x{k[0]}/{k[1]}": cap[k] for k in SERVE_KEYS},
                 "budget_gib": args.serve_budget_gib, "peak_resident_gib": srv.budget.peak / 2**30,
                 "rom_build_s": t_rom, "rom_rank": args.rank, "rom_train": args.serve_train,
                 "graph_cg_iters": args.serve_graph_cg_iters,
@@ -629,12 +632,16 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="open-loop arrival rate (requests/s); 0: 0.8 x the measured capacity")
     ap.add_argument("--serve-train", type=int, default=32)
+    ap.add_argument("--serve-batch-mcd", type=int, default=1024,
+                    help="a key's slots: about this many million cell-direction updates per sweep")
+    ap.add_argument("--serve-min-slots", type=int, default=32)
+    ap.add_argument("--serve-max-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-baseline", type=int, default=3,
                     help="requests of every key timed alone through plain single-instance SI-DSA")
     ap.add_argument("--serve-graph-cg-iters", type=int, default=0,
                     help="> 0: the slot pools run each outer iteration as one HIP graph launch")
-    ap.add_argument("--serve-iters-per-round", type=int, default=1,
+    ap.add_argument("--serve-iters-per-round", type=int, default=2,
                     help="outer iterations of a slot pool between retire/admit rounds")
     args = ap.parse_args()
 
