@@ -505,9 +505,17 @@ __device__ void block_sum2(double &v0, double &v1) {
     }
 }
 
+// Sum of an instance's n block partials, computed by a whole wave (all 64 lanes must be active):
+// lane l adds p[l], p[l + 64], ... in order, then a butterfly over the wave.  Partner lanes add
+// the same two values in opposite order, and IEEE addition is commutative, so every lane ends
+// with the same bits; the order depends on n only, so every block and wave that needs the sum
+// gets the same value.  (One memory round trip per wave: a lane-serial loop over the partials
+// waits on n dependent loads, and every block of every CG kernel repeats it.)
 __device__ double sum_parts(const double *p, int n) {
+    const int lane = threadIdx.x & 63;
     double s = 0.0;
-    for (int k = 0; k < n; ++k) s += p[k];
+    for (int k = lane; k < n; k += 64) s += p[k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     return s;
 }
 
@@ -670,6 +678,135 @@ __global__ void __launch_bounds__(kCgBlock) cg_matvec_kernel(MipArgs a, int it, 
         pat(cell, pc);
         store4(p_new, base + cell, pc);
         store4(q, base + cell, y);
+        for (int k = 0; k < 4; ++k) pq += pc[k] * y[k];
+    }
+    block_sum2(pq, dummy);
+    if (threadIdx.x == 0) slot(part, b, 2, nb)[blk.x] = pq;
+}
+
+// Tiled operator applications.  A block of kCgBlock threads owns a 16 x 16 tile of cells (tile
+// index = block index, row-major over the mesh's tiles), so these kernels need the per-instance
+// block count to equal the tile count.  The value the operator acts on is formed once per cell of
+// the tile and of its one-cell halo into LDS, and the five-cell stencil reads it from there; the
+// one-cell-per-thread kernels form it again for each of a cell's four neighbours, from global
+// memory.
+constexpr int kTile = 16;
+constexpr int kTileW = kTile + 2;
+static_assert(kTile * kTile == kCgBlock, "one thread per cell of a tile");
+
+struct TileCell {
+    int i, j, me;          // mesh coordinates, LDS position
+    bool in;               // inside the mesh
+    long long cell;
+};
+
+__device__ __forceinline__ TileCell tile_cell(const MipArgs &a, int ntx, int tile) {
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int li = threadIdx.x % kTile, lj = threadIdx.x / kTile;
+    TileCell t;
+    t.i = tx * kTile + li;
+    t.j = ty * kTile + lj;
+    t.in = t.i < a.nx && t.j < a.ny;
+    t.cell = (long long)t.j * a.nx + t.i;
+    t.me = (lj + 1) * kTileW + li + 1;
+    return t;
+}
+
+// sp[] <- val(cell) for every in-mesh cell of the tile and of its halo; own[] <- the thread's own
+// cell's value.  Ends with a barrier; every thread of the block must call it.
+template <typename F>
+__device__ void tile_fill(const MipArgs &a, int ntx, int tile, const TileCell &tc, F val,
+                          double4 *sp, double own[4]) {
+    if (tc.in) {
+        val(tc.cell, own);
+        sp[tc.me] = make_double4(own[0], own[1], own[2], own[3]);
+    }
+    if (threadIdx.x < 4 * kTile) {            // the halo: left, right, bottom, top edges
+        const int tx = tile % ntx, ty = tile / ntx;
+        const int side = threadIdx.x / kTile, t = threadIdx.x % kTile;
+        const int hi = side == 0 ? tx * kTile - 1 : side == 1 ? tx * kTile + kTile : tx * kTile + t;
+        const int hj = side == 2 ? ty * kTile - 1 : side == 3 ? ty * kTile + kTile : ty * kTile + t;
+        const int at = side == 0 ? (t + 1) * kTileW
+                     : side == 1 ? (t + 1) * kTileW + kTile + 1
+                     : side == 2 ? t + 1 : (kTile + 1) * kTileW + t + 1;
+        if (hi >= 0 && hi < a.nx && hj >= 0 && hj < a.ny) {
+            double v[4];
+            val((long long)hj * a.nx + hi, v);
+            sp[at] = make_double4(v[0], v[1], v[2], v[3]);
+        }
+    }
+    __syncthreads();
+}
+
+// reader of the tile's values for the operator: a neighbour's linear offset from the cell is
+// -1, +1, -nx or +nx (0: the cell itself, read for a missing neighbour and weighted by zero)
+struct TileReader {
+    const double4 *sp;
+    long long cell, nx;
+    int me;
+    __device__ void operator()(long long c, double v[4]) const {
+        const long long d = c - cell;
+        int o = (int)d;
+        if (d == nx) o = kTileW;
+        else if (d == -nx) o = -kTileW;
+        const double4 t = sp[me + o];
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+};
+
+template <typename TZ>
+__global__ void __launch_bounds__(kCgBlock) cg_matvec_tile_kernel(MipArgs a, int ntx, int it,
+                                                                  double rtol2, int maxit,
+                                                                  const TZ *z,
+                                                                  const double *p_old,
+                                                                  double *p_new, double *q,
+                                                                  double *part, int *state,
+                                                                  int *iters, int *n_running) {
+    __shared__ double4 sp[kTileW * kTileW];
+    const Blk blk = xcd_block();
+    const int b = blk.y;
+    if (state[b] != 1) return;
+    const int nb = a.nblk;
+    const double bb = sum_parts(slot(part, b, 4, nb), nb);
+    const double rr = it == 1 ? bb : sum_parts(slot(part, b, 3, nb), nb);
+    const bool done = !(rr > rtol2 * bb);     // also stops on NaN
+    if (done || it > maxit) {
+        if (blk.x == 0 && threadIdx.x == 0) {
+            const int st = done && rr == rr ? 2 : 3;
+            state[b] = st;
+            iters[b] = it - 1;
+            atomicSub(n_running, 1);
+            if (st == 3) atomicAdd(n_running + 1, 1);
+        }
+        return;
+    }
+    double beta = 0.0;
+    if (it > 1) {
+        const double rz_cur = sum_parts(slot(part, b, (it - 1) & 1, nb), nb);
+        const double rz_prev = sum_parts(slot(part, b, it & 1, nb), nb);
+        beta = rz_cur / rz_prev;
+    }
+    const size_t base = (size_t)b * a.ncell;
+    auto pat = [&](long long c, double v[4]) {
+        double zz[4];
+        load4(z, base + c, zz);
+        if (it > 1) {
+            double po[4];
+            load4(p_old, base + c, po);
+            for (int k = 0; k < 4; ++k) v[k] = zz[k] + beta * po[k];
+        } else {
+            for (int k = 0; k < 4; ++k) v[k] = zz[k];
+        }
+    };
+    const TileCell tc = tile_cell(a, ntx, blk.x);
+    double pc[4] = {0.0, 0.0, 0.0, 0.0};
+    tile_fill(a, ntx, blk.x, tc, pat, sp, pc);
+    double pq = 0.0, dummy = 0.0;
+    if (tc.in) {
+        double y[4];
+        mip_apply_hoisted<double>(a, b, tc.i, tc.j, TileReader{sp, tc.cell, a.nx, tc.me}, y);
+        store4(p_new, base + tc.cell, pc);
+        store4(q, base + tc.cell, y);
         for (int k = 0; k < 4; ++k) pq += pc[k] * y[k];
     }
     block_sum2(pq, dummy);
@@ -1187,6 +1324,85 @@ __global__ void __launch_bounds__(kCgBlock) mg_post_dg_kernel(MipArgs a, const i
     if (threadIdx.x == 0) slot(part, b, s, a.nblk)[blk.x] = rz;
 }
 
+// mg_resid_dg_kernel on 16 x 16 tiles (t = r - A z with z read through LDS)
+template <typename TZ>
+__global__ void __launch_bounds__(kCgBlock) mg_resid_dg_tile_kernel(MipArgs a, int ntx, int *state,
+                                                                    const double *r, const TZ *z,
+                                                                    TZ *t, const double *part,
+                                                                    const double *tol2,
+                                                                    int *n_running) {
+    __shared__ double4 sp[kTileW * kTileW];
+    const Blk blk = xcd_block();
+    const int b = blk.y;
+    if (state[b] != 1) return;
+    {
+        const double bb = sum_parts(part + ((size_t)b * 5 + 4) * a.nblk, a.nblk);
+        const double rr = sum_parts(part + ((size_t)b * 5 + 3) * a.nblk, a.nblk);
+        if (!(rr > tol2[0] * bb)) {
+            if (blk.x == 0 && threadIdx.x == 0) {
+                const int st = rr == rr ? 2 : 3;
+                state[b] = st;
+                atomicSub(n_running, 1);
+                if (st == 3) atomicAdd(n_running + 1, 1);
+            }
+            return;
+        }
+    }
+    const size_t base = (size_t)b * a.ncell;
+    auto zat = [&](long long c, double v[4]) { load4(z, base + c, v); };
+    const TileCell tc = tile_cell(a, ntx, blk.x);
+    double zc[4];
+    tile_fill(a, ntx, blk.x, tc, zat, sp, zc);
+    if (!tc.in) return;
+    double y[4], rv[4];
+    mip_apply_hoisted<TZ>(a, b, tc.i, tc.j, TileReader{sp, tc.cell, a.nx, tc.me}, y);
+    load4(r, base + tc.cell, rv);
+    for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
+    store4(t, base + tc.cell, y);
+}
+
+// mg_post_dg_kernel on 16 x 16 tiles (z + P x0 formed once per cell into LDS)
+template <typename TZ>
+__global__ void __launch_bounds__(kCgBlock) mg_post_dg_tile_kernel(MipArgs a, int ntx,
+                                                                   const int *state,
+                                                                   const double *r,
+                                                                   const double *x0, VG g,
+                                                                   const TZ *z, TZ *z_out,
+                                                                   double *part, int s) {
+    __shared__ double4 sp[kTileW * kTileW];
+    const Blk blk = xcd_block();
+    const int b = blk.y;
+    if (state[b] != 1) return;
+    const size_t base = (size_t)b * a.ncell;
+    const double sqa = sqrt(a.hx * a.hy);
+    const double *xb = x0 + (size_t)b * g.nv;
+    auto zat = [&](long long c, double v[4]) {
+        double pc[4];
+        load4(z, base + c, v);
+        p_cell(xb, g.nvx, (int)(c % a.nx), (int)(c / a.nx), sqa, pc);
+        for (int k = 0; k < 4; ++k) v[k] += pc[k];
+    };
+    const TileCell tc = tile_cell(a, ntx, blk.x);
+    double zc[4] = {0.0, 0.0, 0.0, 0.0};
+    tile_fill(a, ntx, blk.x, tc, zat, sp, zc);
+    double rz = 0.0, dummy = 0.0;
+    if (tc.in) {
+        double y[4], rv[4], dz[4], zn[4];
+        mip_apply_hoisted<TZ>(a, b, tc.i, tc.j, TileReader{sp, tc.cell, a.nx, tc.me}, y);
+        load4(r, base + tc.cell, rv);
+        for (int k = 0; k < 4; ++k) y[k] = rv[k] - y[k];
+        binv_apply(a, b, tc.cell, y, dz);
+        // (r, z) of the value as stored, so that the CG's beta matches the z it reads
+        for (int k = 0; k < 4; ++k) {
+            zn[k] = (double)(TZ)(zc[k] + kOmegaDG * dz[k]);
+            rz += rv[k] * zn[k];
+        }
+        store4(z_out, base + tc.cell, zn);
+    }
+    block_sum2(rz, dummy);
+    if (threadIdx.x == 0) slot(part, b, s, a.nblk)[blk.x] = rz;
+}
+
 // two damped Jacobi sweeps from zero: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - S x1)
 __global__ void mg_vpre_kernel(const int *state, VG g, const float *S, const double *bv, double *x2) {
     const Blk blk = xcd_block();
@@ -1669,16 +1885,26 @@ hipError_t mg_precond_t(const rte_problem *p, const CGSpace &c, int slot_id, hip
     TZ *t = reinterpret_cast<TZ *>(c.mg.t);
     // z holds the pre-smoothed z = omega D^-1 r (written with r by the CG kernels);
     // residual t = r - A z and the coarse right-hand side P^T t
-    hipLaunchKernelGGL(mg_resid_dg_kernel<TZ>, gc, dim3(256), 0, s, a, c.state, c.r, z, t,
-                       c.part, c.tol2, c.n_running);
+    const int ntx = (p->nx + kTile - 1) / kTile, nty = (p->ny + kTile - 1) / kTile;
+    const bool tiled = (long long)ntx * nty == c.nblk && (long long)c.nblk == (long long)gc.x;
+    if (tiled)
+        hipLaunchKernelGGL(mg_resid_dg_tile_kernel<TZ>, gc, dim3(kCgBlock), 0, s, a, ntx, c.state,
+                           c.r, z, t, c.part, c.tol2, c.n_running);
+    else
+        hipLaunchKernelGGL(mg_resid_dg_kernel<TZ>, gc, dim3(256), 0, s, a, c.state, c.r, z, t,
+                           c.part, c.tol2, c.n_running);
     // a grid-wide level 0 gets its first smoothing step (into xb) with the restriction
     const bool x_first = vertex_grid_level(p, c, 0);
     hipLaunchKernelGGL(mg_restrict_dg_kernel<TZ>, dim3(blocks_for(L0.nv, 256), p->B), dim3(256),
                        0, s, a, c.state, t, g0, L0.bv, L0.S32, x_first ? L0.xb : nullptr);
     const double *x0 = vcycle(p, c, 0, s);
     // coarse correction and post-smoothing; the preconditioned residual goes to t
-    hipLaunchKernelGGL(mg_post_dg_kernel<TZ>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a, c.state,
-                       c.r, x0, g0, z, t, c.part, slot_id);
+    if (tiled)
+        hipLaunchKernelGGL(mg_post_dg_tile_kernel<TZ>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
+                           ntx, c.state, c.r, x0, g0, z, t, c.part, slot_id);
+    else
+        hipLaunchKernelGGL(mg_post_dg_kernel<TZ>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
+                           c.state, c.r, x0, g0, z, t, c.part, slot_id);
     return hipGetLastError();
 }
 }  // namespace
@@ -1734,17 +1960,29 @@ hipError_t launch_cg_iteration(const rte_problem *p, const CGSpace &c, int it, d
     const double *p_old = (it & 1) ? c.p0 : c.p1;
     const double *z = c.mg.L == 0 ? c.z : c.mg.t;    // preconditioned residual
     const int bj = c.mg.L == 0 ? 1 : 2;
+    const int ntx = (p->nx + kTile - 1) / kTile, nty = (p->ny + kTile - 1) / kTile;
+    const bool tiled = (long long)ntx * nty == c.nblk;
+    if (tiled && c.zf32)
+        hipLaunchKernelGGL(cg_matvec_tile_kernel<float>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s,
+                           a, ntx, it, rtol * rtol, maxit, reinterpret_cast<const float *>(z),
+                           p_old, p_new, c.q, c.part, c.state, c.iters, c.n_running);
+    else if (tiled)
+        hipLaunchKernelGGL(cg_matvec_tile_kernel<double>, dim3(c.nblk, p->B), dim3(kCgBlock), 0,
+                           s, a, ntx, it, rtol * rtol, maxit, z, p_old, p_new, c.q, c.part,
+                           c.state, c.iters, c.n_running);
     if (c.zf32) {
-        hipLaunchKernelGGL(cg_matvec_kernel<float>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
-                           it, rtol * rtol, maxit, reinterpret_cast<const float *>(z), p_old,
-                           p_new, c.q, c.part, c.state, c.iters, c.n_running);
+        if (!tiled)
+            hipLaunchKernelGGL(cg_matvec_kernel<float>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s,
+                               a, it, rtol * rtol, maxit, reinterpret_cast<const float *>(z),
+                               p_old, p_new, c.q, c.part, c.state, c.iters, c.n_running);
         hipLaunchKernelGGL(cg_update_kernel<float>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
                            it, p_new, c.q, c.x, c.r, reinterpret_cast<float *>(c.z), c.part,
                            c.state, c.iters, bj);
     } else {
-        hipLaunchKernelGGL(cg_matvec_kernel<double>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
-                           it, rtol * rtol, maxit, z, p_old, p_new, c.q, c.part, c.state, c.iters,
-                           c.n_running);
+        if (!tiled)
+            hipLaunchKernelGGL(cg_matvec_kernel<double>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s,
+                               a, it, rtol * rtol, maxit, z, p_old, p_new, c.q, c.part, c.state,
+                               c.iters, c.n_running);
         hipLaunchKernelGGL(cg_update_kernel<double>, dim3(c.nblk, p->B), dim3(kCgBlock), 0, s, a,
                            it, p_new, c.q, c.x, c.r, c.z, c.part, c.state, c.iters, bj);
     }
