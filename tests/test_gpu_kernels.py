@@ -149,10 +149,13 @@ def test_dsa1d_matches_appendix_b(R):
         assert rel_err(delta[b], ref) < 1e-12
 
 
+# 11x7, 16x16, 64x48, 32x32, 47x47 and 100x16 run the operator on 16x16 tiles (the tile count
+# equals the CG's block count; 47x47 and 100x16 have ragged tiles), 40x33 one cell per thread
 @pytest.mark.parametrize("nx,ny,L,mg", [(11, 7, 1.0, True), (40, 33, 10.0, True),
                                         (16, 16, 0.05, True), (64, 48, 3.0, True),
                                         (32, 32, 30.0, True), (40, 33, 10.0, False),
-                                        (16, 16, 0.05, False)])
+                                        (16, 16, 0.05, False), (47, 47, 2.0, True),
+                                        (100, 16, 5.0, True)])
 def test_dsa2d_matches_mip_direct_solve(R, nx, ny, L, mg):
     import torch
     rte, problems = R
