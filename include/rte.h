@@ -392,6 +392,26 @@ int rte_sym_eig(double *A, int n, double *evals, double *evecs, rte_stream_t str
 int rte_pod_weights(const double *evals, const double *evecs, int ncol, int r, double eps_pod,
                     double *sv, double *W, int *r_out, double *eps_out, rte_stream_t stream);
 
+/* Upper Cholesky factor of a small SPD matrix and its inverse (the QR route of the POD, Sec. 3.1:
+ * CholeskyQR of the snapshot matrix F from Gram matrices): G [n][n] (device FP64, row-major,
+ * symmetric), n <= 256; R and T = R^-1 [n][n] upper triangular with G + shift I = R^T R; work
+ * [n][n] scratch.  shifted = 0: no shift; else shift = 11 (m n + n (n+1)) u trace(G), u = 2^-53,
+ * for the Gram matrix of an m x n matrix (shifted CholeskyQR, m >= 1).  info (device int [1]):
+ * 0, or k + 1 if pivot k was not positive (R, T then incomplete).  dev (device [1], or NULL):
+ * max |G_ij - delta_ij|, how far the columns whose Gram matrix G is are from orthonormal. */
+int rte_chol_upper(const double *G, int n, int shifted, long long m, double *work, double *R,
+                   double *T, int *info, double *dev, rte_stream_t stream);
+
+/* One-sided Jacobi SVD of a small matrix A [n][n] (device FP64, row-major, n <= 256): lam [n] the
+ * squared singular values (unsorted), V [n][n] the right singular vectors as columns, and US
+ * [n][n] (or NULL) = A V, whose column k is s_k u_k; work: 2 n^2 doubles of scratch.  Rounds of
+ * the round-robin ordering until a sweep applies no rotation or max_sweeps; sweeps_out (device
+ * int [1]) the sweeps run (max_sweeps: not converged).  (lam, V) or (lam, US) plug into
+ * rte_pod_weights in place of the Gram eigenpairs: with US it returns the kept left singular
+ * vectors u_k = US[:, k] / s_k. */
+int rte_svd_jacobi(const double *A, int n, double *work, double *lam, double *V, double *US,
+                   int max_sweeps, int *sweeps_out, rte_stream_t stream);
+
 /* C = alpha op(A) B for small dense FP64 matrices (device, row-major): op(A) = A [m][k]
  * (trans_a = 0) or the transpose of A [k][m] (trans_a = 1); B [k][n], or NULL for the identity
  * (then k == n and C = alpha op(A)); C [m][n].  The reduced products of the offline construction

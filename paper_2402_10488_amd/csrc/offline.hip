@@ -6,6 +6,10 @@
 //                      (v_mfma_f64_16x16x4f64, split over the rows, fixed-order split sum)
 //   eigenpairs of G    cyclic Jacobi, one workgroup (the method of snapshots: F = U S V^T with
 //                      F^T F = V S^2 V^T, U = F V S^-1)
+//   QR route           shifted CholeskyQR3 of F from Gram matrices of F and of two transformed
+//                      copies (chol_upper_kernel: R and R^-1 of a small SPD matrix), then a
+//                      one-sided Jacobi SVD of the small triangular factor (svd_jacobi_kernel):
+//                      singular values far below the largest keep their relative accuracy
 //   basis weights      sorted singular values, the rank (fixed or by eq. (pod_truncation)) and
 //                      W = V S^-1 of the kept columns (pod_weights_kernel, one workgroup)
 //   basis              U = X W for a small W (v_mfma_f64_16x16x4f64)
@@ -380,6 +384,170 @@ __global__ void __launch_bounds__(256) pod_weights_kernel(const double *evals, c
     }
 }
 
+// Cholesky factor of a small SPD matrix, G + shift I = R^T R (R upper triangular, n <= 256), and
+// T = R^-1, one workgroup.  W (n x n scratch) receives G + shift I and is overwritten by the
+// right-looking elimination.  With shifted != 0 the shift is 11 (m n + n (n + 1)) u trace(G)
+// (u the FP64 unit roundoff): the shift of shifted CholeskyQR, which keeps the factorization of
+// the Gram matrix of an m x n matrix defined for condition numbers up to about 1/u.  A pivot that
+// is not positive leaves info = its index + 1 (else 0) and stops.  dev (optional) receives
+// max |G_ij - delta_ij|, how far the factored columns are from orthonormal.
+__global__ void __launch_bounds__(256) chol_upper_kernel(const double *G, int n, int shifted,
+                                                         long long m, double *W, double *R,
+                                                         double *T, int *info, double *dev) {
+    __shared__ double piv;
+    __shared__ double tr_part[256], dv_part[256];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    double tr = 0.0, dv = 0.0;
+    for (int i = t; i < n; i += blockDim.x) tr += G[(size_t)i * n + i];
+    for (int i = t; i < n * n; i += blockDim.x)
+        dv = fmax(dv, fabs(G[i] - (i / n == i % n ? 1.0 : 0.0)));
+    tr_part[t] = tr;
+    dv_part[t] = dv;
+    if (t == 0) bad = 0;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0, d = 0.0;
+        for (int k = 0; k < (int)blockDim.x; ++k) { s += tr_part[k]; d = fmax(d, dv_part[k]); }
+        tr_part[0] = s;
+        if (dev) *dev = d;
+    }
+    __syncthreads();
+    const double u = 0.5 * 2.220446049250313e-16;
+    const double shift = shifted ? 11.0 * ((double)m * n + (double)n * (n + 1)) * u * tr_part[0] : 0.0;
+    for (int i = t; i < n * n; i += blockDim.x) {
+        const int r = i / n, c = i % n;
+        W[i] = G[i] + (r == c ? shift : 0.0);
+        R[i] = 0.0;
+        T[i] = 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (t == 0) {
+            const double d = W[(size_t)j * n + j];
+            if (!(d > 0.0)) {
+                bad = j + 1;
+                piv = 1.0;
+            } else {
+                piv = sqrt(d);
+            }
+            R[(size_t)j * n + j] = piv;
+        }
+        __syncthreads();
+        if (bad) break;
+        const double rjj = piv;
+        for (int i = j + 1 + t; i < n; i += blockDim.x) R[(size_t)j * n + i] = W[(size_t)j * n + i] / rjj;
+        __syncthreads();
+        // trailing update of the upper triangle: W[i][k] -= R[j][i] R[j][k], j < i <= k
+        const int nt = n - j - 1;
+        for (int idx = t; idx < nt * nt; idx += blockDim.x) {
+            const int i = j + 1 + idx / nt, k = j + 1 + idx % nt;
+            if (k >= i) W[(size_t)i * n + k] -= R[(size_t)j * n + i] * R[(size_t)j * n + k];
+        }
+        __syncthreads();
+    }
+    if (t == 0) *info = bad;
+    if (bad) return;
+    // T = R^-1 column by column (back substitution), one thread per column
+    for (int c = t; c < n; c += blockDim.x) {
+        T[(size_t)c * n + c] = 1.0 / R[(size_t)c * n + c];
+        for (int i = c - 1; i >= 0; --i) {
+            double acc = 0.0;
+            for (int k = i + 1; k <= c; ++k) acc += R[(size_t)i * n + k] * T[(size_t)k * n + c];
+            T[(size_t)i * n + c] = -acc / R[(size_t)i * n + i];
+        }
+    }
+}
+
+// One-sided (Hestenes) Jacobi SVD of a small n x n matrix A (n <= 256), one workgroup of four
+// waves.  Columns are stored transposed (At[col][row]) so that each column is contiguous; pairs of
+// columns are orthogonalized by plane rotations applied from the right, A J and V J, in the
+// round-robin order of the tournament (n/2 disjoint pairs per round, one wave per pair, rounds
+// separated by barriers), until a sweep applies no rotation (|a_p . a_q| <= 1e-15 |a_p| |a_q| for
+// every pair) or after max_sweeps.  Then A V = U S with orthogonal columns: lam[k] = |A v_k|^2 =
+// s_k^2 (unsorted), V[i][k] = v_k[i] (right singular vectors as columns) and, if US is given,
+// US[i][k] = (A v_k)[i] = s_k u_k[i].  Each s_k comes with a small relative error, also for
+// singular values far below the largest.
+__global__ void __launch_bounds__(256) svd_jacobi_kernel(const double *A, int n, double *At,
+                                                         double *Vt, double *lam, double *V,
+                                                         double *US, int max_sweeps,
+                                                         int *sweeps_out) {
+    __shared__ int rotated;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6, nw = (int)blockDim.x >> 6;
+    const int m = n + (n & 1);                  // padded size (dummy column m-1 when n is odd)
+    for (int i = t; i < n * n; i += blockDim.x) {
+        const int r = i / n, c = i % n;
+        At[(size_t)c * n + r] = A[i];
+        Vt[i] = (r == c) ? 1.0 : 0.0;
+    }
+    int sw = 0;
+    for (; sw < max_sweeps; ++sw) {
+        if (t == 0) rotated = 0;
+        __syncthreads();
+        for (int round = 0; round < m - 1; ++round) {
+            for (int k = wave; k < m / 2; k += nw) {
+                int a, b;
+                if (k == 0) { a = m - 1; b = round; }
+                else {
+                    a = (round + k) % (m - 1);
+                    b = (round - k + (m - 1)) % (m - 1);
+                }
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                if (q >= n) continue;                    // the dummy column
+                double *cp = At + (size_t)p * n, *cq = At + (size_t)q * n;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = lane; i < n; i += 64) {
+                    const double x = cp[i], y = cq[i];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    al += __shfl_xor(al, off, 64);
+                    be += __shfl_xor(be, off, 64);
+                    ga += __shfl_xor(ga, off, 64);
+                }
+                if (!(fabs(ga) > 1e-15 * sqrt(al * be))) continue;   // wave-uniform
+                const double zeta = (be - al) / (2.0 * ga);
+                const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+                for (int i = lane; i < n; i += 64) {
+                    const double x = cp[i], y = cq[i];
+                    cp[i] = c * x - s * y;
+                    cq[i] = s * x + c * y;
+                }
+                double *vp = Vt + (size_t)p * n, *vq = Vt + (size_t)q * n;
+                for (int i = lane; i < n; i += 64) {
+                    const double x = vp[i], y = vq[i];
+                    vp[i] = c * x - s * y;
+                    vq[i] = s * x + c * y;
+                }
+                if (lane == 0) rotated = 1;
+            }
+            __syncthreads();
+        }
+        const int any = rotated;
+        __syncthreads();
+        if (!any) break;
+    }
+    for (int k = wave; k < n; k += nw) {
+        double s2 = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double x = At[(size_t)k * n + i];
+            s2 += x * x;
+        }
+        for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+        if (lane == 0) lam[k] = s2;
+    }
+    for (int i = t; i < n * n; i += blockDim.x) {
+        const int r = i / n, c = i % n;
+        V[i] = Vt[(size_t)c * n + r];
+        if (US) US[i] = At[(size_t)c * n + r];
+    }
+    if (t == 0) *sweeps_out = sw;
+}
+
 // C[m][n] = alpha op(A)[m][k] B[k][n] (B null: the k x n identity, so C = alpha op(A)); op(A) = A
 // [m][k] or, transposed, A [k][m]; row-major FP64, one thread per entry, for the reduced (r x r,
 // ncol x r) products of the offline ROM construction.
@@ -494,6 +662,24 @@ int rte_pod_weights(const double *evals, const double *evecs, int ncol, int r, d
     if (r == 0 && !(eps_pod >= 0.0 && eps_pod < 1.0)) return RTE_EINVAL;
     hipLaunchKernelGGL(rte::pod_weights_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, evals,
                        evecs, ncol, r, eps_pod, sv, W, r_out, eps_out);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_chol_upper(const double *G, int n, int shifted, long long m, double *work, double *R,
+                   double *T, int *info, double *dev, rte_stream_t stream) {
+    if (!G || !work || !R || !T || !info || n < 1 || n > 256 || (shifted && m < 1))
+        return RTE_EINVAL;
+    hipLaunchKernelGGL(rte::chol_upper_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, G, n,
+                       shifted, m, work, R, T, info, dev);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
+}
+
+int rte_svd_jacobi(const double *A, int n, double *work, double *lam, double *V, double *US,
+                   int max_sweeps, int *sweeps_out, rte_stream_t stream) {
+    if (!A || !work || !lam || !V || !sweeps_out || n < 1 || n > 256 || max_sweeps < 1)
+        return RTE_EINVAL;
+    hipLaunchKernelGGL(rte::svd_jacobi_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, A, n,
+                       work, work + (size_t)n * n, lam, V, US, max_sweeps, sweeps_out);
     return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EDEVICE;
 }
 

@@ -86,7 +86,7 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
             "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve", "rte_f_natural",
             "rte_last_device_error", "rte_sweep_noalloc", "rte_tune_sweep",
-            "rte_pod_weights", "rte_small_gemm"]
+            "rte_pod_weights", "rte_small_gemm", "rte_chol_upper", "rte_svd_jacobi"]
 
 
 def _load():

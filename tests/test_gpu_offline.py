@@ -100,14 +100,90 @@ def test_pod_weights_and_small_products(R):
     assert np.array_equal(host(offline.small_gemm(dev(A), trans_a=True)), A.T)
 
 
-def test_offline_rom_matches_oracle_rom(R):
+def test_cholesky_and_jacobi_svd_kernels(R):
+    """rte_chol_upper (plain and shifted) and rte_svd_jacobi against their definitions and numpy,
+    on matrices with singular values down to 1e-13 of the largest."""
+    import torch
+    rte, problems, offline = R
+    rng = np.random.default_rng(17)
+    for n in (1, 5, 24, 61):
+        M = rng.normal(size=(n, n))
+        G = M @ M.T + n * np.eye(n)
+        say(f"chol_upper n={n}")
+        Rd, Td, info, dev_ = offline.chol_upper(dev(G))
+        Rh, Th = host(Rd), host(Td)
+        assert info == 0
+        assert abs(dev_ - np.abs(G - np.eye(n)).max()) <= 1e-15 * np.abs(G).max()
+        assert np.array_equal(np.triu(Rh), Rh) and np.array_equal(np.triu(Th), Th)
+        assert rel_err(Rh.T @ Rh, G) < 1e-14
+        assert rel_err(Rh, np.linalg.cholesky(G).T) < 1e-13
+        assert np.abs(Rh @ Th - np.eye(n)).max() < 1e-13
+        # the shifted factorization: G + s I with s = 11 (m n + n (n + 1)) u trace(G)
+        m = 1000
+        s_ = 11.0 * (m * n + n * (n + 1)) * 2.0 ** -53 * np.trace(G)
+        Rs, _, info, _ = offline.chol_upper(dev(G), shift_rows=m)
+        Rs = host(Rs)
+        assert info == 0 and rel_err(Rs.T @ Rs, G + s_ * np.eye(n)) < 1e-14
+    # a pivot that is not positive is reported, not hidden
+    _, _, info, _ = offline.chol_upper(dev(np.diag([1.0, -1.0, 2.0])))
+    assert info == 2
+    for n in (1, 6, 33, 64):
+        U0, _ = np.linalg.qr(rng.normal(size=(n, n)))
+        V0, _ = np.linalg.qr(rng.normal(size=(n, n)))
+        sig = np.logspace(0, -13, n)
+        A = np.triu((U0 * sig) @ V0.T) if n > 1 else np.array([[3.0]])
+        say(f"svd_jacobi n={n}")
+        lam, V, US = offline.svd_jacobi(dev(A))
+        lam, V, US = host(lam), host(V), host(US)
+        ref = np.linalg.svd(A, compute_uv=False)
+        s_gpu = np.sort(np.sqrt(lam))[::-1]
+        assert np.all(np.abs(s_gpu - ref) <= 1e-14 * ref[0] + 1e-10 * ref)
+        assert np.abs(V.T @ V - np.eye(n)).max() < 1e-13
+        assert rel_err(US, A @ V) < 1e-13
+        C = US.T @ US                                    # orthogonal columns of A V
+        off = np.abs(C - np.diag(np.diag(C)))
+        assert np.all(off <= 1e-14 * np.sqrt(np.outer(np.diag(C), np.diag(C))) + 1e-30)
+
+
+def test_pod_qr_route_small_singular_values(R):
+    """The QR route of the POD on columns with singular values down to 1e-12 of the largest:
+    singular values and the basis against numpy's SVD (the Gram route cannot resolve them).
+    (pod_weights keeps singular values above 1e-13 of the largest.)"""
+    import torch
+    rte, problems, offline = R
+    rng = np.random.default_rng(23)
+    n, L = 40, 30011
+    U0, _ = np.linalg.qr(rng.normal(size=(L, n)))
+    V0, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    sig = np.logspace(0, -12, n)
+    F = (U0 * sig) @ V0.T
+    say("pod_qr")
+    sv, Wq, r, eps_eff, Q = offline.pod_qr([dev(F.T)], r=n)
+    assert r == n
+    assert np.all(np.abs(sv - sig) <= 2e-15 * sig[0] + 1e-8 * sig)
+    Ub = host(offline.combine(Q, Wq))                   # [r, L], rows = basis vectors
+    assert np.abs(Ub @ Ub.T - np.eye(n)).max() < 1e-12
+    # each basis vector is the matching left singular vector, up to sign
+    dots = np.abs(np.sum(Ub * U0.T, axis=1))
+    assert np.all(np.abs(dots[:30] - 1.0) < 1e-9)
+    # the Gram route on the same columns loses the tail
+    X = dev(F.T)
+    ev, Vg = offline.sym_eig(offline.gram(X, X))
+    sv_g, _, _, _ = offline.pod_weights(ev, Vg, n, 0.0)
+    say(f"  worst relative error of sv below 1e-9: QR {np.max(np.abs(sv - sig)[sig < 1e-9] / sig[sig < 1e-9]):.1e}, "
+        f"Gram {np.max(np.abs(sv_g - sig)[sig < 1e-9] / sig[sig < 1e-9]):.1e}")
+
+
+@pytest.mark.parametrize("pod", ["qr", "gram"])
+def test_offline_rom_matches_oracle_rom(R, pod):
     """Same training set, window and rank: same singular values and the same ROMSA correction
-    (a basis-independent output of the reduced model)."""
+    (a basis-independent output of the reduced model), by both POD routes."""
     import torch
     rte, problems, offline = R
     train = W.c2_lattice([30000 + i for i in range(5)], n=12, n_phi=8)
-    say("offline rom build")
-    ra = offline.build_correction_rom(train, r=9, window=3, eps_train=1e-12, cg_rtol=1e-13)
+    say(f"offline rom build ({pod})")
+    ra = offline.build_correction_rom(train, r=9, window=3, eps_train=1e-12, cg_rtol=1e-13,
+                                      pod=pod)
     discs = [discretize(train, b) for b in range(train.B)]
     ro = orom.build_correction_rom(discs, orom.plane_affine(discs[0]), orom.plane_psi, window=3,
                                    r=9, eps_train=1e-12)
@@ -126,6 +202,45 @@ def test_offline_rom_matches_oracle_rom(R):
         d = discretize(test, b)
         ref = ro.correct(d, d.apply_Ss(rs[b] - rp[b]))
         assert rel_err(delta[b], ref) < 1e-7, rel_err(delta[b], ref)
+
+
+def test_offline_rom_qr_route_at_the_papers_truncation(R):
+    """The homogeneous-medium family (Sec. 4.3.1) at 16^2 with CL(8, 2), its 21 training values,
+    window 3, truncated at eps_POD = 1e-9 as in the paper: the kept singular values reach 5e-9 of
+    the largest and the first dropped ones lie below, where the Gram matrix no longer resolves
+    them.  The library's QR route gives the oracle's rank and singular values (the oracle takes
+    LAPACK's SVD) and a ROM whose ROMSA corrections equal the oracle ROM's (measured 3.8e-8)."""
+    import torch
+    rte, problems, offline = R
+    quad = ("cl", (8, 2))
+    train = W.homogeneous_medium(W.homogeneous_training(), 16, quad)
+    say("offline rom build, homogeneous family, eps_pod 1e-9")
+    ra = offline.build_correction_rom(train, r=None, eps_pod=1e-9, window=3, eps_train=1e-12,
+                                      cg_rtol=1e-13)
+    discs = [discretize(train, b) for b in range(train.B)]
+    ro = orom.build_correction_rom(discs, orom.plane_affine(discs[0]), orom.plane_psi, window=3,
+                                   eps_pod=1e-9, eps_train=1e-12)
+    k = ro.r
+    r_gpu = ra.U_rho.shape[1]
+    say(f"  rank {r_gpu} (oracle {k}), sv[r-1]/sv[0] {ro.sv[k - 1] / ro.sv[0]:.1e}")
+    assert r_gpu == k
+    sv_a, sv_o = np.asarray(ra.sv)[:k + 2], np.asarray(ro.sv)[:k + 2]
+    assert np.all(np.abs(sv_a - sv_o) <= 1e-13 * sv_o[0] + 1e-8 * sv_o)
+    test = W.homogeneous_medium(W.homogeneous_test(3), 16, quad)
+    P = problems.plane_problem(test)
+    Rm = rte.Rom(P, ra.U_rho, ra.U_iso, ra.A0, ra.A, ra.eps_pod, ra.eps_train)
+    rng = np.random.default_rng(13)
+    rs = rng.uniform(0, 1, (test.B, P.ndof))
+    rp = rs + 1e-3 * rng.normal(size=rs.shape)
+    delta = torch.zeros((test.B, P.ndof), dtype=torch.float64, device="cuda")
+    rte.rom_correct(P, Rm, problems.plane_psi(test), dev(rs), dev(rp), delta, precision="fp64")
+    delta = host(delta)
+    errs = []
+    for b in range(test.B):
+        d = discretize(test, b)
+        errs.append(rel_err(delta[b], ro.correct(d, d.apply_Ss(rs[b] - rp[b]))))
+    say(f"  ROMSA correction vs the oracle ROM's: max {max(errs):.1e}")
+    assert max(errs) < 1e-6
 
 
 def test_offline_rom_fp32_snapshots_and_chunks(R):
