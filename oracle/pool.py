@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def pool_size(limit=16):
-    """Worker count: the host's cores, at most ``limit`` (the CPU share of a one-GPU machine)."""
+    """Worker count: the host's cores, at most ``limit`` (the CPU share of a one-GPU host)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
