@@ -481,6 +481,56 @@ def solve_timed(rte, P, rho, reps=1, **kw):
     return r, (time.perf_counter() - t0) / reps
 
 
+def split_leg(args, plane, rte, problems, rom_arrays, tuning, ref_n_sweep, headline_ms):
+    """The headline batch solved as ``args.split`` sub-batches at once, each with its own problem
+    handle, workspace and stream in its own host thread (rte_sisa_solve_multi), with the
+    headline's sweep schedule, so every instance's result equals its result in the headline
+    solve (checked on the sweep counts).  While one sub-batch's host polls or its kernels leave
+    gaps, another's run."""
+    import torch
+    K = args.split
+    B = plane.B
+    bounds = [B * k // K for k in range(K + 1)]
+    subs = []
+    for k in range(K):
+        sub = plane.subset(range(bounds[k], bounds[k + 1]))
+        Pk = problems.plane_problem(sub, dg=tuning["dg"], wpb=tuning["wpb"])
+        Rk = (rte.Rom(Pk, rom_arrays.U_rho, rom_arrays.U_iso, rom_arrays.A0, rom_arrays.A,
+                      rom_arrays.eps_pod, rom_arrays.eps_train) if rom_arrays is not None else None)
+        psik = problems.plane_psi(sub) if rom_arrays is not None else None
+        rhok = torch.zeros((Pk.B, Pk.ndof), dtype=torch.float64, device="cuda")
+        subs.append((Pk, Rk, psik, rhok, Pk.workspace(args.mode, Rk, args.precision, 500)))
+    streams = [torch.cuda.Stream() for _ in range(K)]
+    kw = dict(mode=args.mode, eps=args.eps, max_iter=500, theta=args.theta, cg_rtol=args.cg_rtol,
+              precision=args.precision, poll_every=args.poll_every)
+
+    def step():
+        for s_ in subs:
+            s_[3].zero_()
+        torch.cuda.synchronize()
+        return rte.sisa_solve_multi([s_[0] for s_ in subs], [s_[3] for s_ in subs], streams,
+                                    roms=[s_[1] for s_ in subs], psis=[s_[2] for s_ in subs],
+                                    wss=[s_[4] for s_ in subs], **kw)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.split_steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.split_steps
+    n_sweep = np.concatenate([r.n_sweep for r in res])
+    cd = float(n_sweep.sum()) * plane.nx * plane.ny * subs[0][0].n_dir
+    del subs
+    torch.cuda.empty_cache()
+    return {"parts": K, "steps": args.split_steps, "value": cd / dt, "unit": "cell-dir updates/s",
+            "ms_per_step": dt * 1e3, "solves_per_s": B / dt, "vs_headline": headline_ms / (dt * 1e3),
+            "sweep_counts_equal_headline": bool(np.array_equal(n_sweep, ref_n_sweep)),
+            "note": "the same batch, schedule and results as the headline, as concurrent "
+                    "sub-batches on their own streams; reported beside the headline, which stays "
+                    "the single-stream solve the roofline object measures"}
+
+
 def si_dsa_batch_leg(args, P, rte, romsad_solves_per_s, romsad_sweeps):
     """The headline batch solved by batched SI-DSA (same precision, schedule and CG tolerance):
     the ROMSAD batch's gain over it is the correction ROM's alone, apart from batching."""
@@ -627,6 +677,10 @@ def main():
     ap.add_argument("--trace-gap", type=float, default=0.0,
                     help="seconds of GPU idle before and after the timed steps, so that a kernel "
                          "trace of the run can cut out the timed region (outside the clock)")
+    ap.add_argument("--split", type=int, default=2,
+                    help="sub-batches of the headline batch solved at once for the split leg "
+                         "(0 or 1: no split leg)")
+    ap.add_argument("--split-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-warmup", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=0.0,
@@ -746,6 +800,13 @@ def main():
         f"sweep kernel {sweep_ms:.1f} ms over {sweep_n} launches; dsa {dsa_ms:.1f} ms ({dsa_n}); "
         f"rom {rom_ms:.1f} ms ({rom_n}); reduce {red_ms:.1f} ms ({red_n})")
 
+    split = None
+    if args.split > 1 and args.graph_cg_iters <= 0:
+        log(f"[bench] the batch as {args.split} concurrent sub-batches")
+        split = split_leg(args, plane, rte, problems, rom_arrays, P.tuning(), results[-1].n_sweep,
+                          elapsed / args.steps * 1e3)
+        log(f"[bench] split: {json.dumps(split)}")
+
     # plain single-instance GPU SI-DSA (same library, batch of one, same precision)
     base = {}
     if args.baseline_instances > 0:
@@ -809,6 +870,8 @@ def main():
         out["autotune"] = {"pick": {"dg": tune["dg"], "wpb": tune["wpb"]}, "ms": tune["ms"],
                            "cached": tune["cached"], "candidates_ms": tune["candidates"]}
     out.update(base)
+    if split is not None:
+        out["split"] = split
     if args.batch_dsa_steps > 0 and args.mode == "romsad":
         out["si_dsa_batch"] = si_dsa_batch_leg(args, P, rte, solves / elapsed, float(sweeps.mean()))
         log(f"[bench] batched si_dsa: {json.dumps(out['si_dsa_batch'])}")

@@ -279,6 +279,24 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
                    const rte_solve_opts *opts, double *rho_inout, void *f_out,
                    rte_solve_stats *stats, void *ws, size_t ws_bytes, rte_stream_t stream);
 
+/* Several independent batches solved at once (Alg. 1, as rte_sisa_solve): batch i on its own
+ * problem handle, density array rho[i], workspace ws[i] (ws_bytes[i]) and stream streams[i], in
+ * its own host thread (batch 0 in the caller's), all with the caller's current device.  While one
+ * batch's host waits on a poll or its kernels leave the device idle between launches, another's
+ * run, so a batch split into sub-batches finishes sooner than in one piece; every instance's
+ * result is the one a solve of its sub-batch alone gives (and, with the same sweep schedule, the
+ * one of the whole batch).  roms, psi, f_out, stats and status may be NULL (else arrays of n; a
+ * NULL entry of roms, psi or f_out as for rte_sisa_solve).  status[i] receives batch i's return
+ * code.  Returns an argument or device error of any batch first, then RTE_ECG, then
+ * RTE_ENOCONV, else RTE_OK.  RTE_EINVAL for n outside [1, RTE_MULTI_MAX], a NULL required
+ * array or entry, or two batches sharing a handle, a density array or workspace bytes. */
+#define RTE_MULTI_MAX 16
+int rte_sisa_solve_multi(int n, const rte_problem *const *probs, rte_mode mode,
+                         const rte_rom *const *roms, const double *const *psi,
+                         const rte_solve_opts *opts, double *const *rho, void *const *f_out,
+                         rte_solve_stats *stats, void *const *ws, const size_t *ws_bytes,
+                         const rte_stream_t *streams, int *status);
+
 /* ------------------------------------------------------------------------------------------
  * DSA-preconditioned restarted GMRES (the paper's Krylov baseline: Sec. 2.4 and the appendix on
  * restarted GMRES).  For every instance it solves the left-preconditioned system

@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "rte_internal.h"
@@ -235,6 +236,10 @@ struct Profiler {
     }
 };
 Profiler g_prof;
+// the profiler's pool and marks are shared by every host thread (rte_sisa_solve_multi runs
+// solves in several); capture of an iteration graph switches timing off for its own thread only
+std::mutex g_prof_mu;
+thread_local bool t_prof_off = false;
 
 struct ProfScope {
     hipEvent_t a = nullptr;
@@ -242,13 +247,15 @@ struct ProfScope {
     hipStream_t s;
     size_t ia = 0;
     ProfScope(int kid, hipStream_t st) : id(kid), s(st) {
-        if (!g_prof.on) return;
+        if (!g_prof.on || t_prof_off) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
         ia = g_prof.next;
         a = g_prof.get();
         if (a) (void)hipEventRecord(a, s);
     }
     ~ProfScope() {
-        if (!g_prof.on || !a) return;
+        if (!g_prof.on || t_prof_off || !a) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
         const size_t ib = g_prof.next;
         hipEvent_t b = g_prof.get();
         if (!b) return;
@@ -309,6 +316,7 @@ int rte_problem::nparts() const { return nparts_for(this); }
 extern "C" {
 
 int rte_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.on = on != 0;
     g_prof.next = 0;
     for (int k = 0; k < RTE_PROF_NKERNELS; ++k) g_prof.marks[k].clear();
@@ -317,6 +325,7 @@ int rte_profile_enable(int on) {
 
 int rte_profile_read(int kernel, double *total_ms, long long *count) {
     if (kernel < 0 || kernel >= RTE_PROF_NKERNELS || !total_ms || !count) return RTE_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
     double t = 0.0;
     for (const auto &m : g_prof.marks[kernel]) {
         if (hipEventSynchronize(g_prof.pool[m.second]) != hipSuccess) return RTE_EDEVICE;
@@ -769,8 +778,8 @@ int iteration_graph(const rte_problem *p, const Layout &L, rte_mode mode, const 
     HIPCHK(hipHostMalloc((void **)&ex->h_active, 2 * sizeof(int), hipHostMallocDefault));
     for (hipEvent_t &e : ex->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // the library's per-kernel event timing stays out of the graph
-    const bool prof = g_prof.on;
-    g_prof.on = false;
+    const bool prof_off = t_prof_off;
+    t_prof_off = true;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal);
     int rc = RTE_OK;
@@ -781,7 +790,7 @@ int iteration_graph(const rte_problem *p, const Layout &L, rte_mode mode, const 
     } else {
         rc = device_error(e);
     }
-    g_prof.on = prof;
+    t_prof_off = prof_off;
     if (rc == RTE_OK && g) {
         e = hipGraphInstantiate(&ex->exec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) rc = device_error(e);
@@ -1138,6 +1147,52 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
                         &iterations, &cg_failed);
     if (rc) return rc;
     return finish_stats(p, L, o->max_iter, iterations, cg_failed, nullptr, stats, s);
+}
+
+int rte_sisa_solve_multi(int n, const rte_problem *const *probs, rte_mode mode,
+                         const rte_rom *const *roms, const double *const *psi,
+                         const rte_solve_opts *opts, double *const *rho, void *const *f_out,
+                         rte_solve_stats *stats, void *const *ws, const size_t *ws_bytes,
+                         const rte_stream_t *streams, int *status) {
+    if (n < 1 || n > RTE_MULTI_MAX || !probs || !opts || !rho || !ws || !ws_bytes || !streams)
+        return RTE_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!probs[i] || !rho[i] || !ws[i]) return RTE_EINVAL;
+        for (int k = 0; k < i; ++k) {
+            const char *a0 = (const char *)ws[i], *b0 = (const char *)ws[k];
+            const bool overlap = a0 < b0 + ws_bytes[k] && b0 < a0 + ws_bytes[i];
+            if (probs[i] == probs[k] || rho[i] == rho[k] || overlap) return RTE_EINVAL;
+        }
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::vector<int> rc(n, RTE_OK);
+    auto run = [&](int i) {
+        if (hipSetDevice(dev) != hipSuccess) { rc[i] = RTE_EDEVICE; return; }
+        rc[i] = rte_sisa_solve(probs[i], mode, roms ? roms[i] : nullptr, psi ? psi[i] : nullptr,
+                               opts, rho[i], f_out ? f_out[i] : nullptr,
+                               stats ? &stats[i] : nullptr, ws[i], ws_bytes[i], streams[i]);
+    };
+    std::vector<std::thread> th;
+    th.reserve(n - 1);
+    try {
+        for (int i = 1; i < n; ++i) th.emplace_back(run, i);
+    } catch (...) {
+        for (auto &t : th) t.join();
+        return RTE_ENOMEM;
+    }
+    run(0);
+    for (auto &t : th) t.join();
+    if (status)
+        for (int i = 0; i < n; ++i) status[i] = rc[i];
+    // an argument or device error first, then a CG failure, then non-convergence
+    for (int i = 0; i < n; ++i)
+        if (rc[i] != RTE_OK && rc[i] != RTE_ECG && rc[i] != RTE_ENOCONV) return rc[i];
+    for (int i = 0; i < n; ++i)
+        if (rc[i] == RTE_ECG) return RTE_ECG;
+    for (int i = 0; i < n; ++i)
+        if (rc[i] == RTE_ENOCONV) return RTE_ENOCONV;
+    return RTE_OK;
 }
 
 int rte_pgmres_solve(const rte_problem *p, const rte_krylov_opts *o, double *rho,

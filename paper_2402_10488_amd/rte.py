@@ -86,7 +86,8 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_sisa_begin", "rte_sisa_admit", "rte_sisa_iterate", "rte_rom_initial_guess",
             "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve", "rte_f_natural",
             "rte_last_device_error", "rte_sweep_noalloc", "rte_tune_sweep",
-            "rte_pod_weights", "rte_small_gemm", "rte_chol_upper", "rte_svd_jacobi"]
+            "rte_pod_weights", "rte_small_gemm", "rte_chol_upper", "rte_svd_jacobi",
+            "rte_sisa_solve_multi"]
 
 
 def _load():
@@ -134,6 +135,12 @@ def _load():
                                  ctypes.POINTER(SolveStats), _vp, ctypes.c_size_t, _vp]
     L.rte_sisa_begin.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(SolveOpts), _vp, ctypes.c_size_t,
                                  _vp]
+    L.rte_sisa_solve_multi.argtypes = [ctypes.c_int, ctypes.POINTER(P), ctypes.c_int,
+                                       ctypes.POINTER(P), ctypes.POINTER(_vp),
+                                       ctypes.POINTER(SolveOpts), ctypes.POINTER(_vp),
+                                       ctypes.POINTER(_vp), ctypes.POINTER(SolveStats),
+                                       ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int)]
     L.rte_sisa_admit.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp, _vp,
                                  ctypes.c_size_t, _vp]
@@ -421,6 +428,45 @@ def sisa_solve(p: Problem, rho_inout, mode="si_dsa", rom: Optional[Rom] = None, 
     if raise_on_error and rc not in (RTE_OK, RTE_ENOCONV):
         raise RteError(rc, "rte_sisa_solve")
     return SolveResult(rc, n_sweep, st, change, kind, stats.iterations, stats.cg_iterations)
+
+
+def sisa_solve_multi(problems, rhos, streams, mode="si_dsa", roms=None, psis=None, eps=1e-8,
+                     max_iter=500, relative=True, theta=5, eps_romsad=-1.0, cg_rtol=1e-10,
+                     cg_maxit=5000, precision="fp64", poll_every=4, wss=None,
+                     raise_on_error=True):
+    """Independent batches solved together (rte_sisa_solve_multi): batch i on problems[i] with
+    densities rhos[i] and workspace wss[i] on the torch stream streams[i].  Returns one
+    SolveResult per batch."""
+    n = len(problems)
+    roms = roms if roms is not None else [None] * n
+    psis = psis if psis is not None else [None] * n
+    wss = wss if wss is not None else [p.workspace(mode, r, precision, max_iter)
+                                       for p, r in zip(problems, roms)]
+    arrays, stats = [], (SolveStats * n)()
+    for i, p in enumerate(problems):
+        B = p.B
+        a = (np.zeros(B, np.int32), np.zeros(B, np.int32), np.zeros((B, max_iter)),
+             np.zeros((B, max_iter), np.int32))
+        arrays.append(a)
+        stats[i] = SolveStats(a[0].ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                              a[1].ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                              a[2].ctypes.data_as(_D),
+                              a[3].ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 0, 0)
+    o = SolveOpts(float(eps), int(max_iter), int(relative), int(theta), float(eps_romsad),
+                  float(cg_rtol), int(cg_maxit), PRECISIONS[precision], int(poll_every), 0)
+    Parr = ctypes.c_void_p * n
+    status = (ctypes.c_int * n)()
+    rc = lib.rte_sisa_solve_multi(
+        n, Parr(*[p.handle for p in problems]), MODES[mode],
+        Parr(*[r.handle if r is not None else None for r in roms]),
+        Parr(*[_ptr(x) for x in psis]), ctypes.byref(o), Parr(*[_ptr(x) for x in rhos]),
+        None, stats, Parr(*[_ptr(w) for w in wss]),
+        (ctypes.c_size_t * n)(*[w.numel() for w in wss]),
+        Parr(*[ctypes.c_void_p(s.cuda_stream) for s in streams]), status)
+    if raise_on_error and rc not in (RTE_OK, RTE_ENOCONV):
+        raise RteError(rc, "rte_sisa_solve_multi")
+    return [SolveResult(status[i], a[0], a[1], a[2], a[3], stats[i].iterations,
+                        stats[i].cg_iterations) for i, a in enumerate(arrays)]
 
 
 class Session:

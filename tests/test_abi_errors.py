@@ -108,3 +108,29 @@ def test_last_device_error_is_empty_when_no_hip_call_failed():
     assert rc == rte.RTE_EINVAL
     assert lib.rte_last_device_error() == b""
     assert "HIP" not in str(rte.RteError(rte.RTE_EINVAL, "x"))
+
+
+def test_multi_batch_solve_checks_its_arguments():
+    """rte_sisa_solve_multi rejects a bad count, missing arrays or entries, and batches that share
+    a handle, a density array or workspace bytes, before any device work."""
+    o = rte.SolveOpts(1e-6, 10, 1, 5, -1.0, 1e-3, 100, 0, 4, 0)
+    P2 = _vp * 2
+    sizes = (ctypes.c_size_t * 2)(1 << 20, 1 << 20)
+    streams = P2(None, None)
+    a, b = _vp(0x1000), _vp(0x2000)
+    ws_apart = P2(_vp(0x100000), _vp(0x300000))
+
+    def call(n, probs, rho, ws, sz=sizes):
+        return lib.rte_sisa_solve_multi(n, probs, 1, None, None, ctypes.byref(o), rho, None, None,
+                                        ws, sz, streams, None)
+
+    assert call(0, P2(a, b), P2(a, b), ws_apart) == rte.RTE_EINVAL
+    assert call(17, P2(a, b), P2(a, b), ws_apart) == rte.RTE_EINVAL
+    assert call(2, None, P2(a, b), ws_apart) == rte.RTE_EINVAL
+    assert call(2, P2(a, None), P2(a, b), ws_apart) == rte.RTE_EINVAL
+    assert call(2, P2(a, a), P2(a, b), ws_apart) == rte.RTE_EINVAL            # shared handle
+    assert call(2, P2(a, b), P2(a, a), ws_apart) == rte.RTE_EINVAL            # shared densities
+    overlap = P2(_vp(0x100000), _vp(0x180000))                                 # 1 MiB apart by half
+    assert call(2, P2(a, b), P2(a, b), overlap) == rte.RTE_EINVAL
+    assert lib.rte_sisa_solve_multi(2, P2(a, b), 1, None, None, None, P2(a, b), None, None,
+                                    ws_apart, sizes, streams, None) == rte.RTE_EINVAL
