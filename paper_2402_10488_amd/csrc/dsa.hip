@@ -861,7 +861,7 @@ __global__ void cg_finish_kernel(long long ndof, const double *x, double *delta,
     const int b = blk.y;
     const int st = state[b];
     if (st == 0) return;
-    if (t < ndof) delta[(size_t)b * ndof + t] = x[(size_t)b * ndof + t];
+    if (x && t < ndof) delta[(size_t)b * ndof + t] = x[(size_t)b * ndof + t];
     if (t == 0 && iters_out) iters_out[b] = iters[b];
     if (t == 0 && total) atomicAdd(total, (unsigned long long)iters[b]);
     if (t == 0 && fails && st == 3) atomicAdd(fails, 1);
@@ -2022,8 +2022,11 @@ void mg_precond_capture(const rte_problem *p, CGSpace &c) {
 
 hipError_t launch_cg_finish(const rte_problem *p, const CGSpace &c, double *delta, int *iters_out,
                             unsigned long long *total, hipStream_t s) {
-    dim3 grid(blocks_for(p->ndof, 256), p->B);
-    hipLaunchKernelGGL(cg_finish_kernel, grid, dim3(256), 0, s, p->ndof, c.x, delta, c.state,
+    // a CG that iterated in the output itself leaves only the statistics to gather
+    const bool copy = c.x != delta;
+    dim3 grid(copy ? blocks_for(p->ndof, 256) : 1u, p->B);
+    hipLaunchKernelGGL(cg_finish_kernel, grid, dim3(256), 0, s, p->ndof, copy ? c.x : nullptr,
+                       delta, c.state,
                        c.iters, iters_out, total, c.fails, p->B);
     return hipGetLastError();
 }

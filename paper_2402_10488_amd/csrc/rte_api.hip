@@ -668,8 +668,12 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
         HIPCHK(launch_dsa1d(p, rho_star, rho_prev, delta, kind, want, L.dsa1d, s));
         return RTE_OK;
     }
+    // the CG iterates in the output itself (the call's last kernel then only gathers its
+    // statistics), unless the output is one of the inputs
+    CGSpace cg = L.cg;
+    if (delta != rho_star && delta != rho_prev) cg.x = delta;
     // the multigrid hierarchy depends only on the materials: built by the caller once
-    HIPCHK(launch_cg_setup(p, L.cg, rho_star, rho_prev, kind, want, guess, rtol, s));
+    HIPCHK(launch_cg_setup(p, cg, rho_star, rho_prev, kind, want, guess, rtol, s));
     // A look at the number of running instances drains the queue, and an iteration launched
     // after every instance stopped still costs its launches (its kernels return at once).  So
     // the host first looks after the iteration at which the previous solve of this call was seen
@@ -679,7 +683,7 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
     const int first = L.cg_look > 0 ? L.cg_look : 8;
     int counts[2] = {1, 0};       // running, failed
     for (int it = 1; it <= maxit + 1; ++it) {
-        HIPCHK(launch_cg_iteration(p, L.cg, it, rtol, maxit, s));
+        HIPCHK(launch_cg_iteration(p, cg, it, rtol, maxit, s));
         if (it >= first || it == maxit + 1) {
             HIPCHK(hipMemcpyAsync(counts, L.cg.n_running, sizeof(counts), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -691,7 +695,7 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
     }
     // iteration maxit + 1 stops every instance still running and counts it as failed
     if (failed) *failed = counts[0] != 0 || counts[1] != 0;
-    HIPCHK(launch_cg_finish(p, L.cg, delta, iters_out, L.cg_total, s));
+    HIPCHK(launch_cg_finish(p, cg, delta, iters_out, L.cg_total, s));
     return RTE_OK;
 }
 
@@ -741,10 +745,12 @@ int enqueue_iteration(const rte_problem *p, const Layout &L, rte_mode mode, cons
         if (p->dim == 1) {
             HIPCHK(launch_dsa1d(p, L.rho_star, rho, L.delta, L.st.kind, 1, L.dsa1d, s));
         } else {
-            HIPCHK(launch_cg_setup(p, L.cg, L.rho_star, rho, L.st.kind, 1, L.delta, o->cg_rtol, s));
+            CGSpace cg = L.cg;
+            cg.x = L.delta;                       // the CG iterates in the correction itself
+            HIPCHK(launch_cg_setup(p, cg, L.rho_star, rho, L.st.kind, 1, L.delta, o->cg_rtol, s));
             for (int it = 1; it <= depth + 1; ++it)
-                HIPCHK(launch_cg_iteration(p, L.cg, it, o->cg_rtol, depth, s));
-            HIPCHK(launch_cg_finish(p, L.cg, L.delta, L.cg.iters, L.cg_total, s));
+                HIPCHK(launch_cg_iteration(p, cg, it, o->cg_rtol, depth, s));
+            HIPCHK(launch_cg_finish(p, cg, L.delta, L.cg.iters, L.cg_total, s));
         }
     }
     HIPCHK(launch_update(p, L.st, L.rho_star, corrected ? L.delta : nullptr, rho, L.src, fp32, s));
