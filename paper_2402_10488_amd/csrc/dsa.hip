@@ -999,13 +999,26 @@ template <typename TS>
 __device__ __forceinline__ TS *st_of(TS *S, int b, long long nv) {
     return S + (size_t)b * kStencilPlanes * nv;
 }
+// The FP32 copy of a Galerkin operator is read as the symmetric operator it is in exact
+// arithmetic: the coupling of v to its neighbour v + d for the four offsets d before it in
+// plane order (k < 4) is taken from that neighbour's plane 8 - k (its coupling back to v).  A
+// V-cycle thus reads planes 4..9 only, and its operator is exactly symmetric.
+template <typename TS>
+__device__ __forceinline__ TS stencil_coef(const TS *Sb, int k, long long nv, long long v,
+                                           long long w) {
+    if constexpr (std::is_same<TS, float>::value)
+        return k < 4 ? Sb[(8 - k) * nv + w] : Sb[k * nv + v];
+    else
+        return Sb[k * nv + v];
+}
+
 template <typename TS>
 __device__ __forceinline__ double stencil_apply(const TS *Sb, const double *x, VG g, int vx,
                                                 int vy) {
     // the nine (coefficient, value) pairs are loaded before the sum: a neighbour outside the
     // grid reads the vertex itself and a select leaves it out, so no load waits behind a branch;
     // the sum keeps its order and its terms
-    const TS *st = Sb + (long long)vy * g.nvx + vx;
+    const long long v = (long long)vy * g.nvx + vx;
     double cv[9], xv[9];
     bool ok[9];
 #pragma unroll
@@ -1015,8 +1028,9 @@ __device__ __forceinline__ double stencil_apply(const TS *Sb, const double *x, V
             const int k = (dy + 1) * 3 + dx + 1;
             const int yy = vy + dy, xx = vx + dx;
             ok[k] = yy >= 0 && yy < g.nvy && xx >= 0 && xx < g.nvx;
-            cv[k] = (double)st[k * g.nv];
-            xv[k] = x[ok[k] ? (long long)yy * g.nvx + xx : (long long)vy * g.nvx + vx];
+            const long long w = ok[k] ? (long long)yy * g.nvx + xx : v;
+            cv[k] = (double)stencil_coef(Sb, k, g.nv, v, w);
+            xv[k] = x[w];
         }
     double s = 0.0;
 #pragma unroll
@@ -1415,7 +1429,6 @@ __global__ void mg_vpre_kernel(const int *state, VG g, const float *S, const dou
     const float *wd = Sb + 9 * g.nv;
     const double *bb = bv + o;
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-    const float *st = Sb + v;
     double sx1 = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int yy = vy + dy;
@@ -1424,7 +1437,7 @@ __global__ void mg_vpre_kernel(const int *state, VG g, const float *S, const dou
             const int xx = vx + dx;
             if (xx < 0 || xx >= g.nvx) continue;
             const long long w = (long long)yy * g.nvx + xx;
-            sx1 += st[((dy + 1) * 3 + dx + 1) * g.nv] * (wd[w] * bb[w]);
+            sx1 += stencil_coef(Sb, (dy + 1) * 3 + dx + 1, g.nv, v, w) * (wd[w] * bb[w]);
         }
     }
     const double x1 = wd[v] * bb[v];
@@ -1450,7 +1463,6 @@ __global__ void mg_vpost1_kernel(const int *state, VG g, const float *S, const d
     const float *Sb = st_of(S, b, g.nv);
     const double *cb = xc + (size_t)b * gc.nv;
     const int vx = (int)(v % g.nvx), vy = (int)(v / g.nvx);
-    const float *st = Sb + v;
     // Every load is issued before the arithmetic.  The coarse values that the prolongation at
     // the nine neighbours reads all lie in the 3 x 3 coarse patch from (PX, PY) = ((vx - 1) >> 1,
     // (vy - 1) >> 1): for a fine offset d the two coarse columns (X0, X1) are patch columns
@@ -1477,8 +1489,9 @@ __global__ void mg_vpost1_kernel(const int *state, VG g, const float *S, const d
             const int k = (dy + 1) * 3 + dx + 1;
             const int yy = vy + dy, xx = vx + dx;
             ok[k] = yy >= 0 && yy < g.nvy && xx >= 0 && xx < g.nvx;
-            cv[k] = st[k * g.nv];
-            xn[k] = x2[o + (ok[k] ? (long long)yy * g.nvx + xx : v)];
+            const long long w = ok[k] ? (long long)yy * g.nvx + xx : v;
+            cv[k] = stencil_coef(Sb, k, g.nv, v, w);
+            xn[k] = x2[o + w];
         }
     auto pick = [&](int re, int ro, int ce, int co) -> double {
         const double e = ex ? cp[re][ce] : cp[re][co];
@@ -1561,7 +1574,10 @@ __global__ void __launch_bounds__(1024) mg_small_vcycle_kernel(const int *state,
         for (int l = 0; l < kMaxLevels; ++l) {
             if (l < sl.n) {
                 const long long nv = sl.nv[l];
-                copy_to_lds<float, 12>(st_of(sl.S[l], b, nv), shf + os, kStencilPlanes * nv, t, nt);
+                // planes 0..3 are never read (stencil_coef takes them from the neighbours'
+                // planes 8..5), so only planes 4..9 are copied
+                copy_to_lds<float, 12>(st_of(sl.S[l], b, nv) + 4 * nv, shf + os + 4 * nv,
+                                       (kStencilPlanes - 4) * nv, t, nt);
                 if (t == 0) {
                     d.nvx[l] = sl.nvx[l];
                     d.nvy[l] = sl.nvy[l];
