@@ -721,9 +721,12 @@ __device__ void tile_fill(const MipArgs &a, int ntx, int tile, const TileCell &t
         val(tc.cell, own);
         sp[tc.me] = make_double4(own[0], own[1], own[2], own[3]);
     }
-    if (threadIdx.x < 4 * kTile) {            // the halo: left, right, bottom, top edges
+    // the halo: left, right, bottom and top edges, one per wavefront (16 lanes each), so that no
+    // wavefront carries all the extra loads
+    static_assert(kCgBlock == 4 * 64, "four wavefronts, one halo side each");
+    if ((threadIdx.x & 63) < kTile) {
         const int tx = tile % ntx, ty = tile / ntx;
-        const int side = threadIdx.x / kTile, t = threadIdx.x % kTile;
+        const int side = threadIdx.x >> 6, t = threadIdx.x & 63;
         const int hi = side == 0 ? tx * kTile - 1 : side == 1 ? tx * kTile + kTile : tx * kTile + t;
         const int hj = side == 2 ? ty * kTile - 1 : side == 3 ? ty * kTile + kTile : ty * kTile + t;
         const int at = side == 0 ? (t + 1) * kTileW
