@@ -494,7 +494,8 @@ def split_leg(args, plane, rte, problems, rom_arrays, tuning, ref_n_sweep, headl
     subs = []
     for k in range(K):
         sub = plane.subset(range(bounds[k], bounds[k + 1]))
-        Pk = problems.plane_problem(sub, dg=tuning["dg"], wpb=tuning["wpb"])
+        Pk = problems.plane_problem(sub, dg=tuning["dg"], wpb=tuning["wpb"],
+                                   bands=tuning["bands"])
         Rk = (rte.Rom(Pk, rom_arrays.U_rho, rom_arrays.U_iso, rom_arrays.A0, rom_arrays.A,
                       rom_arrays.eps_pod, rom_arrays.eps_train) if rom_arrays is not None else None)
         psik = problems.plane_psi(sub) if rom_arrays is not None else None
@@ -728,10 +729,10 @@ def main():
         P0 = problems.plane_problem(plane)
         r0 = torch.rand((P0.B, P0.ndof), dtype=torch.float64, device="cuda")
         tune = autotune.tune(P0, r0, args.precision)
-        log(f"[bench] sweep schedule: dg={tune['dg']} wpb={tune['wpb']} "
+        log(f"[bench] sweep schedule: dg={tune['dg']} wpb={tune['wpb']} bands={tune['bands']} "
             f"({'cached' if tune['cached'] else 'measured'}: {tune['candidates']})")
         del r0, P0
-        P = problems.plane_problem(plane, dg=tune["dg"], wpb=tune["wpb"])
+        P = problems.plane_problem(plane, dg=tune["dg"], wpb=tune["wpb"], bands=tune["bands"])
     psi = problems.plane_psi(plane)
     Rm, rom_arrays = None, None
     if args.mode == "romsad":
@@ -867,7 +868,8 @@ def main():
                                   else "event-timed groups of one extra kernel-by-kernel step"},
     }
     if tune is not None:
-        out["autotune"] = {"pick": {"dg": tune["dg"], "wpb": tune["wpb"]}, "ms": tune["ms"],
+        out["autotune"] = {"pick": {"dg": tune["dg"], "wpb": tune["wpb"], "bands": tune["bands"]},
+                           "ms": tune["ms"],
                            "cached": tune["cached"], "candidates_ms": tune["candidates"]}
     out.update(base)
     if split is not None:

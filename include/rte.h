@@ -112,18 +112,33 @@ void rte_problem_destroy(rte_problem *p);
  * partial-density order. */
 int rte_problem_create_tuned(const rte_problem_desc *desc, int dg, int wpb, rte_problem **out);
 
+/* rte_problem_create_tuned with the number of mesh bands (64 rows each) a 2D sweep workgroup
+ * keeps in flight: 1 sweeps the bands one after another; b > 1 runs b consecutive bands at once,
+ * each 64 pipeline steps behind the one above, which cuts the dependent steps of an instance
+ * from about nbands * nx to about nx + 64 nbands (a single large instance, or the last
+ * iterations of a batch, run that many times more wavefronts).  The cells, solves and sums are
+ * the same, so results are bitwise independent of bands.  0 = automatic: 1 when the batch has
+ * at least 4096 wavefronts of work (16 per CU), 2 below that, and 4 below 1024 (where an
+ * automatic wpb also drops to 2).  The launch uses fewer when the mesh has fewer bands, or
+ * 64 wpb bands threads or the workgroup's LDS (partial sums and y-trace rings, 64 KiB) would not
+ * fit.  bands in [0, 16].  rte_problem_create and rte_problem_create_tuned choose bands
+ * automatically. */
+int rte_problem_create_sched(const rte_problem_desc *desc, int dg, int wpb, int bands,
+                             rte_problem **out);
+
 /* Autotuner measurement: times the 2D sweep (source prologue, sweep, partial-density reduction:
  * one iteration's sweep of rte_sisa_solve; with f_out != NULL the angular flux is written too, as
- * rte_sweep does) of the batch described by desc under each candidate schedule (dg[i], wpb[i]) of
- * rte_problem_create_tuned.  ms_out[i] receives the average milliseconds per sweep over `reps`
+ * rte_sweep does) of the batch described by desc under each candidate schedule (dg[i], wpb[i],
+ * bands[i]) of rte_problem_create_sched (bands NULL: 1 band in flight).  ms_out[i] receives the average milliseconds per sweep over `reps`
  * timed sweeps after `warmup` untimed ones (HIP events on the stream), or -1 for a candidate the
- * library does not run as given (unknown values, or one the LDS budget would change).
+ * library does not run as given (unknown values, or one the LDS budget or the mesh would
+ * change: for bands, the number a solve in precision prec would run).
  *   rho_in   device [B][N_DOF] density swept;  f_out  device angular flux (layout above) or NULL
  * A setup call, not a hot one: it creates a handle and allocates and frees a workspace per
  * candidate, and synchronizes the stream.  2D only (RTE_EUNSUPPORTED otherwise). */
 int rte_tune_sweep(const rte_problem_desc *desc, rte_precision prec, int n_cand, const int *dg,
-                   const int *wpb, const double *rho_in, void *f_out, int warmup, int reps,
-                   double *ms_out, rte_stream_t stream);
+                   const int *wpb, const int *bands, const double *rho_in, void *f_out,
+                   int warmup, int reps, double *ms_out, rte_stream_t stream);
 
 /* Selects the preconditioner of the 2D diffusion CG: on != 0 (default) the two-level
  * multigrid (block-Jacobi smoothing on the DG space, continuous-Q1 vertex-grid coarse space with
@@ -134,6 +149,9 @@ int rte_problem_dsa_multigrid(rte_problem *p, int on);
 /* Reports the schedule in use: directions per lane, wavefronts per workgroup and the number of
  * per-instance partial densities the 2D sweep produces. */
 int rte_problem_tuning(const rte_problem *p, int *dg, int *wpb, int *nparts);
+
+/* The bands in flight the handle's 2D sweeps ask for (rte_problem_create_sched). */
+int rte_problem_bands(const rte_problem *p, int *bands);
 
 /* Checks sigma_t >= sigma_s >= 0 and finiteness of the device materials; synchronizes the
  * stream.  Returns RTE_EINVAL on violation. */

@@ -1,9 +1,10 @@
 """Measured choice of the 2D sweep schedule, cached per (device, mesh, directions, batch, precision).
 
-The sweep kernel gives every wavefront one (instance, quadrant, group of dg directions) and puts
-wpb wavefronts in a workgroup.  Which schedule is fastest depends on the batch size, the direction
-count and the precision (registers per lane grow with dg; the number of wavefronts in flight falls
-with it).  The tuner times every schedule the library runs on the workload itself
+The sweep kernel gives every wavefront one (instance, quadrant, group of dg directions), puts wpb
+wavefronts of a band in a workgroup and runs `bands` mesh bands of it at once.  Which schedule is
+fastest depends on the batch size, the direction count and the precision (registers per lane grow
+with dg; the number of wavefronts in flight falls with it; more bands in flight shorten the
+pipeline of a single large instance).  The tuner times every schedule the library runs on the workload itself
 (rte_tune_sweep: HIP events around the sweeps, on the device) and keeps the fastest.  The choice
 is stored in a JSON file, so a workload is timed once per device; later problems of the same shape
 read it back.
@@ -12,9 +13,9 @@ import json
 import os
 import tempfile
 
-CANDIDATES = tuple((dg, w) for dg in (1, 2, 4, 8) for w in (1, 2, 4))
+CANDIDATES = tuple((dg, w, nb) for dg in (1, 2, 4, 8) for w in (1, 2, 4) for nb in (1, 2, 4))
 CACHE_ENV = "RTE_TUNE_CACHE"
-VERSION = 1
+VERSION = 2
 
 
 def default_cache_path():
@@ -59,7 +60,7 @@ def store(path, table):
 
 
 def select(times):
-    """The fastest schedule among {(dg, wpb): ms} with ms > 0 (ties: the smaller (dg, wpb));
+    """The fastest schedule among {(dg, wpb, bands): ms} with ms > 0 (ties: the smaller tuple);
     None if no candidate ran."""
     valid = {k: v for k, v in times.items() if v is not None and v > 0}
     if not valid:
@@ -79,7 +80,8 @@ def tune(problem, rho_in, precision="mixed", f_out=None, path=None, refresh=Fals
     """The schedule for ``problem``'s workload: read from the cache, or timed and stored.
 
     timer(candidates) -> milliseconds per sweep for each candidate (default: rte_tune_sweep on
-    rho_in).  Returns {"dg", "wpb", "ms", "candidates": {"dg,wpb": ms}, "cached", "key"}."""
+    rho_in).  Returns {"dg", "wpb", "bands", "ms", "candidates": {"dg,wpb,bands": ms}, "cached",
+    "key"}."""
     path = path or default_cache_path()
     device = device or device_name()
     key = workload_key(device, problem.nx, problem.ny, problem.n_dir, problem.B, precision,
@@ -95,8 +97,8 @@ def tune(problem, rho_in, precision="mixed", f_out=None, path=None, refresh=Fals
     pick = select(times)
     if pick is None:
         raise RuntimeError(f"no sweep schedule ran for {key}")
-    entry = {"dg": int(pick[0]), "wpb": int(pick[1]), "ms": times[pick],
-             "candidates": {f"{d},{w}": t for (d, w), t in times.items()}}
+    entry = {"dg": int(pick[0]), "wpb": int(pick[1]), "bands": int(pick[2]), "ms": times[pick],
+             "candidates": {",".join(map(str, c)): t for c, t in times.items()}}
     table = load(path)               # another process may have added entries meanwhile
     table[key] = entry
     try:

@@ -189,9 +189,14 @@ int device_error(hipError_t e) {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-void choose_tuning(rte_problem *p, int dg_req, int wpb_req) {
+void choose_tuning(rte_problem *p, int dg_req, int wpb_req, int bands_req) {
     int nqmax = 0;
     for (int q = 0; q < 4; ++q) nqmax = std::max(nqmax, p->quad.count[q]);
+    auto wavefronts = [&](int d) {
+        long long items = 0;
+        for (int q = 0; q < 4; ++q) items += (long long)p->B * ((p->quad.count[q] + d - 1) / d);
+        return items;
+    };
     int dg = 1;
     if (dg_req > 0) {
         dg = dg_req;
@@ -202,9 +207,7 @@ void choose_tuning(rte_problem *p, int dg_req, int wpb_req) {
         for (int i = 0; i < 4; ++i) {
             const int d = cand[i];
             if (d > nqmax) continue;
-            long long items = 0;
-            for (int q = 0; q < 4; ++q) items += (long long)p->B * ((p->quad.count[q] + d - 1) / d);
-            if (items >= 4096 || d == 1) { dg = d; break; }   // items = wavefronts
+            if (wavefronts(d) >= 4096 || d == 1) { dg = d; break; }
         }
     }
     // wavefronts per workgroup: as many direction groups of a quadrant as fit (<= 4)
@@ -215,8 +218,24 @@ void choose_tuning(rte_problem *p, int dg_req, int wpb_req) {
     auto lds = [&](int w, int d) { return (size_t)2 * w * 64 * 4 * 8 + (size_t)w * p->nx * d * 2 * 8; };
     while (wpb > 1 && lds(wpb, dg) > 64 * 1024) wpb /= 2;
     while (dg > 1 && lds(wpb, dg) > 64 * 1024) dg /= 2;
+    // mesh bands in flight per workgroup: a batch too small to fill the chip (fewer than 16
+    // wavefronts per CU) runs two bands at once, one with fewer than 4 per CU runs four bands
+    // of two-wavefront workgroups; the launch lowers the count to what the mesh and LDS allow
+    int bands = 1;
+    if (bands_req > 0) {
+        bands = bands_req;
+    } else if (p->dim == 2) {
+        const long long wf = wavefronts(dg);
+        if (wf < 1024) {
+            bands = 4;
+            if (wpb_req <= 0 && wpb > 2) wpb = 2;
+        } else if (wf < 4096) {
+            bands = 2;
+        }
+    }
     p->tune.dg = dg;
     p->tune.wpb = wpb;
+    p->tune.bands = bands;
 }
 
 // Per-kernel timing with HIP events recorded on the launch stream (enabled by
@@ -358,11 +377,17 @@ const char *rte_last_device_error(void) {
 }
 
 int rte_problem_create(const rte_problem_desc *d, rte_problem **out) {
-    return rte_problem_create_tuned(d, 0, 0, out);
+    return rte_problem_create_sched(d, 0, 0, 0, out);
 }
 
 int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_problem **out) {
+    return rte_problem_create_sched(d, dg, wpb, 0, out);
+}
+
+int rte_problem_create_sched(const rte_problem_desc *d, int dg, int wpb, int bands,
+                             rte_problem **out) {
     if (!d || !out) return RTE_EINVAL;
+    if (bands < 0 || bands > 16) return RTE_EINVAL;
     *out = nullptr;
     if (d->dim != 1 && d->dim != 2) return RTE_EINVAL;
     if (d->nx < 1 || d->ny < 1 || d->batch < 1 || d->n_dir < 1) return RTE_EINVAL;
@@ -470,7 +495,7 @@ int rte_problem_create_tuned(const rte_problem_desc *d, int dg, int wpb, rte_pro
         }
     }
     p->n_sorted = (int)table.size();
-    choose_tuning(p, dg, wpb);
+    choose_tuning(p, dg, wpb, bands);
     hipError_t e = hipSuccess;
     auto upload = [&](auto **dst, const void *src, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc((void **)dst, bytes);
@@ -517,6 +542,12 @@ int rte_problem_tuning(const rte_problem *p, int *dg, int *wpb, int *nparts) {
     if (dg) *dg = p->tune.dg;
     if (wpb) *wpb = p->tune.wpb;
     if (nparts) *nparts = p->dim == 2 ? nparts_for(p) : 0;
+    return RTE_OK;
+}
+
+int rte_problem_bands(const rte_problem *p, int *bands) {
+    if (!p || !bands) return RTE_EINVAL;
+    *bands = sweep_bands(p);
     return RTE_OK;
 }
 
@@ -1023,8 +1054,8 @@ int rte_sweep_noalloc(const rte_problem *p, const double *rho_in, void *f_out, d
 }
 
 int rte_tune_sweep(const rte_problem_desc *desc, rte_precision prec, int n_cand, const int *dg,
-                   const int *wpb, const double *rho_in, void *f_out, int warmup, int reps,
-                   double *ms_out, rte_stream_t stream) {
+                   const int *wpb, const int *bands, const double *rho_in, void *f_out,
+                   int warmup, int reps, double *ms_out, rte_stream_t stream) {
     if (!desc || !dg || !wpb || !rho_in || !ms_out || n_cand < 1 || warmup < 0 || reps < 1)
         return RTE_EINVAL;
     if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
@@ -1035,13 +1066,17 @@ int rte_tune_sweep(const rte_problem_desc *desc, rte_precision prec, int n_cand,
     for (hipEvent_t &e : ev) HIPCHK(hipEventCreate(&e));
     int rc = RTE_OK;
     for (int i = 0; i < n_cand && rc == RTE_OK; ++i) {
-        if (dg[i] < 1 || wpb[i] < 1) continue;
+        if (dg[i] < 1 || wpb[i] < 1 || (bands && bands[i] < 1)) continue;
         rte_problem *p = nullptr;
-        const int cr = rte_problem_create_tuned(desc, dg[i], wpb[i], &p);
+        const int cr = rte_problem_create_sched(desc, dg[i], wpb[i], bands ? bands[i] : 1, &p);
         if (cr == RTE_EINVAL) continue;                       // not a schedule the sweep has
         if (cr != RTE_OK) { rc = cr; break; }
         // a schedule the LDS budget would change is not this candidate
-        if (p->tune.dg != dg[i] || p->tune.wpb != wpb[i]) { rte_problem_destroy(p); continue; }
+        if (p->tune.dg != dg[i] || p->tune.wpb != wpb[i] ||
+            (bands && sweep_bands_used(p, prec) != bands[i])) {
+            rte_problem_destroy(p);
+            continue;
+        }
         size_t bytes = 0;
         rte_workspace_size(p, RTE_SI, nullptr, prec, 1, &bytes);
         void *ws = nullptr;

@@ -31,8 +31,11 @@ struct QuadLayout {
 
 struct Tuning {
     int dg;         // directions per lane in the 2D sweep (1, 2, 4, 8, 16)
-    int wpb;        // waves per workgroup in the 2D sweep
+    int wpb;        // waves per band in a 2D sweep workgroup (direction groups summed in LDS)
+    int bands;      // bands of the mesh in flight per 2D sweep workgroup (1: one after another)
 };
+// LDS a 2D sweep workgroup may use (partial-sum buffers and y-trace rings)
+constexpr size_t kSweepLdsBytes = 64 * 1024;
 
 struct Workspace;   // carve-up of the caller's workspace, see rte_api.hip
 
@@ -228,10 +231,17 @@ struct SweepLaunch {
     const int *active;        // [B] or nullptr
     int zero_inflow;
     int fp32;
+    int bands = 0;            // bands in flight (0: the handle's schedule); results do not depend on it
 };
 hipError_t launch_sweep2d(const SweepLaunch &a, hipStream_t s);
 // wavefronts per sweep workgroup (direction groups summed in LDS) and partial slots per instance
 int sweep_waves(const rte_problem *p);
+int sweep_bands(const rte_problem *p);
+// bands a 2D sweep launch runs in flight for a request (clamped to the mesh's bands, 1024 threads
+// and the LDS budget for partial sums (if any) and rings of elem-byte values); the number a solve
+// of precision prec uses
+int bands_in_flight(const rte_problem *p, int requested, bool partial, size_t elem);
+int sweep_bands_used(const rte_problem *p, rte_precision prec);
 int sweep_nparts(const rte_problem *p);
 
 // 1D sweep: writes f (always, T) to f_out [B][ncell][n_dir][2]; src as in 2D (K = 2).

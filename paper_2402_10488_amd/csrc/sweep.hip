@@ -26,6 +26,10 @@ constexpr double kS3 = 1.7320508075688772935;
 
 struct Sweep2DArgs {
     int nx, ny, B, nbands, P, n_dir, nparts;
+    int wpb;         // wavefronts per band: direction groups summed in LDS
+    int nbc;         // bands in flight per workgroup (each with its own wpb wavefronts)
+    int P2;          // steps between a wavefront's consecutive bands: max(P, 64 nbc)
+    int total;       // steps of the workgroup's pipeline
     int gq[4];       // workgroups (blocks of W direction groups) per quadrant
     int qstart[4];   // first entry of each quadrant in the sorted direction table
     int qpad[4];     // padded table length of each quadrant
@@ -174,16 +178,21 @@ __device__ __forceinline__ void store_f4(__amdgpu_buffer_rsrc_t r, int off, cons
     __builtin_amdgcn_raw_buffer_store_b128(y, r, off + 16, 0, kStoreAux);
 }
 
-// One workgroup = W wavefronts = W consecutive direction groups of one (instance, quadrant).
-// The wavefronts walk the same pipeline in lockstep (one barrier per step), so at every step
-// lane j of every wavefront is at the same cell; their FP64 partial densities are summed in
-// LDS in a fixed order and one partial per (instance, quadrant block) is written.
-template <typename T, int DG, bool WF>
-__global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
+// One workgroup = W wavefronts per band = W consecutive direction groups of one (instance,
+// quadrant), for nbc bands in flight.  The W wavefronts of a band walk the same pipeline in
+// lockstep (one barrier per step), so at every step lane j of each is at the same cell; their
+// FP64 partial densities are summed in LDS in a fixed order and one partial per (instance,
+// quadrant block) is written.  With nbc > 1 the bands k, k+1, ... of the mesh run at once, band
+// slot k mod nbc 64 steps behind the slot above it, which hands its last row's y-traces on
+// through an LDS ring: the same cells, solves and sums in the same order as with one band in
+// flight, over fewer dependent steps (a band no longer waits for the whole band above).
+template <typename T, int DG, bool WF, int NB>
+__global__ void __launch_bounds__(256 * NB) sweep2d_kernel(Sweep2DArgs a) {
     extern __shared__ double smem_d[];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int W = blockDim.x >> 6;
+    const int W = (blockDim.x >> 6) / NB;                     // wavefronts per band
+    const int wv = NB == 1 ? (int)(threadIdx.x >> 6) : (int)(threadIdx.x >> 6) % W;  // direction group
+    const int kb = NB == 1 ? 0 : (int)(threadIdx.x >> 6) / W;                        // band slot
     const int item = blockIdx.x;                              // (instance, quadrant block)
     if (item >= a.B * a.nparts) return;                       // whole workgroup leaves
     const int b = item / a.nparts;
@@ -195,10 +204,15 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
     const int d0 = a.qstart[q] + g * DG;
     const int dend = a.qstart[q] + a.qpad[q];                 // end of this quadrant's table
     const bool rx = (q & 1) != 0, ry = (q & 2) != 0;
-    // LDS: [2][W][64][4] doubles of partial densities (double buffered by step parity), then
-    // the W rings of y-traces handed from lane 63 to lane 0 of the next band
-    double *red = smem_d;
-    T *ring = reinterpret_cast<T *>(smem_d + a.ring_off) + (size_t)wv * a.nx * DG * 2;
+    // LDS: per band slot [2][W][64][4] doubles of partial densities (double buffered by step
+    // parity), then per (band slot, direction group) a ring of y-traces, written by lane 63 and
+    // read by lane 0 of the same direction group in the next band's slot
+    double *red = smem_d + (size_t)kb * 2 * W * 64 * 4;
+    const size_t ring_len = (size_t)a.nx * DG * 2;
+    T *ring = reinterpret_cast<T *>(smem_d + a.ring_off) + ((size_t)kb * W + wv) * ring_len;
+    const T *ring_in = NB == 1 ? ring
+                               : reinterpret_cast<const T *>(smem_d + a.ring_off) +
+                                     ((size_t)((kb + NB - 1) % NB) * W + wv) * ring_len;
 
     DirConst<T> dc[DG];
     T wt[DG];
@@ -249,7 +263,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
 
     // lane position in the pipeline: band k, column i (k P + i = t - lane), tracked
     // incrementally so the loop carries no division
-    const int P = a.P, nx = a.nx, ny = a.ny, nb = a.nbands;
+    const int P2 = NB == 1 ? a.P : a.P2, nx = a.nx, ny = a.ny, nb = a.nbands;
     // position of the lane's cell in this quadrant's diagonal layout (inputs, partials)
     auto locate = [&](int kk, int ii, bool &ok) -> int {
         const int jr = kk * 64 + lane;
@@ -292,8 +306,8 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
             } else {
 #pragma unroll
                 for (int d = 0; d < DG; ++d) {
-                    r0v[d] = ring[(i0 * DG + d) * 2];
-                    r1v[d] = ring[(i0 * DG + d) * 2 + 1];
+                    r0v[d] = ring_in[(i0 * DG + d) * 2];
+                    r1v[d] = ring_in[(i0 * DG + d) * 2 + 1];
                 }
             }
         }
@@ -306,7 +320,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
         // next position and prefetch of its cell data (overlaps this step's arithmetic)
         nxt.k = cur.k;
         nxt.i = cur.i + 1;
-        if (nxt.i == P) { nxt.i = 0; ++nxt.k; }
+        if (nxt.i == P2) { nxt.i = 0; nxt.k += NB; }
         load_cell(nxt);
         // the lane's DG directions are summed in T, the groups and quadrants in FP64.
         // With f, every lane runs the arithmetic, also a lane outside the mesh: its values never
@@ -389,13 +403,18 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(Sweep2DArgs a) {
         // them in order; without partial sums this compiler-only barrier does (no instruction:
         // the LDS executes one wavefront's accesses in program order).
         if constexpr (WF) asm volatile("" ::: "memory");
+        // with several bands in flight the ring links different wavefronts: a barrier per step
+        // (the partial sums above already hold one)
+        if constexpr (NB > 1) {
+            if (!part_out) __syncthreads();
+        }
         rw = rw + 1 == W ? 0 : rw + 1;
     };
     CellIn A, B;
-    A.k = 0;
-    A.i = -lane;
+    A.k = kb;                                  // band slot kb starts 64 kb steps after slot 0
+    A.i = -lane - 64 * kb;
     load_cell(A);
-    const int total = nb * P + 63;
+    const int total = NB == 1 ? nb * a.P + 63 : a.total;
     int t = 0;
     for (; t + 1 < total; t += 2) {
         step(t, A, B);
@@ -609,14 +628,35 @@ hipError_t sweep2d_launch_t(const SweepLaunch &L, hipStream_t s) {
     a.f_out = L.f_out;
     a.active = L.active;
     const unsigned grid = (unsigned)((long long)a.B * a.nparts);
-    // partial-sum buffers only when partial densities are formed, then the y-trace rings
-    const size_t red = L.partial ? (size_t)2 * W * 64 * 4 * sizeof(double) : 0;
-    const size_t lds = red + (size_t)W * p->nx * DG * 2 * sizeof(T);
+    // bands in flight: the launch's choice, else the handle's, within what the mesh, the
+    // workgroup size and the LDS budget allow
+    const int NB = bands_in_flight(p, L.bands > 0 ? L.bands : sweep_bands(p), L.partial != nullptr,
+                                   sizeof(T));
+    a.wpb = W;
+    a.nbc = NB;
+    a.P2 = a.P > 64 * NB ? a.P : 64 * NB;
+    // the last band (nbands - 1) sits in round (nbands - 1) / NB, slot (nbands - 1) % NB
+    a.total = (a.nbands - 1) / NB * a.P2 + 64 * ((a.nbands - 1) % NB) + a.P + 63;
+    // per band slot: partial-sum buffers (only when partial densities are formed); then the
+    // y-trace rings of every (band slot, direction group)
+    const size_t red = L.partial ? (size_t)NB * 2 * W * 64 * 4 * sizeof(double) : 0;
+    const size_t lds = red + (size_t)NB * W * p->nx * DG * 2 * sizeof(T);
     a.ring_off = (int)(red / sizeof(double));
-    if (L.f_out)
-        hipLaunchKernelGGL((sweep2d_kernel<T, DG, true>), dim3(grid), dim3(64 * W), lds, s, a);
-    else
-        hipLaunchKernelGGL((sweep2d_kernel<T, DG, false>), dim3(grid), dim3(64 * W), lds, s, a);
+    const dim3 blk(64 * W * NB);
+    switch (NB) {
+        case 1:
+            if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 1>), dim3(grid), blk, lds, s, a);
+            else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 1>), dim3(grid), blk, lds, s, a);
+            break;
+        case 2:
+            if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 2>), dim3(grid), blk, lds, s, a);
+            else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 2>), dim3(grid), blk, lds, s, a);
+            break;
+        default:
+            if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 4>), dim3(grid), blk, lds, s, a);
+            else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 4>), dim3(grid), blk, lds, s, a);
+            break;
+    }
     return hipGetLastError();
 }
 
@@ -727,6 +767,26 @@ hipError_t launch_check_materials(const rte_problem *p, int *bad, hipStream_t s)
 
 namespace rte {
 int sweep_waves(const rte_problem *p) { return p->tune.wpb; }
+int sweep_bands(const rte_problem *p) { return p->tune.bands > 0 ? p->tune.bands : 1; }
+
+size_t sweep_lds_bytes(const rte_problem *p, int bands, bool partial, size_t elem) {
+    const int W = p->tune.wpb, DG = p->tune.dg;
+    const size_t red = partial ? (size_t)bands * 2 * W * 64 * 4 * sizeof(double) : 0;
+    return red + (size_t)bands * W * p->nx * DG * 2 * elem;
+}
+
+int bands_in_flight(const rte_problem *p, int requested, bool partial, size_t elem) {
+    // the kernel is compiled for 1, 2 or 4 bands in flight
+    int nb = requested >= 4 ? 4 : requested >= 2 ? 2 : 1;
+    const int nbands = (p->ny + 63) / 64;
+    while (nb > 1 && (nb > nbands || sweep_lds_bytes(p, nb, partial, elem) > kSweepLdsBytes))
+        nb /= 2;
+    return nb;
+}
+
+int sweep_bands_used(const rte_problem *p, rte_precision prec) {
+    return bands_in_flight(p, sweep_bands(p), true, prec == RTE_MIXED ? sizeof(float) : sizeof(double));
+}
 int sweep_nparts(const rte_problem *p) {
     const int W = p->tune.wpb, DG = p->tune.dg;
     int n = 0;

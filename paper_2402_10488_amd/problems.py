@@ -10,12 +10,12 @@ def _dev(a, device="cuda"):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device).contiguous()
 
 
-def plane_problem(plane, device="cuda", dg=0, wpb=0) -> Problem:
+def plane_problem(plane, device="cuda", dg=0, wpb=0, bands=0) -> Problem:
     """Problem handle for every instance of a 2D description (materials uploaded to ``device``)."""
     vx, vy, w = quadrature.plane_rule(plane.quad)
     return Problem(2, plane.nx, plane.ny, vx, w, _dev(plane.sigma_t, device), _dev(plane.sigma_s, device),
                    _dev(plane.G, device), _dev(plane.g, device), dirs_y=vy, lx=plane.Lx, ly=plane.Ly,
-                   dg=dg, wpb=wpb)
+                   dg=dg, wpb=wpb, bands=bands)
 
 
 def slab_problem(slabs, device="cuda") -> Problem:

@@ -87,7 +87,7 @@ EXPORTED = ["rte_problem_create", "rte_problem_create_tuned", "rte_problem_destr
             "rte_inflow_loads", "rte_pgmres_workspace_size", "rte_pgmres_solve", "rte_f_natural",
             "rte_last_device_error", "rte_sweep_noalloc", "rte_tune_sweep",
             "rte_pod_weights", "rte_small_gemm", "rte_chol_upper", "rte_svd_jacobi",
-            "rte_sisa_solve_multi"]
+            "rte_sisa_solve_multi", "rte_problem_create_sched", "rte_problem_bands"]
 
 
 def _load():
@@ -110,6 +110,9 @@ def _load():
     L.rte_last_device_error.argtypes = []
     L.rte_problem_create_tuned.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(P)]
+    L.rte_problem_create_sched.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.POINTER(P)]
+    L.rte_problem_bands.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
     L.rte_problem_destroy.argtypes = [P]
     L.rte_problem_destroy.restype = None
     L.rte_problem_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
@@ -124,7 +127,7 @@ def _load():
     L.rte_sweep_noalloc.argtypes = [P, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
     _ip = ctypes.POINTER(ctypes.c_int)
     L.rte_tune_sweep.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int, ctypes.c_int, _ip, _ip,
-                                 _vp, _vp, ctypes.c_int, ctypes.c_int, _D, _vp]
+                                 _ip, _vp, _vp, ctypes.c_int, ctypes.c_int, _D, _vp]
     L.rte_scalar_flux.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
     L.rte_f_natural.argtypes = [P, _vp, _vp, ctypes.c_int, _vp]
     L.rte_dsa_correct.argtypes = [P, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
@@ -207,7 +210,7 @@ class Problem:
     """
 
     def __init__(self, dim, nx, ny, dirs_x, weights, sigma_t, sigma_s, G, inflow, dirs_y=None,
-                 lx=1.0, ly=1.0, widths=None, dg=0, wpb=0):
+                 lx=1.0, ly=1.0, widths=None, dg=0, wpb=0, bands=0):
         import torch
         for t in (sigma_t, sigma_s, G, inflow):
             assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
@@ -229,8 +232,8 @@ class Problem:
         d = ProblemDesc(dim, nx, ny, self.B, self.n_dir, float(lx), float(ly), pwd, pdx, pdy, pw,
                         _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow))
         h = ctypes.c_void_p()
-        _check(lib.rte_problem_create_tuned(ctypes.byref(d), int(dg), int(wpb), ctypes.byref(h)),
-               "rte_problem_create")
+        _check(lib.rte_problem_create_sched(ctypes.byref(d), int(dg), int(wpb), int(bands),
+                                            ctypes.byref(h)), "rte_problem_create")
         self.handle = h
         self._desc = d            # host arrays it points to are kept above
         self.weights = np.asarray(weights, dtype=np.float64)
@@ -239,7 +242,9 @@ class Problem:
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib.rte_problem_tuning(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "rte_problem_tuning")
-        return {"dg": a.value, "wpb": b.value, "nparts": c.value}
+        nb = ctypes.c_int()
+        _check(lib.rte_problem_bands(self.handle, ctypes.byref(nb)), "rte_problem_bands")
+        return {"dg": a.value, "wpb": b.value, "nparts": c.value, "bands": nb.value}
 
     def dsa_multigrid(self, on=True):
         """Multigrid (default) or block-Jacobi preconditioning of the 2D diffusion CG."""
@@ -334,15 +339,17 @@ NOALLOC_SCRATCH_BYTES = 32 << 20      # RTE_NOALLOC_SCRATCH_BYTES of include/rte
 
 
 def tune_sweep(p: Problem, candidates, rho_in, precision="mixed", f_out=None, warmup=1, reps=3):
-    """Milliseconds per 2D sweep of p's batch under each (dg, wpb) candidate (rte_tune_sweep);
-    -1 marks a candidate the library does not run as given."""
-    c = np.ascontiguousarray(candidates, dtype=np.int32).reshape(-1, 2)
+    """Milliseconds per 2D sweep of p's batch under each (dg, wpb) or (dg, wpb, bands) candidate
+    (rte_tune_sweep); -1 marks a candidate the library does not run as given."""
+    rows = [tuple(c_) + (1,) * (3 - len(c_)) for c_ in candidates]
+    c = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1, 3)
     dg = np.ascontiguousarray(c[:, 0])
     wpb = np.ascontiguousarray(c[:, 1])
+    bands = np.ascontiguousarray(c[:, 2])
     ms = np.zeros(len(c))
     ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
     _check(lib.rte_tune_sweep(ctypes.byref(p._desc), PRECISIONS[precision], len(c), ip(dg), ip(wpb),
-                              _ptr(rho_in), _ptr(f_out), int(warmup), int(reps),
+                              ip(bands), _ptr(rho_in), _ptr(f_out), int(warmup), int(reps),
                               ms.ctypes.data_as(_D), _stream()), "rte_tune_sweep")
     return ms
 
