@@ -18,7 +18,7 @@ def _arr(a):
 
 
 def _create(dim=2, nx=4, ny=3, batch=1, vx=(0.5, -0.5), vy=(0.5, 0.5), w=(0.5, 0.5),
-            widths=None, lx=1.0, ly=1.0, dg=0, wpb=0):
+            widths=None, lx=1.0, ly=1.0, dg=0, wpb=0, bands=0):
     keep = []
     _, pvx = _arr(vx); keep.append(_)
     _, pvy = _arr(vy); keep.append(_)
@@ -29,7 +29,7 @@ def _create(dim=2, nx=4, ny=3, batch=1, vx=(0.5, -0.5), vy=(0.5, 0.5), w=(0.5, 0
     d = rte.ProblemDesc(dim, nx, ny, batch, len(vx), lx, ly, pwd, pvx,
                         pvy if dim == 2 else None, pw, FAKE, FAKE, FAKE, FAKE)
     h = ctypes.c_void_p()
-    rc = lib.rte_problem_create_tuned(ctypes.byref(d), dg, wpb, ctypes.byref(h))
+    rc = lib.rte_problem_create_sched(ctypes.byref(d), dg, wpb, bands, ctypes.byref(h))
     return rc, h
 
 
@@ -45,6 +45,8 @@ def _create(dim=2, nx=4, ny=3, batch=1, vx=(0.5, -0.5), vy=(0.5, 0.5), w=(0.5, 0
     dict(dg=16),                                         # 1, 2, 4 or 8 directions per lane
     dict(dg=3),
     dict(wpb=5),
+    dict(bands=-1),                                      # 0 (automatic) to 16 bands in flight
+    dict(bands=17),
     dict(dim=1, ny=2, widths=[0.25] * 4),                # a slab has one row
     dict(dim=1, ny=1, widths=[0.25, 0.0, 0.25, 0.5]),    # cell widths must be positive
     dict(dim=1, ny=1, widths=None),
@@ -58,6 +60,8 @@ def test_problem_create_rejects_invalid_descriptions(kw):
 def test_problem_create_rejects_null_arguments():
     h = ctypes.c_void_p()
     assert lib.rte_problem_create_tuned(None, 0, 0, ctypes.byref(h)) == rte.RTE_EINVAL
+    assert lib.rte_problem_create_sched(None, 0, 0, 0, ctypes.byref(h)) == rte.RTE_EINVAL
+    assert lib.rte_problem_bands(None, ctypes.byref(ctypes.c_int())) == rte.RTE_EINVAL
 
 
 def test_entry_points_reject_a_null_problem():
