@@ -102,6 +102,35 @@ def test_c4_full_size_point_symmetry(c4):
 
 
 @pytest.fixture(scope="module")
+def c4_sweep_oracle():
+    """The oracle's FP64 sweep of the C4 instance for one seeded density (about 4 s on one core)."""
+    plane = W.c4_multiscale()
+    d = discretize(plane, 0)
+    rho = np.random.default_rng(4).uniform(0.0, 1.0, d.ndof) * np.sqrt(d.hx * d.hy)
+    say("c4 oracle sweep")
+    r_or, _ = d.sweep(rho)
+    return plane, rho, r_or
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c4_full_size_sweep_against_oracle(R, c4_sweep_oracle, precision):
+    """One transport sweep (eq. (transport_sweep)) of the 512^2, 256-direction instance in the
+    schedule the benchmark's C4 leg runs (the automatic one: one direction per lane, two
+    wavefronts per band, four bands in flight), element by element against the oracle's sweep
+    of the same density: 1e-12 in FP64, 2e-6 with the FP32 sweep."""
+    import torch
+    rte, problems, _ = R
+    plane, rho, r_or = c4_sweep_oracle
+    P = problems.plane_problem(plane)
+    say(f"c4 sweep {precision}, tuning {P.tuning()}")
+    rs = torch.zeros((1, P.ndof), dtype=torch.float64, device="cuda")
+    rte.sweep(P, torch.as_tensor(rho[None], device="cuda"), rho_star_out=rs, precision=precision)
+    e = rel_err(host(rs)[0], r_or)
+    say(f"  error {e:.3g}")
+    assert e < (1e-12 if precision == "fp64" else 2e-6)
+
+
+@pytest.fixture(scope="module")
 def c4_ref(R):
     """The C4 solution to a tight tolerance: FP64 SI-DSA to a relative change of 1e-11."""
     import torch
