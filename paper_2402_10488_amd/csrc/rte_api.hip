@@ -330,6 +330,38 @@ struct rte_iter_graph {
     }
 };
 
+// The multigrid preconditioner's launches (one graph per parity slot of its (r, z) partial sums),
+// kept by the problem handle for the workspace carve-up they were captured with: their kernels
+// hold its device pointers, so a call with another workspace, mode, precision, iteration
+// history, ROM or preconditioner choice captures again.  A call holds the graphs it uses by a
+// shared pointer, so a capture for another call on the handle never frees them under it.
+struct rte_precond_graphs {
+    struct Exec {
+        hipGraphExec_t g[2] = {nullptr, nullptr};
+        ~Exec() {
+            for (hipGraphExec_t &x : g)
+                if (x) (void)hipGraphExecDestroy(x);
+        }
+    };
+    struct Key {
+        int caller;                           // 0 rte_sisa_solve, 1 rte_pgmres_solve
+        const void *ws;
+        size_t ws_bytes;
+        int mode, precision, max_iter, mg;
+        unsigned long long rom;
+        const void *z, *t, *part;             // a check on the carve-up itself
+        bool operator==(const Key &o) const {
+            return caller == o.caller && ws == o.ws && ws_bytes == o.ws_bytes && mode == o.mode &&
+                   precision == o.precision && max_iter == o.max_iter && mg == o.mg &&
+                   rom == o.rom && z == o.z && t == o.t && part == o.part;
+        }
+    };
+    std::mutex mu;
+    Key key{};
+    bool valid = false;
+    std::shared_ptr<Exec> cur;
+};
+
 int rte_problem::nparts() const { return nparts_for(this); }
 
 extern "C" {
@@ -528,6 +560,7 @@ void rte_problem_destroy(rte_problem *p) {
     if (p->d_widths) (void)hipFree(p->d_widths);
     if (p->d_vxy) (void)hipFree(p->d_vxy);
     delete p->iter_graph;
+    delete p->precond_graphs;
     delete p;
 }
 
@@ -731,15 +764,62 @@ int do_dsa(const rte_problem *p, const Layout &L, const double *rho_star, const 
 }
 
 
-// The multigrid preconditioner captured as graphs for the duration of one long call (released on
-// every return path); the kernels run one by one when capture is off or fails.
+// The multigrid preconditioner as graphs for one long call: the handle's cached capture for this
+// carve-up, or a new one (kept for the next call).  The graphs stay alive while the call holds
+// them; the kernels run one by one when capture is off or fails.
 struct PrecondGraphs {
     CGSpace &c;
-    PrecondGraphs(const rte_problem *p, CGSpace &cg, bool on) : c(cg) {
-        if (on) mg_precond_capture(p, c);
+    std::shared_ptr<rte_precond_graphs::Exec> ex;
+    PrecondGraphs(const rte_problem *p, CGSpace &cg, bool on,
+                  const rte_precond_graphs::Key &k) : c(cg) {
+        c.precond[0] = c.precond[1] = nullptr;
+        if (!on || c.mg.L == 0) return;
+        if (!p->precond_graphs) {
+            p->precond_graphs = new (std::nothrow) rte_precond_graphs();
+            if (!p->precond_graphs) return;
+        }
+        rte_precond_graphs &G = *p->precond_graphs;
+        std::lock_guard<std::mutex> lock(G.mu);
+        if (!(G.valid && G.key == k)) {
+            G.valid = false;
+            G.cur.reset();
+            CGSpace tmp = c;
+            mg_precond_capture(p, tmp);
+            if (!tmp.precond[0] || !tmp.precond[1]) {
+                mg_precond_release(tmp);
+                return;
+            }
+            auto e = std::make_shared<rte_precond_graphs::Exec>();
+            e->g[0] = tmp.precond[0];
+            e->g[1] = tmp.precond[1];
+            G.cur = e;
+            G.key = k;
+            G.valid = true;
+        }
+        ex = G.cur;
+        c.precond[0] = ex->g[0];
+        c.precond[1] = ex->g[1];
     }
-    ~PrecondGraphs() { mg_precond_release(c); }
+    ~PrecondGraphs() { c.precond[0] = c.precond[1] = nullptr; }
 };
+
+rte_precond_graphs::Key precond_key(int caller, const rte_problem *p, const Layout &L,
+                                    const void *ws, size_t ws_bytes, int mode, int precision,
+                                    int max_iter, const rte_rom *rom) {
+    rte_precond_graphs::Key k{};
+    k.caller = caller;
+    k.ws = ws;
+    k.ws_bytes = ws_bytes;
+    k.mode = mode;
+    k.precision = precision;
+    k.max_iter = max_iter;
+    k.mg = p->dsa_mg;
+    k.rom = rom ? rom->serial : 0ull;
+    k.z = L.cg.z;
+    k.t = L.cg.mg.t;
+    k.part = L.cg.part;
+    return k;
+}
 
 // psi is checked only where the ROM correction runs (need_psi)
 int check_solve_args(const rte_problem *p, rte_mode mode, const rte_rom *rom, const double *psi,
@@ -1180,7 +1260,9 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     HIPCHK(launch_zero_rows(L.delta, p->B, p->ndof, nullptr, s));
     HIPCHK(launch_zero_u64(L.cg_total, 1, s));
     if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
-    PrecondGraphs graphs(p, L.cg, mode != RTE_SI && p->dim == 2 && o->graph_cg_iters <= 0);
+    PrecondGraphs graphs(p, L.cg, mode != RTE_SI && p->dim == 2 && o->graph_cg_iters <= 0,
+                         precond_key(0, p, L, ws, ws_bytes, (int)mode, (int)o->precision,
+                                     o->max_iter, mode == RTE_ROMSAD ? rom : nullptr));
     HIPCHK(launch_source(p, rho, L.src, nullptr, o->precision == RTE_MIXED, s));
     int iterations = 0;
     bool cg_failed = false;
@@ -1281,7 +1363,9 @@ int rte_pgmres_solve(const rte_problem *p, const rte_krylov_opts *o, double *rho
     HIPCHK(launch_fill_int(G.n_sweep, p->B, 0, s));
     HIPCHK(launch_fill_int(G.n_iter, p->B, 0, s));
     if (o->precondition && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, nullptr, s));
-    PrecondGraphs graphs(p, L.cg, o->precondition && p->dim == 2);
+    PrecondGraphs graphs(p, L.cg, o->precondition && p->dim == 2,
+                         precond_key(1, p, L, ws, ws_bytes, (int)RTE_SI_DSA, (int)RTE_FP64,
+                                     o->restart, nullptr));
     // b_bar: one sweep from zero with the source and the inflow; |M^-1 b_bar|
     HIPCHK(launch_zero_rows(G.u, p->B, p->ndof, nullptr, s));
     if ((rc = sweep(G.u, G.bbar, G.act, false))) return rc;

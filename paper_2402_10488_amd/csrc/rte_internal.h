@@ -66,6 +66,9 @@ struct rte_problem {
     // the outer iteration of rte_sisa_solve / rte_sisa_iterate captured as a HIP graph for the
     // last (workspace, arguments) it was used with; owned by the handle (rte_api.hip)
     mutable struct rte_iter_graph *iter_graph;
+    // the multigrid preconditioner of the 2D diffusion CG captured as HIP graphs for the last
+    // workspace carve-up it was used with; owned by the handle (rte_api.hip)
+    mutable struct rte_precond_graphs *precond_graphs;
 };
 
 namespace rte {

@@ -152,3 +152,21 @@ def test_graph_session_equals_eager_session(R):
         out.append((host(S.rho), S.n_sweep.copy()))
     assert np.array_equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][0], out[1][0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_preconditioner_graphs_kept_across_calls(R, precision):
+    """The multigrid preconditioner's graphs are captured once per (handle, workspace carve-up)
+    and replayed by later calls.  Repeated solves on one workspace, a solve on a second one (a
+    new capture) and a return to the first (another) give bitwise-equal results, and so does a
+    fresh handle."""
+    rte, problems = R
+    plane = W.c2_lattice([20000 + i for i in range(3)], n=48, n_phi=16, left_inflow=True)
+    P = problems.plane_problem(plane)
+    kw = dict(precision=precision, cg_rtol=1e-6, max_iter=300)
+    ws1 = P.workspace("si_dsa", None, precision, 300)
+    ws2 = P.workspace("si_dsa", None, precision, 300)
+    ref = _run(rte, problems.plane_problem(plane), "si_dsa", 1e-8, **kw)
+    for k, ws in enumerate([ws1, ws1, ws2, ws1, ws1]):
+        say(f"preconditioner graphs {precision}: call {k}")
+        _same(_run(rte, P, "si_dsa", 1e-8, ws=ws, **kw), ref)
