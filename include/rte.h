@@ -207,7 +207,13 @@ int rte_workspace_size(const rte_problem *p, rte_mode mode, const rte_rom *rom,
  *                 double).  2D with f_out: fewer than 2^26 cells per instance (RTE_EUNSUPPORTED
  *                 beyond)
  *   rho_star_out  device [B][N_DOF], rho^* = sum_j w_j f_j; may be NULL
- *   zero_inflow   nonzero: use g = 0 (the kinetic correction equation's boundary condition) */
+ *   zero_inflow   nonzero: use g = 0 (the kinetic correction equation's boundary condition)
+ * 2D: an instance whose sigma_t takes at most 16 distinct values is swept from a table of the
+ * cell solve's sigma_t-dependent coefficients per (direction, value), formed in FP64 in the
+ * workspace at the start of the call (rte_sisa_solve: of the solve; rte_sisa_admit: of the
+ * admitted slots); an instance with more values, or a NaN, by the per-cell solve.  Both are
+ * the same cell solve; the table form rounds its coefficients once instead of forming them in
+ * the sweep's precision at every cell. */
 int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
               int zero_inflow, rte_precision prec, void *ws, size_t ws_bytes, rte_stream_t stream);
 

@@ -53,6 +53,12 @@ struct Layout {
     int *flag;
     int *mask;              // [B] instances selected by rte_sisa_admit
     GmresSpace gm;          // DSA-preconditioned GMRES (rte_pgmres_solve)
+    // 2D material tables of the sweep (launch_materials): cell indices [B][ncell], flags and
+    // counts [B], values [B][kMaxMat], coefficients [B][n_sorted][kMaxMat][8] T
+    int *mat, *mat_ok, *nmat;
+    double *mvals;
+    void *mcoef;
+    bool use_mat;           // host: this call's sweeps use them (prepared in this workspace)
     // host-side: the CG iteration after which the previous diffusion solve of this call was
     // first seen finished (0: none yet); where do_dsa first looks at the running count
     mutable int cg_look;
@@ -85,6 +91,13 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
     L.cg_fail = c.take<int>(1);
     L.flag = c.take<int>(1);
     L.mask = c.take<int>(B);
+    if (p->dim == 2) {
+        L.mat = c.take<int>(B * (size_t)p->ncell);
+        L.mat_ok = c.take<int>(B);
+        L.nmat = c.take<int>(B);
+        L.mvals = c.take<double>(B * (size_t)kMaxMat);
+        L.mcoef = c.take<char>(B * (size_t)p->n_sorted * kMaxMat * 8 * ts);
+    }
     if (mode != RTE_SI) {
         if (p->dim == 2) {
             L.cg.nblk = (int)cg_blocks_per_instance(p);
@@ -528,6 +541,12 @@ int rte_problem_create_sched(const rte_problem_desc *d, int dg, int wpb, int ban
     }
     p->n_sorted = (int)table.size();
     choose_tuning(p, dg, wpb, bands);
+    // the sweep's table kernels need dynamic LDS past 64 KiB (set once, outside any capture)
+    {
+        static std::once_flag lds_once;
+        const int lds_max = p->lds_per_cu;
+        std::call_once(lds_once, [lds_max] { sweep_lds_limits(lds_max); });
+    }
     hipError_t e = hipSuccess;
     auto upload = [&](auto **dst, const void *src, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc((void **)dst, bytes);
@@ -685,6 +704,19 @@ void rte_rom_destroy(rte_rom *r) {
 namespace {
 
 // one sweep of every active instance: src -> rho_star (+ change maxima against rho_prev)
+// The material tables of the selected instances (all if mask is null) for this call's sweeps
+bool mat_usable(const rte_problem *p, const Layout &L, int fp32) {
+    return p->dim == 2 && L.mat && sweep_mat_fits(p, fp32 ? sizeof(float) : sizeof(double));
+}
+
+int prepare_materials(const rte_problem *p, Layout &L, const int *mask, int fp32, hipStream_t s) {
+    L.use_mat = false;
+    if (!mat_usable(p, L, fp32)) return RTE_OK;
+    HIPCHK(launch_materials(p, mask, L.mat, L.mat_ok, L.nmat, L.mvals, L.mcoef, fp32, s));
+    L.use_mat = true;
+    return RTE_OK;
+}
+
 int do_sweep(const rte_problem *p, const Layout &L, const void *src, void *f_out,
              double *rho_star, const double *rho_prev, const int *active, int zero_inflow,
              int fp32, hipStream_t s) {
@@ -699,6 +731,10 @@ int do_sweep(const rte_problem *p, const Layout &L, const void *src, void *f_out
         a.active = active;
         a.zero_inflow = zero_inflow;
         a.fp32 = fp32;
+        if (L.use_mat) {
+            a.mat_ok = L.mat_ok;
+            a.mat_coef = L.mcoef;
+        }
         {
             ProfScope ps(RTE_PROF_SWEEP2D, s);
             HIPCHK(launch_sweep2d(a, s));
@@ -1059,19 +1095,34 @@ int finish_stats(const rte_problem *p, const Layout &L, int max_iter, int iterat
 
 }  // namespace
 
+// One sweep of rte_sweep.  prepare: form the material tables first (else the ones an earlier
+// call formed in this workspace are used).
+int sweep_call(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
+               int zero_inflow, rte_precision prec, void *ws, size_t ws_bytes, hipStream_t s,
+               bool prepare) {
+    Carver c(ws, ws_bytes);
+    Layout L = carve(c, p, RTE_SI, nullptr, prec, 1);
+    if (!c.ok) return RTE_ENOMEM;
+    const int fp32 = prec == RTE_MIXED;
+    if (prepare) {
+        const int rc = prepare_materials(p, L, nullptr, fp32, s);
+        if (rc) return rc;
+    } else {
+        L.use_mat = mat_usable(p, L, fp32);
+    }
+    HIPCHK(launch_source(p, rho_in, L.src, nullptr, fp32, s, true, L.use_mat ? L.mat : nullptr,
+                         L.mat_ok));
+    return do_sweep(p, L, L.src, f_out, rho_star_out, nullptr, nullptr, zero_inflow, fp32, s);
+}
+
 extern "C" {
 
 int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *rho_star_out,
               int zero_inflow, rte_precision prec, void *ws, size_t ws_bytes, rte_stream_t stream) {
     if (!p || !rho_in || (!f_out && !rho_star_out) || !ws) return RTE_EINVAL;
     if (prec != RTE_FP64 && prec != RTE_MIXED) return RTE_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    Carver c(ws, ws_bytes);
-    Layout L = carve(c, p, RTE_SI, nullptr, prec, 1);
-    if (!c.ok) return RTE_ENOMEM;
-    const int fp32 = prec == RTE_MIXED;
-    HIPCHK(launch_source(p, rho_in, L.src, nullptr, fp32, s));
-    return do_sweep(p, L, L.src, f_out, rho_star_out, nullptr, nullptr, zero_inflow, fp32, s);
+    return sweep_call(p, rho_in, f_out, rho_star_out, zero_inflow, prec, ws, ws_bytes,
+                      (hipStream_t)stream, true);
 }
 
 }  // extern "C"
@@ -1129,8 +1180,10 @@ int rte_sweep_noalloc(const rte_problem *p, const double *rho_in, void *f_out, d
     void *ws = nullptr;
     int rc = scratch_address(&ws);
     if (rc) return rc;
-    return rte_sweep(p, rho_in, f_out, rho_star_out, zero_inflow, prec, ws,
-                     (size_t)RTE_NOALLOC_SCRATCH_BYTES, stream);
+    // rte_sweep's kernels, material tables included (the material kernels write every value
+    // they or the sweep read, so nothing left by an earlier call matters)
+    return sweep_call(p, rho_in, f_out, rho_star_out, zero_inflow, prec, ws,
+                      (size_t)RTE_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream, true);
 }
 
 int rte_tune_sweep(const rte_problem_desc *desc, rte_precision prec, int n_cand, const int *dg,
@@ -1164,11 +1217,13 @@ int rte_tune_sweep(const rte_problem_desc *desc, rte_precision prec, int n_cand,
         hipError_t e = hipMalloc(&ws, bytes);
         if (e == hipSuccess) e = hipMalloc((void **)&rs, sizeof(double) * (size_t)p->B * p->ndof);
         if (e != hipSuccess) rc = device_error(e);
+        // the material tables once, as a solve forms them once; then the timed sweeps
+        if (rc == RTE_OK) rc = sweep_call(p, rho_in, f_out, rs, 0, prec, ws, bytes, s, true);
         for (int k = 0; k < warmup && rc == RTE_OK; ++k)
-            rc = rte_sweep(p, rho_in, f_out, rs, 0, prec, ws, bytes, stream);
+            rc = sweep_call(p, rho_in, f_out, rs, 0, prec, ws, bytes, s, false);
         if (rc == RTE_OK) rc = hipEventRecord(ev[0], s) == hipSuccess ? RTE_OK : RTE_EDEVICE;
         for (int k = 0; k < reps && rc == RTE_OK; ++k)
-            rc = rte_sweep(p, rho_in, f_out, rs, 0, prec, ws, bytes, stream);
+            rc = sweep_call(p, rho_in, f_out, rs, 0, prec, ws, bytes, s, false);
         if (rc == RTE_OK) {
             e = hipEventRecord(ev[1], s);
             if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
@@ -1263,7 +1318,9 @@ int rte_sisa_solve(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     PrecondGraphs graphs(p, L.cg, mode != RTE_SI && p->dim == 2 && o->graph_cg_iters <= 0,
                          precond_key(0, p, L, ws, ws_bytes, (int)mode, (int)o->precision,
                                      o->max_iter, mode == RTE_ROMSAD ? rom : nullptr));
-    HIPCHK(launch_source(p, rho, L.src, nullptr, o->precision == RTE_MIXED, s));
+    if ((rc = prepare_materials(p, L, nullptr, o->precision == RTE_MIXED, s))) return rc;
+    HIPCHK(launch_source(p, rho, L.src, nullptr, o->precision == RTE_MIXED, s, true,
+                         L.use_mat ? L.mat : nullptr, L.mat_ok));
     int iterations = 0;
     bool cg_failed = false;
     rc = run_iterations(p, L, mode, rom, psi, o, rho, f_out, o->max_iter, ws, ws_bytes, s,
@@ -1440,6 +1497,7 @@ int rte_sisa_begin(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     if (!c.ok) return RTE_ENOMEM;
     HIPCHK(launch_init_state(p, L.st, o->max_iter, nullptr, 0, s));
     HIPCHK(launch_zero_u64(L.cg_total, 1, s));
+    if (L.mat_ok) HIPCHK(launch_fill_int(L.mat_ok, p->B, 0, s));   // no slot has a table yet
     return RTE_OK;
 }
 
@@ -1463,7 +1521,9 @@ int rte_sisa_admit(const rte_problem *p, rte_mode mode, const rte_rom *rom, cons
     HIPCHK(launch_init_state(p, L.st, o->max_iter, L.mask, 1, s));
     HIPCHK(launch_zero_rows(L.delta, p->B, p->ndof, L.mask, s));
     if (mode != RTE_SI && p->dim == 2) HIPCHK(launch_dsa_build(p, L.cg, L.mask, s));
-    HIPCHK(launch_source(p, rho, L.src, L.mask, o->precision == RTE_MIXED, s));
+    if ((rc = prepare_materials(p, L, L.mask, o->precision == RTE_MIXED, s))) return rc;
+    HIPCHK(launch_source(p, rho, L.src, L.mask, o->precision == RTE_MIXED, s, true,
+                         L.use_mat ? L.mat : nullptr, L.mat_ok));
     // the host mask must outlive the copy
     HIPCHK(hipStreamSynchronize(s));
     return RTE_OK;
@@ -1479,6 +1539,7 @@ int rte_sisa_iterate(const rte_problem *p, rte_mode mode, const rte_rom *rom, co
     Carver c(ws, ws_bytes);
     Layout L = carve(c, p, mode, mode == RTE_ROMSAD ? rom : nullptr, o->precision, o->max_iter);
     if (!c.ok) return RTE_ENOMEM;
+    L.use_mat = mat_usable(p, L, o->precision == RTE_MIXED);   // prepared by rte_sisa_admit
     int iterations = 0;
     bool cg_failed = false;
     rc = run_iterations(p, L, mode, rom, psi, o, rho, nullptr, n_iter, ws, ws_bytes, s,

@@ -21,7 +21,8 @@ struct DirEntry {
     int pad;
 };
 
-constexpr int kQuadPad = 16;   // each quadrant's block of the sorted table is padded to this multiple
+constexpr int kQuadPad = 16;
+constexpr int kMaxMat = 16;    // materials (distinct sigma_t) of an instance swept from its table   // each quadrant's block of the sorted table is padded to this multiple
 
 // Per-quadrant layout of the sorted direction table.
 struct QuadLayout {
@@ -224,7 +225,8 @@ namespace rte {
 
 // 2D sweep input block (one allocation, T = float or double):
 //   srcA [B][ncell][4], srcB [B][ncell][4]  sigma_s rho + G sqrt(hx hy) delta_k0 in layouts A, B
-//   sigA [B][ncell],    sigB [B][ncell]     sigma_t in layouts A, B
+//   sigA [B][ncell],    sigB [B][ncell]     sigma_t in layouts A, B (an instance with a
+//                                           material table: the cell's material index)
 // 1D: src [B][ncell][2] in natural order.
 struct SweepLaunch {
     const rte_problem *p;
@@ -235,8 +237,23 @@ struct SweepLaunch {
     int zero_inflow;
     int fp32;
     int bands = 0;            // bands in flight (0: the handle's schedule); results do not depend on it
+    // material tables (launch_materials; both null: every instance by the per-cell kernel)
+    const int *mat_ok = nullptr;      // [B] 1: swept by the table kernel
+    const void *mat_coef = nullptr;   // [B][n_sorted][kMaxMat][8] T
 };
 hipError_t launch_sweep2d(const SweepLaunch &a, hipStream_t s);
+// Per instance (mask[b] != 0, all if null): the distinct sigma_t values (vals [B][kMaxMat]
+// ascending, nmat [B]), each cell's index among them (mat [B][ncell]), mat_ok [B] = 1 when there
+// are at most kMaxMat and every cell has one, and the cell-solve coefficients of every (sorted
+// direction, material) in T (coef [B][n_sorted][kMaxMat][8]).
+hipError_t launch_materials(const rte_problem *p, const int *mask, int *mat, int *mat_ok,
+                            int *nmat, double *vals, void *coef, int fp32, hipStream_t s);
+// LDS bytes a table kernel adds to a sweep workgroup (elem: sizeof T), and whether the table
+// kernels fit the device's LDS for every launch of the handle's schedule
+size_t sweep_mat_lds_bytes(const rte_problem *p, size_t elem);
+bool sweep_mat_fits(const rte_problem *p, size_t elem);
+// dynamic LDS limit of every 2D sweep kernel (once per process)
+void sweep_lds_limits(int bytes);
 // wavefronts per sweep workgroup (direction groups summed in LDS) and partial slots per instance
 int sweep_waves(const rte_problem *p);
 int sweep_bands(const rte_problem *p);
@@ -244,6 +261,8 @@ int sweep_bands(const rte_problem *p);
 // and the LDS budget for partial sums (if any) and rings of elem-byte values); the number a solve
 // of precision prec uses
 int bands_in_flight(const rte_problem *p, int requested, bool partial, size_t elem);
+// LDS bytes of a per-cell sweep workgroup with `bands` in flight
+size_t sweep_lds_bytes(const rte_problem *p, int bands, bool partial, size_t elem);
 int sweep_bands_used(const rte_problem *p, rte_precision prec);
 int sweep_nparts(const rte_problem *p);
 
@@ -251,10 +270,12 @@ int sweep_nparts(const rte_problem *p);
 hipError_t launch_sweep1d(const rte_problem *p, const void *src, void *f_out, const int *active,
                           int zero_inflow, int fp32, hipStream_t s);
 
-// sweep input block from rho: src = sigma_s rho + G * (cell integral of phi_0), plus sigma_t
-// (with_G false: src = sigma_s rho, the source of L rho)
+// sweep input block from rho: src = sigma_s rho + G * (cell integral of phi_0), plus sigma_t, or
+// for instances with mat_ok[b] != 0 (mat, mat_ok from launch_materials, nullable) the material
+// index (with_G false: src = sigma_s rho, the source of L rho)
 hipError_t launch_source(const rte_problem *p, const double *rho, void *src, const int *active,
-                         int fp32, hipStream_t s, bool with_G = true);
+                         int fp32, hipStream_t s, bool with_G = true, const int *mat = nullptr,
+                         const int *mat_ok = nullptr);
 
 // rho = sum of nparts partial slots (fixed order); optional change/magnitude maxima per instance
 hipError_t launch_reduce_parts(const rte_problem *p, const double *partial, int nparts,

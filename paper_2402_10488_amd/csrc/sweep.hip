@@ -17,6 +17,8 @@
 //   (A from the volume and outflow-edge terms of eq. (DG) in the orthonormal basis), solved in
 //   closed form by block elimination: with X = aA + (b+sigma)I, Y = aA + (3b+sigma)I and
 //   A^2 = 4A - 6I, the Schur complement X Y + 3 b^2 I = uA + wI is again a polynomial in A.
+#include <type_traits>
+
 #include "rte_internal.h"
 
 namespace rte {
@@ -43,6 +45,12 @@ struct Sweep2DArgs {
     void *f_out;
     int ring_off;            // LDS offset (in doubles) of the y-trace rings
     const int *active;
+    // material tables: with mat_ok set, the table kernel sweeps the instances with mat_ok[b] != 0
+    // and the per-cell kernel the others
+    const int *mat_ok;       // [B] or null
+    const void *mcoef;       // [B][n_sorted][kMaxMat][8] T (mat_coef_kernel)
+    int n_sorted;
+    int mcoef_off;           // LDS offset (in doubles) of the workgroup's copy of its table rows
 };
 
 __device__ __forceinline__ float recip(float x);
@@ -186,7 +194,9 @@ __device__ __forceinline__ void store_f4(__amdgpu_buffer_rsrc_t r, int off, cons
 // slot k mod nbc 64 steps behind the slot above it, which hands its last row's y-traces on
 // through an LDS ring: the same cells, solves and sums in the same order as with one band in
 // flight, over fewer dependent steps (a band no longer waits for the whole band above).
-template <typename T, int DG, bool WF, int NB>
+// MAT: the cell solve's coefficients that depend on sigma_t come from the instance's material
+// table (the sweep input then carries the cell's material index in place of sigma_t).
+template <typename T, int DG, bool WF, int NB, bool MAT>
 __global__ void __launch_bounds__(256 * NB) sweep2d_kernel(Sweep2DArgs a) {
     extern __shared__ double smem_d[];
     const int lane = threadIdx.x & 63;
@@ -198,6 +208,7 @@ __global__ void __launch_bounds__(256 * NB) sweep2d_kernel(Sweep2DArgs a) {
     const int b = item / a.nparts;
     const int gpart = item - b * a.nparts;
     if (a.active && a.active[b] == 0) return;
+    if (a.mat_ok && (a.mat_ok[b] != 0) != MAT) return;    // the other kernel's instance
     int part = gpart, q = 0;
     while (q < 3 && part >= a.gq[q]) { part -= a.gq[q]; ++q; }
     const int g = part * W + wv;                              // direction group of this wave
@@ -260,6 +271,24 @@ __global__ void __launch_bounds__(256 * NB) sweep2d_kernel(Sweep2DArgs a) {
     T tx0[DG], tx1[DG], ty0[DG], ty1[DG];
 #pragma unroll
     for (int d = 0; d < DG; ++d) { tx0[d] = tx1[d] = ty0[d] = ty1[d] = T(0); }
+    // the material table rows of the workgroup's W x DG directions, copied into LDS once (a
+    // direction past the quadrant's padded table gets zeros: its values are never used)
+    const Vec4<T> *mt = nullptr;
+    if constexpr (MAT) {
+        Vec4<T> *mtw = reinterpret_cast<Vec4<T> *>(smem_d + a.mcoef_off);
+        const Vec4<T> *gm = reinterpret_cast<const Vec4<T> *>(a.mcoef) +
+                            (size_t)b * a.n_sorted * kMaxMat * 2;
+        const int first = a.qstart[q] + part * W * DG;
+        for (int e = threadIdx.x; e < W * DG * kMaxMat * 2; e += blockDim.x) {
+            const int di = first + e / (kMaxMat * 2);
+            Vec4<T> v;
+            v.x = v.y = v.z = v.w = T(0);
+            if (di < dend) v = gm[(size_t)first * kMaxMat * 2 + e];
+            mtw[e] = v;
+        }
+        __syncthreads();
+        mt = mtw + (size_t)wv * DG * kMaxMat * 2;
+    }
 
     // lane position in the pipeline: band k, column i (k P + i = t - lane), tracked
     // incrementally so the loop carries no division
@@ -347,7 +376,23 @@ __global__ void __launch_bounds__(256 * NB) sweep2d_kernel(Sweep2DArgs a) {
                 const T r2 = s2 + dc[d].al * tx1[d] - dc[d].cb * yi0[d];
                 const T r3 = s3 - dc[d].ca * tx1[d] - dc[d].cb * yi1[d];
                 T f0, f1, f2, f3;
-                q1_solve<T>(dc[d], sig, r0, r1, r2, r3, f0, f1, f2, f3);
+                if constexpr (MAT) {
+                    // (x00, x11, (3u + w)/detM, s3 u/detM), ((u + w)/detM, x11/detX, x00/detX,
+                    // s3 a/detX) of the cell's material: q1_solve with its divisions folded in
+                    const int m = (int)sig & (kMaxMat - 1);
+                    const Vec4<T> c0 = mt[(d * kMaxMat + m) * 2];
+                    const Vec4<T> c1 = mt[(d * kMaxMat + m) * 2 + 1];
+                    const T g0 = c0.x * r2 + (dc[d].ca * r3 + dc[d].cb * r0);
+                    const T g1 = c0.y * r3 + (dc[d].cb * r1 - dc[d].ca * r2);
+                    f2 = c0.z * g0 - c0.w * g1;
+                    f3 = c0.w * g0 + c1.x * g1;
+                    const T h0 = r0 - dc[d].cb * f2;
+                    const T h1 = r1 - dc[d].cb * f3;
+                    f0 = c1.y * h0 - c1.w * h1;
+                    f1 = c1.w * h0 + c1.z * h1;
+                } else {
+                    q1_solve<T>(dc[d], sig, r0, r1, r2, r3, f0, f1, f2, f3);
+                }
                 tx0[d] = f0 + c * f1;
                 tx1[d] = f2 + c * f3;
                 ty0[d] = f0 + c * f2;
@@ -461,11 +506,13 @@ __global__ void __launch_bounds__(256) sweep1d_kernel(int nc, int n_dir, int B, 
 }
 
 // ------------------------------------------------------------------ source, reductions
+// mat / mat_ok (2D, nullable): an instance with mat_ok[b] != 0 gets each cell's material index in
+// place of its sigma_t (the table kernel of the sweep reads it)
 template <typename T>
 __global__ void source_kernel(int dim, long long ncell, int K, int B, int nx, int ny,
                               const double *rho, const double *sigma_t, const double *sigma_s,
                               const double *G, const double *cellw, double ghost, T *src,
-                              const int *active) {
+                              const int *active, const int *mat, const int *mat_ok) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)B * ncell) return;
     const int b = (int)(t / ncell);
@@ -475,7 +522,104 @@ __global__ void source_kernel(int dim, long long ncell, int K, int B, int nx, in
     const double g0 = G ? G[t] * (cellw ? sqrt(cellw[cell]) : ghost) : 0.0;   // G null: no source
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < K; ++k) v[k] = ss * rho[t * K + k] + (k == 0 ? g0 : 0.0);
-    write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, v, sigma_t[t], src);
+    const double st = mat && mat_ok[b] ? (double)mat[t] : sigma_t[t];
+    write_sweep_input<T>(dim, ncell, B, b, nx, ny, cell, v, st, src);
+}
+
+// ------------------------------------------------------------------ materials
+// The distinct sigma_t values of each selected instance, ascending (at most kMaxMat): round r
+// finds the smallest value above the previous round's by a block-wide minimum.  nmat[b] is their
+// count (kMaxMat when there are more), mat_ok[b] = 0 when there are more.
+__global__ void __launch_bounds__(256) mat_scan_kernel(long long ncell, const double *sigma_t,
+                                                       const int *mask, double *vals, int *nmat,
+                                                       int *mat_ok) {
+    __shared__ double wmin[4];
+    const int b = blockIdx.x;
+    if (mask && mask[b] == 0) return;
+    const double *sb = sigma_t + (size_t)b * ncell;
+    double last = -INFINITY;
+    int n = 0;
+    bool over = false;
+    for (int r = 0; r <= kMaxMat; ++r) {
+        double mn = INFINITY;
+        for (long long c = threadIdx.x; c < ncell; c += blockDim.x) {
+            const double v = sb[c];
+            if (v > last && v < mn) mn = v;
+        }
+        for (int off = 32; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, 64));
+        if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = mn;
+        __syncthreads();
+        mn = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+        __syncthreads();
+        if (!(mn < INFINITY)) break;
+        if (n == kMaxMat) {
+            over = true;
+            break;
+        }
+        if (threadIdx.x == 0) vals[(size_t)b * kMaxMat + n] = mn;
+        ++n;
+        last = mn;
+    }
+    if (threadIdx.x == 0) {
+        nmat[b] = n;
+        mat_ok[b] = over ? 0 : 1;
+    }
+}
+
+// each cell's index in its instance's value list; a cell whose value is not there (a NaN)
+// sends the instance to the per-cell kernel
+__global__ void mat_map_kernel(long long ncell, const double *sigma_t, const int *mask,
+                               const double *vals, const int *nmat, int *mat, int *mat_ok) {
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if ((mask && mask[b] == 0) || cell >= ncell) return;
+    const size_t t = (size_t)b * ncell + cell;
+    const double v = sigma_t[t];
+    const int n = nmat[b];
+    int m = -1;
+    for (int j = 0; j < n; ++j)
+        if (vals[(size_t)b * kMaxMat + j] == v) m = j;
+    if (m < 0) {
+        mat_ok[b] = 0;
+        m = 0;
+    }
+    mat[t] = m;
+}
+
+// The sigma_t-dependent coefficients of the Q1 cell solve (q1_solve's u, w, det M, det X and
+// the diagonal entries) for every (instance, sorted direction, material), in FP64 and stored in
+// T: x00, x11, (3u + w)/det M, s3 u/det M, (u + w)/det M, x11/det X, x00/det X, s3 a/det X.
+template <typename T>
+__global__ void mat_coef_kernel(int B, int n_sorted, const DirEntry *dirs, const int *mask,
+                                const double *vals, const int *nmat, T *coef) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)B * n_sorted * kMaxMat) return;
+    const int m = (int)(t % kMaxMat);
+    const long long bd = t / kMaxMat;
+    const int di = (int)(bd % n_sorted), b = (int)(bd / n_sorted);
+    if (mask && mask[b] == 0) return;
+    T *o = coef + (size_t)t * 8;
+    if (m >= nmat[b]) {
+        for (int k = 0; k < 8; ++k) o[k] = T(0);
+        return;
+    }
+    const double al = dirs[di].alpha, be = dirs[di].beta, sg = vals[(size_t)b * kMaxMat + m];
+    const double u = 2.0 * al * sg + 4.0 * al * (al + be);
+    const double w = sg * (sg + 4.0 * be) + 6.0 * (be * be - al * al);
+    const double tm = 2.0 * u + w;
+    const double detM = tm * tm + 2.0 * u * u;
+    const double tx = sg + be + 2.0 * al;
+    const double detX = tx * tx + 2.0 * al * al;
+    const double iM = 1.0 / detM, iX = 1.0 / detX;
+    const double x00 = sg + al + be, x11 = sg + 3.0 * al + be;
+    o[0] = (T)x00;
+    o[1] = (T)x11;
+    o[2] = (T)((3.0 * u + w) * iM);
+    o[3] = (T)(kS3 * u * iM);
+    o[4] = (T)((u + w) * iM);
+    o[5] = (T)(x11 * iX);
+    o[6] = (T)(x00 * iX);
+    o[7] = (T)(kS3 * al * iX);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -627,6 +771,9 @@ hipError_t sweep2d_launch_t(const SweepLaunch &L, hipStream_t s) {
     a.partial = L.partial;
     a.f_out = L.f_out;
     a.active = L.active;
+    a.mat_ok = L.mat_ok;
+    a.mcoef = L.mat_coef;
+    a.n_sorted = p->n_sorted;
     const unsigned grid = (unsigned)((long long)a.B * a.nparts);
     // bands in flight: the launch's choice, else the handle's, within what the mesh, the
     // workgroup size and the LDS budget allow
@@ -642,22 +789,53 @@ hipError_t sweep2d_launch_t(const SweepLaunch &L, hipStream_t s) {
     const size_t red = L.partial ? (size_t)NB * 2 * W * 64 * 4 * sizeof(double) : 0;
     const size_t lds = red + (size_t)NB * W * p->nx * DG * 2 * sizeof(T);
     a.ring_off = (int)(red / sizeof(double));
+    // the table kernel's rows of its W x DG directions follow the rings
+    a.mcoef_off = (int)(lds / sizeof(double));
+    const size_t lds_mat = lds + (size_t)W * DG * kMaxMat * 2 * sizeof(Vec4<T>);
     const dim3 blk(64 * W * NB);
-    switch (NB) {
-        case 1:
-            if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 1>), dim3(grid), blk, lds, s, a);
-            else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 1>), dim3(grid), blk, lds, s, a);
-            break;
-        case 2:
-            if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 2>), dim3(grid), blk, lds, s, a);
-            else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 2>), dim3(grid), blk, lds, s, a);
-            break;
-        default:
-            if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 4>), dim3(grid), blk, lds, s, a);
-            else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 4>), dim3(grid), blk, lds, s, a);
-            break;
-    }
+    auto go = [&](auto mat) {
+        constexpr bool M = decltype(mat)::value;
+        const size_t sh = M ? lds_mat : lds;
+        switch (NB) {
+            case 1:
+                if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 1, M>), dim3(grid), blk, sh, s, a);
+                else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 1, M>), dim3(grid), blk, sh, s, a);
+                break;
+            case 2:
+                if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 2, M>), dim3(grid), blk, sh, s, a);
+                else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 2, M>), dim3(grid), blk, sh, s, a);
+                break;
+            default:
+                if (L.f_out) hipLaunchKernelGGL((sweep2d_kernel<T, DG, true, 4, M>), dim3(grid), blk, sh, s, a);
+                else hipLaunchKernelGGL((sweep2d_kernel<T, DG, false, 4, M>), dim3(grid), blk, sh, s, a);
+                break;
+        }
+    };
+    // with tables: the table kernel for the instances that have one, then the per-cell kernel
+    // for the others (its workgroups of table instances leave at once)
+    if (L.mat_ok) go(std::true_type{});
+    go(std::false_type{});
     return hipGetLastError();
+}
+
+// the dynamic LDS limit of every 2D sweep kernel (the table kernels go past 64 KiB)
+template <typename T, int DG>
+void sweep_lds_limit_t(int bytes) {
+    auto set = [&](const void *f) {
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    };
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, false, 1, false>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, true, 1, false>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, false, 2, false>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, true, 2, false>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, false, 4, false>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, true, 4, false>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, false, 1, true>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, true, 1, true>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, false, 2, true>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, true, 2, true>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, false, 4, true>));
+    set(reinterpret_cast<const void *>(&sweep2d_kernel<T, DG, true, 4, true>));
 }
 
 template <typename T>
@@ -679,6 +857,46 @@ hipError_t launch_sweep2d(const SweepLaunch &a, hipStream_t s) {
     return a.fp32 ? sweep2d_dispatch<float>(a, s) : sweep2d_dispatch<double>(a, s);
 }
 
+void sweep_lds_limits(int bytes) {
+    sweep_lds_limit_t<float, 1>(bytes);
+    sweep_lds_limit_t<float, 2>(bytes);
+    sweep_lds_limit_t<float, 4>(bytes);
+    sweep_lds_limit_t<float, 8>(bytes);
+    sweep_lds_limit_t<double, 1>(bytes);
+    sweep_lds_limit_t<double, 2>(bytes);
+    sweep_lds_limit_t<double, 4>(bytes);
+    sweep_lds_limit_t<double, 8>(bytes);
+    (void)hipGetLastError();
+}
+
+size_t sweep_mat_lds_bytes(const rte_problem *p, size_t elem) {
+    return (size_t)sweep_waves(p) * p->tune.dg * kMaxMat * 2 * 4 * elem;
+}
+
+bool sweep_mat_fits(const rte_problem *p, size_t elem) {
+    // the largest workgroup of a table kernel: partial sums, rings at the most bands in flight
+    // the handle's schedule can run, and the table rows
+    const int NB = bands_in_flight(p, 4, true, elem);
+    return sweep_lds_bytes(p, NB, true, elem) + sweep_mat_lds_bytes(p, elem) <=
+           (size_t)p->lds_per_cu;
+}
+
+hipError_t launch_materials(const rte_problem *p, const int *mask, int *mat, int *mat_ok,
+                            int *nmat, double *vals, void *coef, int fp32, hipStream_t s) {
+    hipLaunchKernelGGL(mat_scan_kernel, dim3(p->B), dim3(256), 0, s, p->ncell, p->sigma_t, mask,
+                       vals, nmat, mat_ok);
+    hipLaunchKernelGGL(mat_map_kernel, dim3(blocks_for(p->ncell, 256), p->B), dim3(256), 0, s,
+                       p->ncell, p->sigma_t, mask, vals, nmat, mat, mat_ok);
+    const long long n = (long long)p->B * p->n_sorted * kMaxMat;
+    if (fp32)
+        hipLaunchKernelGGL(mat_coef_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->B,
+                           p->n_sorted, p->d_dirs, mask, vals, nmat, (float *)coef);
+    else
+        hipLaunchKernelGGL(mat_coef_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->B,
+                           p->n_sorted, p->d_dirs, mask, vals, nmat, (double *)coef);
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep1d(const rte_problem *p, const void *src, void *f_out, const int *active,
                           int zero_inflow, int fp32, hipStream_t s) {
     const long long n = (long long)p->B * p->n_dir;
@@ -694,7 +912,8 @@ hipError_t launch_sweep1d(const rte_problem *p, const void *src, void *f_out, co
 }
 
 hipError_t launch_source(const rte_problem *p, const double *rho, void *src, const int *active,
-                         int fp32, hipStream_t s, bool with_G) {
+                         int fp32, hipStream_t s, bool with_G, const int *mat,
+                         const int *mat_ok) {
     const long long n = (long long)p->B * p->ncell;
     const double ghost = sqrt(p->hx * p->hy);
     const double *cw = p->dim == 1 ? p->d_widths : nullptr;
@@ -702,11 +921,11 @@ hipError_t launch_source(const rte_problem *p, const double *rho, void *src, con
     if (fp32)
         hipLaunchKernelGGL(source_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->dim,
                            p->ncell, p->K, p->B, p->nx, p->ny, rho, p->sigma_t, p->sigma_s,
-                           G, cw, ghost, (float *)src, active);
+                           G, cw, ghost, (float *)src, active, mat, mat_ok);
     else
         hipLaunchKernelGGL(source_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            p->dim, p->ncell, p->K, p->B, p->nx, p->ny, rho, p->sigma_t,
-                           p->sigma_s, G, cw, ghost, (double *)src, active);
+                           p->sigma_s, G, cw, ghost, (double *)src, active, mat, mat_ok);
     return hipGetLastError();
 }
 

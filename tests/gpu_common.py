@@ -91,3 +91,20 @@ def f_library(f_nat, P):
     out = np.empty_like(f3)
     np.put_along_axis(out, pos[:, :, None], f3, axis=1)
     return out
+
+
+def first_divergence(res, b, ns, kinds):
+    """(l, kind) of the first iteration at which the GPU's trajectory of instance b leaves the
+    oracle's: 'stop' (one stops at sweep l, the other does not) or 'switch' (Alg. 2 chose
+    differently after sweep l); None if sweep counts and correction kinds are equal."""
+    ng = int(res.n_sweep[b])
+    gk = list(res.kind[b, :ng - 1])
+    for l in range(1, min(ng, ns) + 1):
+        g_stop, o_stop = l == ng, l == ns
+        if g_stop != o_stop:
+            return l, "stop"
+        if g_stop:
+            return None
+        if gk[l - 1] != kinds[l - 1]:
+            return l, "switch"
+    return None

@@ -18,7 +18,7 @@ import rte_workloads as W
 from oracle import rom as orom
 from oracle.problem import discretize
 from oracle import pool as oracle_pool
-from tests.gpu_common import host, rel_err, say
+from tests.gpu_common import first_divergence, host, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -64,23 +64,6 @@ def batch(R, oracle_rom):
     return plane, P, Rm, host(rho), res
 
 
-def _first_divergence(res, b, ns, kinds):
-    """(l, kind) of the first iteration at which the GPU's trajectory of instance b leaves the
-    oracle's: 'stop' (one stops at sweep l, the other does not) or 'switch' (Alg. 2 chose
-    differently after sweep l); None if sweep counts and correction kinds are equal."""
-    ng = int(res.n_sweep[b])
-    gk = list(res.kind[b, :ng - 1])
-    for l in range(1, min(ng, ns) + 1):
-        g_stop, o_stop = l == ng, l == ns
-        if g_stop != o_stop:
-            return l, "stop"
-        if g_stop:
-            return None
-        if gk[l - 1] != kinds[l - 1]:
-            return l, "switch"
-    return None
-
-
 @pytest.mark.timeout(1200)
 def test_c2_romsad_batch_every_instance_equals_the_oracle(batch, oracle_rom):
     """Equal sweep counts and correction kinds, densities within 1e-5.  A mixed-precision
@@ -100,7 +83,7 @@ def test_c2_romsad_batch_every_instance_equals_the_oracle(batch, oracle_rom):
     for b in range(B):
         ns, kinds, changes, rho_or, conv = ref[b]
         assert conv, b
-        div = _first_divergence(res, b, ns, kinds)
+        div = first_divergence(res, b, ns, kinds)
         if div is not None:
             l, what = div
             thr = EPS if what == "stop" else eps_romsad

@@ -11,7 +11,7 @@ from oracle import rom as orom
 from oracle.pgmres import pgmres
 from oracle.problem import discretize
 from oracle.sisa import sisa
-from tests.gpu_common import host, rel_err, say
+from tests.gpu_common import first_divergence, host, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -80,12 +80,33 @@ def test_family_romsad(R, fam, precision):
     res = rte.sisa_solve(P, rho, mode="romsad", rom=Rm, psi=problems.plane_psi(test), eps=eps,
                          theta=5, precision=precision, cg_rtol=1e-13, max_iter=500)
     rho = host(rho)
+    eps_romsad = 0.1 * max(rom.eps_train, rom.eps_pod)
     for b in range(test.B):
         d = discretize(test, b)
         ref = sisa(d, "romsad", eps=eps, rom=rom, theta=5)
-        assert res.n_sweep[b] == ref.n_sweep, (b, res.n_sweep[b], ref.n_sweep)
-        assert list(res.kind[b, :res.n_sweep[b] - 1]) == ref.kinds
-        assert rel_err(rho[b], ref.rho) < (1e-12 if precision == "fp64" else 1e-5)
+        if precision == "mixed":
+            # A mixed-precision trajectory may leave the FP64 oracle's only where a decision
+            # straddles its threshold within the precision to which the FP32 sweep measures the
+            # relative change e_l.  e_l ~ 1e-6 is the difference of two swept densities that each
+            # carry FP32 rounding of a few 1e-7 of themselves; between sweeps of nearly the same
+            # input those errors cancel (1e-3 of e_l in the full-size batch), but right after a
+            # ROMSA correction has changed the input they do not, and e_l is known to some tens
+            # of percent (measured: the pin cell's instance 1 after its correction, GPU e_2 15%
+            # below the oracle's).  Accepted: the oracle's e_l within 30% of the threshold; the
+            # density must still be within 1e-5.
+            assert rel_err(rho[b], ref.rho) < 1e-5
+            div = first_divergence(res, b, ref.n_sweep, ref.kinds)
+            if div is not None:
+                l, what = div
+                thr = eps if what == "stop" else eps_romsad
+                e_or, e_gpu = ref.changes[l - 1], float(res.change[b, l - 1])
+                say(f"  instance {b}: {what} decision after sweep {l} differs: oracle e_l "
+                    f"{e_or:.6e}, GPU e_l {e_gpu:.6e}, threshold {thr:.3e}")
+                assert abs(e_or - thr) <= 0.3 * thr, (b, l, what, e_or, e_gpu, thr)
+        else:
+            assert res.n_sweep[b] == ref.n_sweep, (b, res.n_sweep[b], ref.n_sweep)
+            assert list(res.kind[b, :res.n_sweep[b] - 1]) == ref.kinds
+            assert rel_err(rho[b], ref.rho) < 1e-12
 
 
 def test_family_romig_then_si_dsa(R, fam):

@@ -273,3 +273,51 @@ def test_cg_limit_reports_ecg(R):
     res = rte.sisa_solve(P, rho, mode="si_dsa", eps=1e-10, cg_rtol=1e-14, cg_maxit=1, max_iter=6,
                          raise_on_error=False)
     assert res.status == rte.RTE_ECG, res.status
+
+
+def _media_with_materials(plane, counts, seed):
+    """The plane with instance b's sigma_t made of counts[b] distinct values (None: one value per
+    cell), sigma_s kept at the same fraction of sigma_t."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    st, ss = plane.sigma_t.copy(), plane.sigma_s.copy()
+    for b, n in enumerate(counts):
+        frac = ss[b] / st[b]
+        if n is None:
+            st[b] = rng.uniform(0.5, 20.0, st[b].shape)
+        else:
+            levels = rng.uniform(0.5, 20.0, n)
+            ids = np.arange(st[b].size) % n
+            rng.shuffle(ids)
+            st[b] = levels[ids].reshape(st[b].shape)
+        ss[b] = frac * st[b]
+    return dataclasses.replace(plane, sigma_t=st, sigma_s=ss)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sweep2d_material_tables_beside_per_cell_instances(R, precision):
+    """An instance whose sigma_t takes at most 16 values is swept from its material table, one
+    with more (17, or a value per cell) by the per-cell kernel, in the same launch: every
+    instance against the oracle, element by element (eq. (transport_sweep))."""
+    import torch
+    rte, problems = R
+    counts = [1, 16, 17, None, 5]
+    base = W.random_plane(321, nx=37, ny=70, n_phi=16, B=len(counts), nbx=3, nby=2)
+    plane = _media_with_materials(base, counts, 5)
+    for b, n in enumerate(counts):
+        assert len(np.unique(plane.sigma_t[b])) == (n if n is not None else plane.sigma_t[b].size)
+    say(f"sweep2d material tables {counts} {precision}")
+    P = problems.plane_problem(plane)
+    discs = [discretize(plane, b) for b in range(P.B)]
+    rho_in = np.stack([_rand_rho(d, 11 + b) for b, d in enumerate(discs)])
+    f_dtype = torch.float64 if precision == "fp64" else torch.float32
+    fd = torch.zeros(rte.f_shape(P), dtype=f_dtype, device="cuda")
+    rs = torch.zeros((P.B, P.ndof), dtype=torch.float64, device="cuda")
+    rte.sweep(P, dev(rho_in), f_out=fd, rho_star_out=rs, precision=precision)
+    rs, f = host(rs), host(fd)
+    tol = TOL64 if precision == "fp64" else TOL32
+    tol_f = TOL64 if precision == "fp64" else TOL32_F
+    for b, d in enumerate(discs):
+        r_or, f_or = d.sweep(rho_in[b], want_f=True)
+        assert rel_err(rs[b], r_or) < tol, (b, counts[b], rel_err(rs[b], r_or))
+        assert rel_err(f_natural(f[b], P), f_or) < tol_f, (b, counts[b])
