@@ -219,7 +219,7 @@ int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *r
 
 /* rte_sweep without a workspace argument, for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The sweep's
- * input block and partial densities live in a library-owned device array of
+ * input block, partial densities and material tables live in a library-owned device array of
  * RTE_NOALLOC_SCRATCH_BYTES per GPU, held from the library's first use on that GPU until the
  * process ends; the call itself allocates and frees nothing.  Arguments, layouts and results are
  * those of rte_sweep (the same kernels run).

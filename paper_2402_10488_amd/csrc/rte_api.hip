@@ -1129,12 +1129,13 @@ int rte_sweep(const rte_problem *p, const double *rho_in, void *f_out, double *r
 
 namespace {
 
-// Device memory of rte_sweep_noalloc: the sweep's input block and partial densities live here
-// instead of in a caller workspace.  Each device that loads the library holds its own copy for
+// Device memory of rte_sweep_noalloc: the sweep's input block, partial densities and material
+// tables live here instead of in a caller workspace.  Each device that loads the library holds its own copy for
 // the life of the process; host code reaches it only through the address that
 // hipGetSymbolAddress returns on that device (the array's name on the host is a stand-in, not
-// a device address).  Nothing in it has to start at zero: the source kernel writes the whole
-// input block and every partial slot is written in full by the sweep before it is reduced.
+// a device address).  Nothing in it has to start at zero: the material kernels write every
+// table value they or the sweep read, the source kernel writes the whole input block, and every
+// partial slot is written in full by the sweep before it is reduced.
 static __device__ __align__(256) unsigned char scratch[RTE_NOALLOC_SCRATCH_BYTES];
 
 constexpr int kMaxScratchDevices = 64;
