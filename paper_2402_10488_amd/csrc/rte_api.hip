@@ -56,7 +56,7 @@ struct Layout {
     // 2D material tables of the sweep (launch_materials): cell indices [B][ncell], flags and
     // counts [B], values [B][kMaxMat], coefficients [B][n_sorted][kMaxMat][8] T
     int *mat, *mat_ok, *nmat;
-    double *mvals;
+    double *mvals, *mcvals;
     void *mcoef;
     bool use_mat;           // host: this call's sweeps use them (prepared in this workspace)
     // host-side: the CG iteration after which the previous diffusion solve of this call was
@@ -96,6 +96,7 @@ Layout carve(Carver &c, const rte_problem *p, rte_mode mode, const rte_rom *rom,
         L.mat_ok = c.take<int>(B);
         L.nmat = c.take<int>(B);
         L.mvals = c.take<double>(B * (size_t)kMaxMat);
+        L.mcvals = c.take<double>(B * (size_t)mat_chunks(p) * (kMaxMat + 1));
         L.mcoef = c.take<char>(B * (size_t)p->n_sorted * kMaxMat * 8 * ts);
     }
     if (mode != RTE_SI) {
@@ -712,7 +713,8 @@ bool mat_usable(const rte_problem *p, const Layout &L, int fp32) {
 int prepare_materials(const rte_problem *p, Layout &L, const int *mask, int fp32, hipStream_t s) {
     L.use_mat = false;
     if (!mat_usable(p, L, fp32)) return RTE_OK;
-    HIPCHK(launch_materials(p, mask, L.mat, L.mat_ok, L.nmat, L.mvals, L.mcoef, fp32, s));
+    HIPCHK(launch_materials(p, mask, L.mat, L.mat_ok, L.nmat, L.mvals, L.mcvals, L.mcoef, fp32,
+                            s));
     L.use_mat = true;
     return RTE_OK;
 }

@@ -245,9 +245,12 @@ hipError_t launch_sweep2d(const SweepLaunch &a, hipStream_t s);
 // Per instance (mask[b] != 0, all if null): the distinct sigma_t values (vals [B][kMaxMat]
 // ascending, nmat [B]), each cell's index among them (mat [B][ncell]), mat_ok [B] = 1 when there
 // are at most kMaxMat and every cell has one, and the cell-solve coefficients of every (sorted
-// direction, material) in T (coef [B][n_sorted][kMaxMat][8]).
+// direction, material) in T (coef [B][n_sorted][kMaxMat][8]); cvals [B][mat_chunks][kMaxMat + 1]
+// is scratch.
+int mat_chunks(const rte_problem *p);
 hipError_t launch_materials(const rte_problem *p, const int *mask, int *mat, int *mat_ok,
-                            int *nmat, double *vals, void *coef, int fp32, hipStream_t s);
+                            int *nmat, double *vals, double *cvals, void *coef, int fp32,
+                            hipStream_t s);
 // LDS bytes a table kernel adds to a sweep workgroup (elem: sizeof T), and whether the table
 // kernels fit the device's LDS for every launch of the handle's schedule
 size_t sweep_mat_lds_bytes(const rte_problem *p, size_t elem);

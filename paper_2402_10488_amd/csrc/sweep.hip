@@ -527,30 +527,67 @@ __global__ void source_kernel(int dim, long long ncell, int K, int B, int nx, in
 }
 
 // ------------------------------------------------------------------ materials
-// The distinct sigma_t values of each selected instance, ascending (at most kMaxMat): round r
-// finds the smallest value above the previous round's by a block-wide minimum.  nmat[b] is their
-// count (kMaxMat when there are more), mat_ok[b] = 0 when there are more.
+// The distinct sigma_t values of each selected instance, ascending (at most kMaxMat), in two
+// levels so that one large instance spreads over many workgroups.  Level one: every chunk of
+// kMatChunk cells lists its smallest kMaxMat + 1 distinct values (INFINITY past its last), round
+// r finding the smallest value above round r - 1's by a block-wide minimum.  Level two merges the
+// chunk lists the same way.  An instance with at most kMaxMat values has every chunk list
+// complete; one with more has more than kMaxMat in some chunk or in the union, and the merge
+// sees kMaxMat + 1.
+constexpr int kMatChunk = 4096;
+constexpr int kMatList = kMaxMat + 1;
+
+__device__ __forceinline__ double block_min256(double v, double *wmin) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = v;
+    __syncthreads();
+    v = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+    __syncthreads();
+    return v;
+}
+
+// grid (chunks, B), 256 threads: cvals [B][chunks][kMatList]
 __global__ void __launch_bounds__(256) mat_scan_kernel(long long ncell, const double *sigma_t,
-                                                       const int *mask, double *vals, int *nmat,
-                                                       int *mat_ok) {
+                                                       const int *mask, double *cvals) {
     __shared__ double wmin[4];
-    const int b = blockIdx.x;
+    const int b = blockIdx.y;
     if (mask && mask[b] == 0) return;
+    const long long c0 = (long long)blockIdx.x * kMatChunk;
+    const long long c1 = c0 + kMatChunk < ncell ? c0 + kMatChunk : ncell;
     const double *sb = sigma_t + (size_t)b * ncell;
+    double *out = cvals + ((size_t)b * gridDim.x + blockIdx.x) * kMatList;
     double last = -INFINITY;
-    int n = 0;
-    bool over = false;
-    for (int r = 0; r <= kMaxMat; ++r) {
+    for (int r = 0; r < kMatList; ++r) {
         double mn = INFINITY;
-        for (long long c = threadIdx.x; c < ncell; c += blockDim.x) {
+        for (long long c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
             const double v = sb[c];
             if (v > last && v < mn) mn = v;
         }
-        for (int off = 32; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, 64));
-        if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = mn;
-        __syncthreads();
-        mn = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
-        __syncthreads();
+        mn = block_min256(mn, wmin);
+        if (threadIdx.x == 0) out[r] = mn;
+        last = mn;
+    }
+}
+
+// grid B, 256 threads: vals [B][kMaxMat] ascending, nmat [B], mat_ok [B] (0: more than kMaxMat)
+__global__ void __launch_bounds__(256) mat_merge_kernel(int chunks, const double *cvals,
+                                                        const int *mask, double *vals, int *nmat,
+                                                        int *mat_ok) {
+    __shared__ double wmin[4];
+    const int b = blockIdx.x;
+    if (mask && mask[b] == 0) return;
+    const double *cb = cvals + (size_t)b * chunks * kMatList;
+    const int n_all = chunks * kMatList;
+    double last = -INFINITY;
+    int n = 0;
+    bool over = false;
+    for (int r = 0; r < kMatList; ++r) {
+        double mn = INFINITY;
+        for (int k = threadIdx.x; k < n_all; k += blockDim.x) {
+            const double v = cb[k];
+            if (v > last && v < mn) mn = v;
+        }
+        mn = block_min256(mn, wmin);
         if (!(mn < INFINITY)) break;
         if (n == kMaxMat) {
             over = true;
@@ -881,10 +918,16 @@ bool sweep_mat_fits(const rte_problem *p, size_t elem) {
            (size_t)p->lds_per_cu;
 }
 
+int mat_chunks(const rte_problem *p) { return (int)((p->ncell + kMatChunk - 1) / kMatChunk); }
+
 hipError_t launch_materials(const rte_problem *p, const int *mask, int *mat, int *mat_ok,
-                            int *nmat, double *vals, void *coef, int fp32, hipStream_t s) {
-    hipLaunchKernelGGL(mat_scan_kernel, dim3(p->B), dim3(256), 0, s, p->ncell, p->sigma_t, mask,
-                       vals, nmat, mat_ok);
+                            int *nmat, double *vals, double *cvals, void *coef, int fp32,
+                            hipStream_t s) {
+    const int chunks = mat_chunks(p);
+    hipLaunchKernelGGL(mat_scan_kernel, dim3(chunks, p->B), dim3(256), 0, s, p->ncell,
+                       p->sigma_t, mask, cvals);
+    hipLaunchKernelGGL(mat_merge_kernel, dim3(p->B), dim3(256), 0, s, chunks, cvals, mask, vals,
+                       nmat, mat_ok);
     hipLaunchKernelGGL(mat_map_kernel, dim3(blocks_for(p->ncell, 256), p->B), dim3(256), 0, s,
                        p->ncell, p->sigma_t, mask, vals, nmat, mat, mat_ok);
     const long long n = (long long)p->B * p->n_sorted * kMaxMat;
